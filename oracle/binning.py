@@ -1,0 +1,80 @@
+"""Cell and vertex binning to lattice tiles (integer work, oracle).
+
+TEST INFRASTRUCTURE ONLY; see the package docstring.
+
+The paper distributes lattice and cells over processors by domain
+decomposition and tracks which region owns which cell (Sec. 2.6).  On one
+device the same bookkeeping becomes binning to cubic lattice tiles of side
+8.  Reading of the rules (exact on the float32 positions the device holds):
+  * vertex owner: node p_d = origin_d + floor(offset_d), wrapped into
+    [0, N_d) on every axis (a walled axis clamps), tile coordinate
+    p_d >> 3, tile id (tz * Ty + ty) * Tx + tx with T_d = ceil(N_d / 8);
+  * cell coverage: per axis the node range
+    [origin + floor(min offset) - 1, origin + floor(max offset) + 2]
+    (the 4-point stencil reach), wrapped on periodic axes and clamped on
+    walled ones; the cell covers every tile the range meets;
+  * CSR lists sorted by (tile, cell) and (tile, cell, vertex).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+WALL = 1
+TILE = 8
+
+
+def tiles_per_axis(dims):
+    return tuple((n + TILE - 1) // TILE for n in dims)
+
+
+def _wrap(p, n, bc):
+    if bc == WALL:
+        return np.clip(p, 0, n - 1)
+    return np.mod(p, n)
+
+
+def vertex_owner(origin, offsets, dims, bc):
+    """Owner tile id of every vertex, int64 [C, V]."""
+    off = np.asarray(offsets, dtype=np.float32)
+    T = tiles_per_axis(dims)
+    t = []
+    for d in range(3):
+        p = origin[:, None, d].astype(np.int64) + np.floor(off[:, :, d]).astype(np.int64)
+        t.append(_wrap(p, dims[d], bc[d]) // TILE)
+    return (t[2] * T[1] + t[1]) * T[0] + t[0]
+
+
+def cell_tiles(origin, offsets, dims, bc, c):
+    """Sorted tile ids covered by cell c."""
+    off = np.asarray(offsets[c], dtype=np.float32)
+    T = tiles_per_axis(dims)
+    per_axis = []
+    for d in range(3):
+        lo = int(origin[c, d]) + int(np.floor(off[:, d].min())) - 1
+        hi = int(origin[c, d]) + int(np.floor(off[:, d].max())) + 2
+        nodes = _wrap(np.arange(lo, hi + 1), dims[d], bc[d])
+        per_axis.append(np.unique(nodes // TILE))
+    tz, ty, tx = np.meshgrid(per_axis[2], per_axis[1], per_axis[0], indexing="ij")
+    return np.unique(((tz * T[1] + ty) * T[0] + tx).ravel())
+
+
+def bins(origin, offsets, dims, bc):
+    """CSR binning: (owner [C*V], vert_ptr [NT+1], tile_vertices, cell_ptr [NT+1], tile_cells)."""
+    C, V = offsets.shape[0], offsets.shape[1]
+    T = tiles_per_axis(dims)
+    nt = T[0] * T[1] * T[2]
+    owner = vertex_owner(origin, offsets, dims, bc).ravel()
+    gidx = np.arange(C * V)
+    order = np.lexsort((gidx, owner))
+    vert_ptr = np.zeros(nt + 1, dtype=np.int64)
+    np.add.at(vert_ptr, owner + 1, 1)
+    vert_ptr = np.cumsum(vert_ptr)
+    pairs = []
+    for c in range(C):
+        for t in cell_tiles(origin, offsets, dims, bc, c):
+            pairs.append((int(t), c))
+    pairs = np.array(sorted(pairs), dtype=np.int64).reshape(-1, 2)
+    cell_ptr = np.zeros(nt + 1, dtype=np.int64)
+    np.add.at(cell_ptr, pairs[:, 0] + 1, 1)
+    cell_ptr = np.cumsum(cell_ptr)
+    return owner, vert_ptr, gidx[order], cell_ptr, pairs[:, 1]
