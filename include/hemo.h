@@ -1,0 +1,179 @@
+/*
+ * hemo.h -- C ABI of the MI355X coupled fluid-cell step library (libhemo.so).
+ *
+ * One coupled time step (HemoCell model, arXiv 2305.02752):
+ *   1. membrane forces on triangulated cells: F = F_link + F_bend + F_area
+ *      + F_volume (+ pole traction)                       -- Sec. 2.3, force sum
+ *   2. immersed-boundary spreading of vertex forces onto the lattice as an
+ *      external force density (Peskin kernel)              -- Sec. 2.3
+ *   3. D3Q19 BGK collide and stream with the force term     -- Sec. 2.2, LBGK update
+ *   4. interpolation of the lattice velocity to the vertices -- Sec. 2.3
+ *   5. explicit Euler advection of the vertices             -- Sec. 2.6
+ *
+ * Conventions
+ *  - Every call returns hc_status; hc_last_error() gives a message.  No C++
+ *    exception crosses this boundary.
+ *  - A context is single-stream and not thread-safe.  All device work is
+ *    enqueued on the stream given by hc_set_stream (default: the null
+ *    stream).  Device errors that happen asynchronously (including the
+ *    non-finite flag raised by the kernels) surface at hc_sync or at the next
+ *    read.
+ *  - Device memory is owned by the caller: hc_query_workspace reports the
+ *    bytes the context needs and hc_bind_workspace hands over one device
+ *    buffer of at least that size (256-byte aligned).  The library never
+ *    frees it and allocates no device memory of its own.
+ *  - Host read/write calls take caller-owned host arrays with an explicit
+ *    element count; a mismatch returns HC_ERR_ARG.  They synchronise the
+ *    stream before returning.
+ *  - Layouts: populations [19][nz][ny][nx] float32, x fastest, direction
+ *    order 0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
+ *    6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1)
+ *    12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1)
+ *    17:(0,1,-1) 18:(0,-1,1); populations are exchanged SHIFTED,
+ *    g_i = f_i - w_i (w: 1/3, 1/18 x6, 1/36 x12).  Vector fields [3][nz][ny][nx].
+ *    Cells: origin int32 [C][3], offsets float32 [C][V][3] (absolute
+ *    position = origin + offset), stiffness float32 [C][4] = link, bend,
+ *    area, volume, traction float32 [C][3].
+ */
+#ifndef HEMO_H
+#define HEMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HC_OK = 0,
+  HC_ERR_ARG = 1,          /* invalid argument or size mismatch               */
+  HC_ERR_STATE = 2,        /* call out of order (no workspace, no cells, ...)  */
+  HC_ERR_DEVICE = 3,       /* HIP runtime error                                */
+  HC_ERR_OOM = 4,          /* workspace too small                              */
+  HC_ERR_NONFINITE = 5,    /* a kernel saw a non-finite vertex position        */
+  HC_ERR_UNSUPPORTED = 6   /* configuration outside what the library handles   */
+} hc_status;
+
+enum { HC_PERIODIC = 0, HC_WALL = 1 };
+enum { HC_PHI2 = 2, HC_PHI4 = 4 };
+
+typedef struct hc_ctx hc_ctx;
+
+/* Lattice description (Sec. 2.2 and Sec. 2.5).
+ *  nx, ny, nz   lattice nodes per axis (node i sits at coordinate i), >= 4.
+ *  bc[3]        HC_PERIODIC or HC_WALL per axis (x, y, z); at most one wall
+ *               axis.  A wall lies half a spacing outside the first and last
+ *               node (half-way bounce-back); no-slip, Sec. 2.5.
+ *  tau          BGK relaxation time (> 0.5); nu = (tau - 1/2)/3 (Sec. 2.2).
+ *  body_force   uniform force density added to every node (lattice units).
+ *  wall_u_lo/hi velocity of the lower / upper wall of the wall axis
+ *               (moving walls impose shear, Sec. 2.5); must be tangential.
+ *  ibm_kernel   HC_PHI4 (Peskin 4-point, default) or HC_PHI2 (linear hat,
+ *               the "linear interpolation" of Sec. 2.3).                     */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t bc[3];
+  float tau;
+  float body_force[3];
+  float wall_u_lo[3];
+  float wall_u_hi[3];
+  int32_t ibm_kernel;
+} hc_lattice_desc;
+
+/* Cell surface mesh shared by all cells (Sec. 2.3: triangulated membrane).
+ *  tri       host int32 [n_tri][3], counter-clockwise seen from outside,
+ *            closed 2-manifold, vertex valence <= 8.
+ *  rest_pos  host float32 [n_vert][3]: the stress-free shape; rest edge
+ *            lengths, dihedral angles, area and volume are taken from it.
+ *            The 32 vertices with the largest / smallest rest x receive the
+ *            pole traction.  Copied at hc_create.                           */
+typedef struct {
+  int32_t n_vert, n_tri;
+  const int32_t* tri;
+  const float* rest_pos;
+} hc_mesh_desc;
+
+/* Create a context for one lattice with room for max_cells cells. */
+hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_t max_cells,
+                    hc_ctx** out);
+void hc_destroy(hc_ctx* ctx);
+const char* hc_last_error(const hc_ctx* ctx);
+
+/* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+hc_status hc_set_stream(hc_ctx* ctx, void* hip_stream);
+
+/* Device bytes the context needs (populations x2, fields, cells, bins). */
+hc_status hc_query_workspace(const hc_ctx* ctx, size_t* bytes);
+/* dev_ptr: device buffer of >= the queried bytes, 256-byte aligned, owned by
+ * the caller and kept alive until hc_destroy. */
+hc_status hc_bind_workspace(hc_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Upload n <= max_cells cells (host arrays; traction may be NULL = none). */
+hc_status hc_set_cells(hc_ctx* ctx, int32_t n, const int32_t* origin, const float* offsets,
+                       const float* k, const float* traction);
+
+/* Populations at equilibrium f_i = f_eq(rho0, u0) (Sec. 2.2 equilibrium). */
+hc_status hc_init_equilibrium(hc_ctx* ctx, float rho0, const float u0[3]);
+
+/* Enqueue n_steps coupled steps (steps 1-5 above). */
+hc_status hc_step(hc_ctx* ctx, int32_t n_steps);
+
+/* Wait for the stream; HC_ERR_NONFINITE if a kernel flagged a non-finite
+ * position since the last sync (the flag is then cleared). */
+hc_status hc_sync(hc_ctx* ctx);
+
+/* Shifted populations g = f - w, count = 19 * nx * ny * nz. */
+hc_status hc_read_populations(hc_ctx* ctx, float* host, int64_t count);
+hc_status hc_write_populations(hc_ctx* ctx, const float* host, int64_t count);
+
+/* Density [N] and velocity [3][N] of the last step's moments (velocity
+ * includes half the force density, Guo forcing); N = nx * ny * nz.
+ * Either pointer may be NULL. */
+hc_status hc_read_macro(hc_ctx* ctx, float* rho, float* u, int64_t n_sites);
+
+/* Force density [3][N] (body force + spread membrane forces) of the last step. */
+hc_status hc_read_force_field(hc_ctx* ctx, float* f, int64_t n_sites);
+
+/* Current cells; vertex_force = membrane forces of the last evaluation
+ * (may be NULL).  Counts: origin 3C, offsets and force 3CV. */
+hc_status hc_read_vertices(hc_ctx* ctx, int32_t* origin, float* offsets, float* vertex_force,
+                           int64_t n_cells);
+hc_status hc_write_vertices(hc_ctx* ctx, const int32_t* origin, const float* offsets,
+                            int64_t n_cells);
+/* Vertex velocity U_v interpolated in the last step (Sec. 2.3), float32
+ * [C][V][3]; the last step moved each vertex by U_v (Sec. 2.6, Euler). */
+hc_status hc_read_vertex_velocity(hc_ctx* ctx, float* vel, int64_t n_cells);
+
+/* Evaluate membrane forces of the current positions only (steps 1 of the
+ * step); area and volume per cell (float64, may be NULL) are returned. */
+hc_status hc_compute_forces(hc_ctx* ctx, double* area, double* volume, int64_t n_cells);
+
+/* Bin the current positions to 8^3 tiles (Tx = ceil(nx/8), ...; tile id
+ * (tz*Ty + ty)*Tx + tx) and read the lists back:
+ *  owner [C*V]        tile of node origin + floor(offset) per vertex
+ *  touch_ptr [NT+1], touch [touch_ptr[NT]]
+ *                     per tile, the vertices whose IBM stencil reaches it,
+ *                     sorted by vertex index
+ *  cell_ptr [NT+1], cells [cell_ptr[NT]]
+ *                     per tile, the cells whose stencil bounding box
+ *                     [floor(min)-1, floor(max)+2] meets it, sorted
+ * cap_touch / cap_cells give the capacities of touch / cells; if too small
+ * HC_ERR_ARG is returned and the needed sizes are in touch_ptr[NT] and
+ * cell_ptr[NT]. */
+hc_status hc_read_bins(hc_ctx* ctx, int32_t* owner, int32_t* touch_ptr, int32_t* touch,
+                       int64_t cap_touch, int32_t* cell_ptr, int32_t* cells, int64_t cap_cells);
+hc_status hc_num_tiles(const hc_ctx* ctx, int32_t* n_tiles);
+
+/* Checkpoint (Sec. 2.6: pause, save, continue): populations, cells, step. */
+hc_status hc_checkpoint_size(const hc_ctx* ctx, size_t* bytes);
+hc_status hc_checkpoint_save(hc_ctx* ctx, void* host, size_t bytes);
+hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
+
+/* Steps taken since hc_set_cells / restore. */
+hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEMO_H */

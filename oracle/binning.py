@@ -13,6 +13,9 @@ device the same bookkeeping becomes binning to cubic lattice tiles of side
     [origin + floor(min offset) - 1, origin + floor(max offset) + 2]
     (the 4-point stencil reach), wrapped on periodic axes and clamped on
     walled ones; the cell covers every tile the range meets;
+  * touch lists: per tile the vertices whose IBM stencil nodes
+    (floor(X)-1 .. floor(X)+2 for the 4-point kernel, floor(X) ..
+    floor(X)+1 for the 2-point one; walls drop outside nodes) lie in it;
   * CSR lists sorted by (tile, cell) and (tile, cell, vertex).
 """
 from __future__ import annotations
@@ -78,3 +81,33 @@ def bins(origin, offsets, dims, bc):
     np.add.at(cell_ptr, pairs[:, 0] + 1, 1)
     cell_ptr = np.cumsum(cell_ptr)
     return owner, vert_ptr, gidx[order], cell_ptr, pairs[:, 1]
+
+
+def touch_lists(origin, offsets, dims, bc, kernel=4):
+    """CSR (ptr [NT+1], vertex ids) of the tiles each vertex's stencil reaches."""
+    off = np.asarray(offsets, dtype=np.float32)
+    C, V = off.shape[:2]
+    T = tiles_per_axis(dims)
+    ks = (-1, 0, 1, 2) if kernel == 4 else (0, 1)
+    pairs = set()
+    for c in range(C):
+        for v in range(V):
+            axes = []
+            for d in range(3):
+                base = int(origin[c, d]) + int(np.floor(off[c, v, d]))
+                tiles = set()
+                for k in ks:
+                    p = base + k
+                    if bc[d] == WALL and not (0 <= p < dims[d]):
+                        continue
+                    tiles.add((p % dims[d]) // TILE)
+                axes.append(tiles)
+            for tz in axes[2]:
+                for ty in axes[1]:
+                    for tx in axes[0]:
+                        pairs.add(((tz * T[1] + ty) * T[0] + tx, c * V + v))
+    pairs = np.array(sorted(pairs), dtype=np.int64).reshape(-1, 2)
+    nt = T[0] * T[1] * T[2]
+    ptr = np.zeros(nt + 1, dtype=np.int64)
+    np.add.at(ptr, pairs[:, 0] + 1, 1)
+    return np.cumsum(ptr), pairs[:, 1]

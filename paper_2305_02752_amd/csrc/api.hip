@@ -1,0 +1,642 @@
+// C ABI of libhemo (declared in include/hemo.h): context set-up, workspace
+// carving, mesh-table construction and the per-step launch sequence.
+//
+// A coupled step enqueues, in order (Sec. 2.3 coupling, Sec. 2.6 Euler):
+//   membrane forces (one wave per cell) -> vertex binning to tiles ->
+//   LDS spread per tile -> collide + stream -> interpolation + advection.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hemo.h"
+#include "common.h"
+
+using namespace hc;
+
+namespace {
+
+constexpr int kNPole = 32;
+constexpr int kMaxCellTiles = 216;   // 6 tiles per axis per cell
+thread_local std::string g_create_error;
+
+struct HostMesh {
+  int nv = 0, nt = 0, nh = 0;
+  std::vector<int> tri, vlink_ptr, vlink_j, vtri_ptr, vtri, vhinge_ptr, vhinge, hinge_v, hinge_t;
+  std::vector<float> vlink_L0, theta0, pole;
+  double A0 = 0, V0 = 0;
+};
+
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    const size_t at = total;
+    total += (bytes + 255) & ~size_t(255);
+    return at;
+  }
+};
+
+}  // namespace
+
+struct hc_ctx {
+  Lattice L{};
+  HostMesh hm;
+  Mesh M{};
+  Cells C{};
+  Bins B{};
+  int max_cells = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  float* pops[2] = {nullptr, nullptr};
+  int cur = 0;
+  float *F = nullptr, *u = nullptr, *rho = nullptr;
+  int *cell_cnt = nullptr, *cell_ptr = nullptr, *cell_tiles = nullptr, *cell_rank = nullptr,
+      *cell_list = nullptr;
+  int64_t step = 0;
+  bool have_cells = false;
+  std::string err;
+  // workspace offsets
+  size_t o_pops[2], o_F, o_u, o_rho, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
+  size_t o_tri, o_vlp, o_vlj, o_vll, o_vtp, o_vt, o_vhp, o_vh, o_hv, o_ht, o_th0, o_pole;
+  size_t o_owner, o_ttile, o_trank, o_tcnt, o_tptr, o_touch, o_flags;
+  size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist;
+};
+
+namespace {
+
+hc_status fail(hc_ctx* c, hc_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+hc_status check(hc_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return HC_OK;
+  return fail(c, HC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HC_TRY(expr)                        \
+  do {                                      \
+    hc_status _s = (expr);                  \
+    if (_s != HC_OK) return _s;             \
+  } while (0)
+
+std::string build_mesh(const hc_mesh_desc* d, HostMesh& m) {
+  if (!d || !d->tri || !d->rest_pos) return "mesh: null pointer";
+  const int nv = d->n_vert, nt = d->n_tri;
+  if (nv < 2 * kNPole || nt < 4) return "mesh: need >= 64 vertices and >= 4 triangles";
+  m.nv = nv;
+  m.nt = nt;
+  m.tri.assign(d->tri, d->tri + 3 * nt);
+  std::vector<double> X(d->rest_pos, d->rest_pos + 3 * nv);
+  auto P = [&](int i, int k) { return X[3 * i + k]; };
+  // directed edge -> (triangle, wing vertex)
+  std::map<std::pair<int, int>, std::pair<int, int>> dir;
+  for (int t = 0; t < nt; ++t) {
+    for (int r = 0; r < 3; ++r) {
+      const int a = m.tri[3 * t + r], b = m.tri[3 * t + (r + 1) % 3], w = m.tri[3 * t + (r + 2) % 3];
+      if (a < 0 || a >= nv || b < 0 || b >= nv || w < 0 || w >= nv) return "mesh: index out of range";
+      if (!dir.emplace(std::make_pair(a, b), std::make_pair(t, w)).second)
+        return "mesh: repeated directed edge (inconsistent orientation)";
+    }
+  }
+  std::vector<std::vector<int>> vl(nv), vh(nv);
+  std::vector<std::vector<int>> vt(nv);
+  for (auto& kv : dir) {
+    const int p = kv.first.first, q = kv.first.second;
+    auto rev = dir.find(std::make_pair(q, p));
+    if (rev == dir.end()) return "mesh: open edge (surface not closed)";
+    vl[p].push_back(q);
+    if (p < q) {
+      const int h = m.nh++;
+      const int k = kv.second.second, l = rev->second.second;
+      m.hinge_v.insert(m.hinge_v.end(), {p, q, k, l});
+      m.hinge_t.insert(m.hinge_t.end(), {kv.second.first, rev->second.first});
+      // rest dihedral angle, float64
+      double e[3], u1[3], v1[3], u2[3], v2[3], n1[3], n2[3];
+      for (int a = 0; a < 3; ++a) {
+        e[a] = P(q, a) - P(p, a);
+        u1[a] = e[a];
+        v1[a] = P(k, a) - P(p, a);
+        u2[a] = P(p, a) - P(q, a);
+        v2[a] = P(l, a) - P(q, a);
+      }
+      auto cr = [](const double* a, const double* b, double* o) {
+        o[0] = a[1] * b[2] - a[2] * b[1];
+        o[1] = a[2] * b[0] - a[0] * b[2];
+        o[2] = a[0] * b[1] - a[1] * b[0];
+      };
+      cr(u1, v1, n1);
+      cr(u2, v2, n2);
+      auto nrm = [](double* a) {
+        const double s = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        a[0] /= s; a[1] /= s; a[2] /= s;
+      };
+      nrm(n1);
+      nrm(n2);
+      nrm(e);
+      double x[3];
+      cr(n1, n2, x);
+      const double sn = x[0] * e[0] + x[1] * e[1] + x[2] * e[2];
+      const double cs = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+      m.theta0.push_back((float)std::atan2(sn, cs));
+      const int roles[4] = {p, q, k, l};
+      for (int r = 0; r < 4; ++r) vh[roles[r]].push_back(h * 4 + r);
+    }
+  }
+  for (int t = 0; t < nt; ++t)
+    for (int r = 0; r < 3; ++r) {
+      const int v = m.tri[3 * t + r];
+      vt[v].insert(vt[v].end(), {t, m.tri[3 * t + (r + 1) % 3], m.tri[3 * t + (r + 2) % 3]});
+    }
+  m.vlink_ptr.push_back(0);
+  m.vtri_ptr.push_back(0);
+  m.vhinge_ptr.push_back(0);
+  for (int v = 0; v < nv; ++v) {
+    if (vl[v].empty()) return "mesh: isolated vertex";
+    std::sort(vl[v].begin(), vl[v].end());
+    for (int j : vl[v]) {
+      double s = 0;
+      for (int a = 0; a < 3; ++a) s += (P(j, a) - P(v, a)) * (P(j, a) - P(v, a));
+      m.vlink_j.push_back(j);
+      m.vlink_L0.push_back((float)std::sqrt(s));
+    }
+    m.vlink_ptr.push_back((int)m.vlink_j.size());
+    m.vtri.insert(m.vtri.end(), vt[v].begin(), vt[v].end());
+    m.vtri_ptr.push_back((int)(m.vtri.size() / 3));
+    m.vhinge.insert(m.vhinge.end(), vh[v].begin(), vh[v].end());
+    m.vhinge_ptr.push_back((int)m.vhinge.size());
+  }
+  // rest area and volume (float64, divergence theorem)
+  double A = 0, V = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int a = m.tri[3 * t], b = m.tri[3 * t + 1], c = m.tri[3 * t + 2];
+    double u[3], w[3], n[3];
+    for (int k = 0; k < 3; ++k) {
+      u[k] = P(b, k) - P(a, k);
+      w[k] = P(c, k) - P(a, k);
+    }
+    n[0] = u[1] * w[2] - u[2] * w[1];
+    n[1] = u[2] * w[0] - u[0] * w[2];
+    n[2] = u[0] * w[1] - u[1] * w[0];
+    A += 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    V += (P(a, 0) * (P(b, 1) * P(c, 2) - P(b, 2) * P(c, 1)) +
+          P(a, 1) * (P(b, 2) * P(c, 0) - P(b, 0) * P(c, 2)) +
+          P(a, 2) * (P(b, 0) * P(c, 1) - P(b, 1) * P(c, 0))) / 6.0;
+  }
+  if (!(V > 0)) return "mesh: non-positive volume (triangles must be counter-clockwise from outside)";
+  m.A0 = A;
+  m.V0 = V;
+  // traction poles: 32 largest / smallest rest x, ties to the lower index
+  std::vector<int> idx(nv);
+  for (int i = 0; i < nv; ++i) idx[i] = i;
+  m.pole.assign(nv, 0.f);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return P(a, 0) > P(b, 0); });
+  for (int i = 0; i < kNPole; ++i) m.pole[idx[i]] = 1.f;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return P(a, 0) < P(b, 0); });
+  for (int i = 0; i < kNPole; ++i) {
+    if (m.pole[idx[i]] != 0.f) return "mesh: pole sets overlap";
+    m.pole[idx[i]] = -1.f;
+  }
+  return "";
+}
+
+template <class T>
+T* at(hc_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+void plan(hc_ctx* c, Layout& lay) {
+  const int64_t N = c->L.n;
+  const int64_t C = c->max_cells, nv = c->hm.nv;
+  const int64_t NT = c->L.ntiles;
+  c->o_pops[0] = lay.add(19 * N * 4);
+  c->o_pops[1] = lay.add(19 * N * 4);
+  c->o_F = lay.add(3 * N * 4);
+  c->o_u = lay.add(3 * N * 4);
+  c->o_rho = lay.add(N * 4);
+  c->o_origin = lay.add(C * 3 * 4);
+  c->o_off = lay.add(C * nv * 3 * 4);
+  c->o_force = lay.add(C * nv * 3 * 4);
+  c->o_vel = lay.add(C * nv * 3 * 4);
+  c->o_k = lay.add(C * 4 * 4);
+  c->o_trac = lay.add(C * 3 * 4);
+  c->o_area = lay.add(C * 8);
+  c->o_vol = lay.add(C * 8);
+  const HostMesh& m = c->hm;
+  c->o_tri = lay.add(m.tri.size() * 4);
+  c->o_vlp = lay.add(m.vlink_ptr.size() * 4);
+  c->o_vlj = lay.add(m.vlink_j.size() * 4);
+  c->o_vll = lay.add(m.vlink_L0.size() * 4);
+  c->o_vtp = lay.add(m.vtri_ptr.size() * 4);
+  c->o_vt = lay.add(m.vtri.size() * 4);
+  c->o_vhp = lay.add(m.vhinge_ptr.size() * 4);
+  c->o_vh = lay.add(m.vhinge.size() * 4);
+  c->o_hv = lay.add(m.hinge_v.size() * 4);
+  c->o_ht = lay.add(m.hinge_t.size() * 4);
+  c->o_th0 = lay.add(m.theta0.size() * 4);
+  c->o_pole = lay.add(m.pole.size() * 4);
+  c->o_owner = lay.add(C * nv * 4);
+  c->o_ttile = lay.add(C * nv * kMaxTouch * 4);
+  c->o_trank = lay.add(C * nv * kMaxTouch * 4);
+  c->o_tcnt = lay.add((NT + 1) * 4);
+  c->o_tptr = lay.add((NT + 1) * 4);
+  c->o_touch = lay.add(std::max<int64_t>(1, C * nv * kMaxTouch) * 4);
+  c->o_flags = lay.add(16);
+  c->o_ccnt = lay.add((NT + 1) * 4);
+  c->o_cptr = lay.add((NT + 1) * 4);
+  c->o_ctiles = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
+  c->o_crank = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
+  c->o_clist = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
+}
+
+hc_status need_ws(hc_ctx* c) {
+  if (!c) return HC_ERR_ARG;
+  if (!c->ws) return fail(c, HC_ERR_STATE, "no workspace bound (hc_bind_workspace)");
+  return HC_OK;
+}
+
+hc_status sync(hc_ctx* c, const char* what) { return check(c, hipStreamSynchronize(c->stream), what); }
+
+hc_status copy_d2h(hc_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return HC_OK;
+  return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream), "d2h copy");
+}
+hc_status copy_h2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return HC_OK;
+  return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream), "h2d copy");
+}
+
+hc_status one_step(hc_ctx* c) {
+  Cells C = c->C;
+  C.n = c->have_cells ? c->C.n : 0;
+  HC_TRY(check(c, launch_membrane(C, c->M, c->stream), "membrane"));
+  HC_TRY(check(c, launch_bin_vertices(C, c->M, c->L, c->B, c->stream), "binning"));
+  HC_TRY(check(c, launch_spread(C, c->M, c->L, c->B, c->F, c->stream), "spread"));
+  HC_TRY(check(c, launch_collide_stream(c->pops[c->cur], c->pops[c->cur ^ 1], c->F, c->rho, c->u,
+                                        c->L, c->stream),
+               "collide_stream"));
+  HC_TRY(check(c, launch_interp_advect(C, c->M, c->L, c->u, c->B.flags, c->stream), "interp"));
+  c->cur ^= 1;
+  c->step += 1;
+  return HC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_t max_cells,
+                    hc_ctx** out) {
+  if (!out || !lat) return fail(nullptr, HC_ERR_ARG, "hc_create: null argument");
+  *out = nullptr;
+  if (lat->nx < 4 || lat->ny < 4 || lat->nz < 4)
+    return fail(nullptr, HC_ERR_ARG, "lattice sides must be >= 4");
+  if ((int64_t)lat->nx * lat->ny * lat->nz > (int64_t)1 << 31)
+    return fail(nullptr, HC_ERR_UNSUPPORTED, "lattice above 2^31 nodes");
+  if (!(lat->tau > 0.5f)) return fail(nullptr, HC_ERR_ARG, "tau must exceed 1/2");
+  if (lat->ibm_kernel != HC_PHI4 && lat->ibm_kernel != HC_PHI2)
+    return fail(nullptr, HC_ERR_ARG, "ibm_kernel must be HC_PHI4 or HC_PHI2");
+  if (max_cells < 0) return fail(nullptr, HC_ERR_ARG, "max_cells < 0");
+  int walls = 0, wall_axis = -1;
+  for (int d = 0; d < 3; ++d) {
+    if (lat->bc[d] != HC_PERIODIC && lat->bc[d] != HC_WALL)
+      return fail(nullptr, HC_ERR_ARG, "bc must be HC_PERIODIC or HC_WALL");
+    if (lat->bc[d] == HC_WALL) {
+      ++walls;
+      wall_axis = d;
+    }
+  }
+  if (walls > 1) return fail(nullptr, HC_ERR_UNSUPPORTED, "at most one wall axis");
+  if (wall_axis >= 0 && (lat->wall_u_lo[wall_axis] != 0.f || lat->wall_u_hi[wall_axis] != 0.f))
+    return fail(nullptr, HC_ERR_ARG, "wall velocities must be tangential");
+  hc_ctx* c = new hc_ctx();
+  std::string e = build_mesh(mesh, c->hm);
+  if (!e.empty()) {
+    delete c;
+    return fail(nullptr, HC_ERR_ARG, e);
+  }
+  Lattice& L = c->L;
+  L.nx = lat->nx;
+  L.ny = lat->ny;
+  L.nz = lat->nz;
+  for (int d = 0; d < 3; ++d) {
+    L.bc[d] = lat->bc[d];
+    L.g[d] = lat->body_force[d];
+    L.ulo[d] = lat->wall_u_lo[d];
+    L.uhi[d] = lat->wall_u_hi[d];
+  }
+  L.wall_axis = wall_axis;
+  L.tau = lat->tau;
+  L.omega = 1.0f / lat->tau;
+  L.kernel = lat->ibm_kernel;
+  L.n = (int64_t)L.nx * L.ny * L.nz;
+  L.tx = (L.nx + kTile - 1) / kTile;
+  L.ty = (L.ny + kTile - 1) / kTile;
+  L.tz = (L.nz + kTile - 1) / kTile;
+  L.ntiles = L.tx * L.ty * L.tz;
+  c->max_cells = max_cells;
+  *out = c;
+  return HC_OK;
+}
+
+void hc_destroy(hc_ctx* ctx) { delete ctx; }
+
+const char* hc_last_error(const hc_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+hc_status hc_set_stream(hc_ctx* c, void* s) {
+  if (!c) return HC_ERR_ARG;
+  c->stream = reinterpret_cast<hipStream_t>(s);
+  return HC_OK;
+}
+
+hc_status hc_query_workspace(const hc_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return HC_ERR_ARG;
+  Layout lay;
+  plan(const_cast<hc_ctx*>(c), lay);
+  *bytes = lay.total;
+  return HC_OK;
+}
+
+hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
+  if (!c || !dev) return fail(c, HC_ERR_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(c, HC_ERR_ARG, "workspace not 256-aligned");
+  Layout lay;
+  plan(c, lay);
+  if (bytes < lay.total) return fail(c, HC_ERR_OOM, "workspace smaller than hc_query_workspace");
+  c->ws = static_cast<char*>(dev);
+  c->ws_bytes = bytes;
+  c->pops[0] = at<float>(c, c->o_pops[0]);
+  c->pops[1] = at<float>(c, c->o_pops[1]);
+  c->cur = 0;
+  c->F = at<float>(c, c->o_F);
+  c->u = at<float>(c, c->o_u);
+  c->rho = at<float>(c, c->o_rho);
+  const HostMesh& m = c->hm;
+  Mesh& M = c->M;
+  M.nv = m.nv;
+  M.nt = m.nt;
+  M.nh = m.nh;
+  M.tri = at<int>(c, c->o_tri);
+  M.vlink_ptr = at<int>(c, c->o_vlp);
+  M.vlink_j = at<int>(c, c->o_vlj);
+  M.vlink_L0 = at<float>(c, c->o_vll);
+  M.vtri_ptr = at<int>(c, c->o_vtp);
+  M.vtri = at<int>(c, c->o_vt);
+  M.vhinge_ptr = at<int>(c, c->o_vhp);
+  M.vhinge = at<int>(c, c->o_vh);
+  M.hinge_v = at<int>(c, c->o_hv);
+  M.hinge_t = at<int>(c, c->o_ht);
+  M.theta0 = at<float>(c, c->o_th0);
+  M.pole = at<float>(c, c->o_pole);
+  M.inv_npole = 1.0f / kNPole;
+  M.A0 = m.A0;
+  M.V0 = m.V0;
+  Cells& C = c->C;
+  C.n = 0;
+  C.origin = at<int>(c, c->o_origin);
+  C.off = at<float>(c, c->o_off);
+  C.force = at<float>(c, c->o_force);
+  C.vel = at<float>(c, c->o_vel);
+  C.k = at<float>(c, c->o_k);
+  C.traction = nullptr;
+  C.area = at<double>(c, c->o_area);
+  C.volume = at<double>(c, c->o_vol);
+  Bins& B = c->B;
+  B.owner = at<int>(c, c->o_owner);
+  B.touch_tile = at<int>(c, c->o_ttile);
+  B.touch_rank = at<int>(c, c->o_trank);
+  B.touch_cnt = at<int>(c, c->o_tcnt);
+  B.touch_ptr = at<int>(c, c->o_tptr);
+  B.touch = at<int>(c, c->o_touch);
+  B.touch_cap = (int64_t)c->max_cells * m.nv * kMaxTouch;
+  B.flags = at<int>(c, c->o_flags);
+  c->cell_cnt = at<int>(c, c->o_ccnt);
+  c->cell_ptr = at<int>(c, c->o_cptr);
+  c->cell_tiles = at<int>(c, c->o_ctiles);
+  c->cell_rank = at<int>(c, c->o_crank);
+  c->cell_list = at<int>(c, c->o_clist);
+  HC_TRY(copy_h2d(c, (void*)M.tri, m.tri.data(), m.tri.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vlink_ptr, m.vlink_ptr.data(), m.vlink_ptr.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vlink_j, m.vlink_j.data(), m.vlink_j.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vlink_L0, m.vlink_L0.data(), m.vlink_L0.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vtri_ptr, m.vtri_ptr.data(), m.vtri_ptr.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vtri, m.vtri.data(), m.vtri.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vhinge_ptr, m.vhinge_ptr.data(), m.vhinge_ptr.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.vhinge, m.vhinge.data(), m.vhinge.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.hinge_v, m.hinge_v.data(), m.hinge_v.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.hinge_t, m.hinge_t.data(), m.hinge_t.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.theta0, m.theta0.data(), m.theta0.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
+  HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
+  HC_TRY(check(c, launch_init_equilibrium(c->pops[0], 1.f, 0.f, 0.f, 0.f, c->L, c->stream), "init"));
+  return sync(c, "bind");
+}
+
+hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float* offsets,
+                       const float* k, const float* traction) {
+  HC_TRY(need_ws(c));
+  if (n < 0 || n > c->max_cells) return fail(c, HC_ERR_ARG, "cell count outside [0, max_cells]");
+  if (n > 0 && (!origin || !offsets || !k)) return fail(c, HC_ERR_ARG, "null cell array");
+  const int64_t nv = c->hm.nv;
+  HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n * 3 * 4));
+  HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n * nv * 3 * 4));
+  HC_TRY(copy_h2d(c, (void*)c->C.k, k, (size_t)n * 4 * 4));
+  if (traction) {
+    HC_TRY(copy_h2d(c, at<float>(c, c->o_trac), traction, (size_t)n * 3 * 4));
+    c->C.traction = at<float>(c, c->o_trac);
+  } else {
+    c->C.traction = nullptr;
+  }
+  c->C.n = n;
+  c->have_cells = n > 0;
+  c->step = 0;
+  return sync(c, "set_cells");
+}
+
+hc_status hc_init_equilibrium(hc_ctx* c, float rho0, const float u0[3]) {
+  HC_TRY(need_ws(c));
+  const float z[3] = {0.f, 0.f, 0.f};
+  const float* u = u0 ? u0 : z;
+  HC_TRY(check(c, launch_init_equilibrium(c->pops[c->cur], rho0, u[0], u[1], u[2], c->L, c->stream),
+               "init"));
+  return HC_OK;
+}
+
+hc_status hc_step(hc_ctx* c, int32_t n) {
+  HC_TRY(need_ws(c));
+  if (n < 0) return fail(c, HC_ERR_ARG, "n_steps < 0");
+  for (int i = 0; i < n; ++i) HC_TRY(one_step(c));
+  return HC_OK;
+}
+
+hc_status hc_sync(hc_ctx* c) {
+  HC_TRY(need_ws(c));
+  HC_TRY(sync(c, "sync"));
+  int flags[4];
+  HC_TRY(copy_d2h(c, flags, c->B.flags, sizeof(flags)));
+  HC_TRY(sync(c, "sync flags"));
+  if (flags[0] || flags[1]) {
+    HC_TRY(check(c, launch_fill_i32(c->B.flags, 0, 4, c->stream), "clear flags"));
+    HC_TRY(sync(c, "sync"));
+    if (flags[0]) return fail(c, HC_ERR_NONFINITE, "non-finite vertex position");
+    return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
+  }
+  return HC_OK;
+}
+
+hc_status hc_read_populations(hc_ctx* c, float* host, int64_t count) {
+  HC_TRY(need_ws(c));
+  if (!host || count != 19 * c->L.n) return fail(c, HC_ERR_ARG, "population count mismatch");
+  HC_TRY(copy_d2h(c, host, c->pops[c->cur], (size_t)count * 4));
+  return sync(c, "read populations");
+}
+
+hc_status hc_write_populations(hc_ctx* c, const float* host, int64_t count) {
+  HC_TRY(need_ws(c));
+  if (!host || count != 19 * c->L.n) return fail(c, HC_ERR_ARG, "population count mismatch");
+  HC_TRY(copy_h2d(c, c->pops[c->cur], host, (size_t)count * 4));
+  return sync(c, "write populations");
+}
+
+hc_status hc_read_macro(hc_ctx* c, float* rho, float* u, int64_t n_sites) {
+  HC_TRY(need_ws(c));
+  if (n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
+  if (rho) HC_TRY(copy_d2h(c, rho, c->rho, (size_t)n_sites * 4));
+  if (u) HC_TRY(copy_d2h(c, u, c->u, (size_t)n_sites * 12));
+  return sync(c, "read macro");
+}
+
+hc_status hc_read_force_field(hc_ctx* c, float* f, int64_t n_sites) {
+  HC_TRY(need_ws(c));
+  if (!f || n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
+  HC_TRY(copy_d2h(c, f, c->F, (size_t)n_sites * 12));
+  return sync(c, "read force field");
+}
+
+hc_status hc_read_vertices(hc_ctx* c, int32_t* origin, float* offsets, float* force,
+                           int64_t n_cells) {
+  HC_TRY(need_ws(c));
+  if (n_cells != c->C.n) return fail(c, HC_ERR_ARG, "cell count mismatch");
+  const size_t nv = c->hm.nv;
+  if (origin) HC_TRY(copy_d2h(c, origin, c->C.origin, (size_t)n_cells * 12));
+  if (offsets) HC_TRY(copy_d2h(c, offsets, c->C.off, (size_t)n_cells * nv * 12));
+  if (force) HC_TRY(copy_d2h(c, force, c->C.force, (size_t)n_cells * nv * 12));
+  return sync(c, "read vertices");
+}
+
+hc_status hc_read_vertex_velocity(hc_ctx* c, float* vel, int64_t n_cells) {
+  HC_TRY(need_ws(c));
+  if (!vel || n_cells != c->C.n) return fail(c, HC_ERR_ARG, "cell count mismatch");
+  HC_TRY(copy_d2h(c, vel, c->C.vel, (size_t)n_cells * c->hm.nv * 12));
+  return sync(c, "read vertex velocity");
+}
+
+hc_status hc_write_vertices(hc_ctx* c, const int32_t* origin, const float* offsets,
+                            int64_t n_cells) {
+  HC_TRY(need_ws(c));
+  if (n_cells != c->C.n || !origin || !offsets) return fail(c, HC_ERR_ARG, "cell count mismatch");
+  HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n_cells * 12));
+  HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n_cells * c->hm.nv * 12));
+  return sync(c, "write vertices");
+}
+
+hc_status hc_compute_forces(hc_ctx* c, double* area, double* volume, int64_t n_cells) {
+  HC_TRY(need_ws(c));
+  if (n_cells != c->C.n) return fail(c, HC_ERR_ARG, "cell count mismatch");
+  HC_TRY(check(c, launch_membrane(c->C, c->M, c->stream), "membrane"));
+  if (area) HC_TRY(copy_d2h(c, area, c->C.area, (size_t)n_cells * 8));
+  if (volume) HC_TRY(copy_d2h(c, volume, c->C.volume, (size_t)n_cells * 8));
+  return sync(c, "compute forces");
+}
+
+hc_status hc_num_tiles(const hc_ctx* c, int32_t* n) {
+  if (!c || !n) return HC_ERR_ARG;
+  *n = c->L.ntiles;
+  return HC_OK;
+}
+
+hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* touch,
+                       int64_t cap_touch, int32_t* cell_ptr, int32_t* cells, int64_t cap_cells) {
+  HC_TRY(need_ws(c));
+  if (!touch_ptr || !cell_ptr) return fail(c, HC_ERR_ARG, "null pointer array");
+  const int NT = c->L.ntiles;
+  HC_TRY(check(c, launch_bin_vertices(c->C, c->M, c->L, c->B, c->stream), "binning"));
+  HC_TRY(check(c, launch_sort_segments(c->B.touch_ptr, c->B.touch, c->B.touch_rank, NT, c->stream),
+               "sort"));
+  HC_TRY(check(c, launch_bin_cells(c->C, c->M, c->L, c->cell_cnt, c->cell_ptr, c->cell_rank,
+                                   c->cell_tiles, c->cell_list,
+                                   (int64_t)c->max_cells * kMaxCellTiles, kMaxCellTiles,
+                                   c->B.flags, c->stream),
+               "cell binning"));
+  HC_TRY(check(c, launch_sort_segments(c->cell_ptr, c->cell_list, c->cell_rank, NT, c->stream),
+               "sort"));
+  HC_TRY(copy_d2h(c, touch_ptr, c->B.touch_ptr, (size_t)(NT + 1) * 4));
+  HC_TRY(copy_d2h(c, cell_ptr, c->cell_ptr, (size_t)(NT + 1) * 4));
+  HC_TRY(sync(c, "read bins"));
+  int flags[4];
+  HC_TRY(copy_d2h(c, flags, c->B.flags, sizeof(flags)));
+  HC_TRY(sync(c, "read bins"));
+  if (flags[1]) return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
+  if (touch_ptr[NT] > cap_touch || cell_ptr[NT] > cap_cells)
+    return fail(c, HC_ERR_ARG, "bin capacity too small");
+  if (owner) HC_TRY(copy_d2h(c, owner, c->B.owner, (size_t)c->C.n * c->hm.nv * 4));
+  if (touch) HC_TRY(copy_d2h(c, touch, c->B.touch, (size_t)touch_ptr[NT] * 4));
+  if (cells) HC_TRY(copy_d2h(c, cells, c->cell_list, (size_t)cell_ptr[NT] * 4));
+  return sync(c, "read bins");
+}
+
+hc_status hc_checkpoint_size(const hc_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return HC_ERR_ARG;
+  *bytes = 16 + (size_t)19 * c->L.n * 4 + (size_t)c->C.n * 12 + (size_t)c->C.n * c->hm.nv * 12;
+  return HC_OK;
+}
+
+hc_status hc_checkpoint_save(hc_ctx* c, void* host, size_t bytes) {
+  HC_TRY(need_ws(c));
+  size_t need;
+  hc_checkpoint_size(c, &need);
+  if (!host || bytes < need) return fail(c, HC_ERR_ARG, "checkpoint buffer too small");
+  char* p = static_cast<char*>(host);
+  int64_t hdr[2] = {c->step, c->C.n};
+  std::memcpy(p, hdr, 16);
+  p += 16;
+  HC_TRY(copy_d2h(c, p, c->pops[c->cur], (size_t)19 * c->L.n * 4));
+  p += (size_t)19 * c->L.n * 4;
+  HC_TRY(copy_d2h(c, p, c->C.origin, (size_t)c->C.n * 12));
+  p += (size_t)c->C.n * 12;
+  HC_TRY(copy_d2h(c, p, c->C.off, (size_t)c->C.n * c->hm.nv * 12));
+  return sync(c, "checkpoint save");
+}
+
+hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
+  HC_TRY(need_ws(c));
+  size_t need;
+  hc_checkpoint_size(c, &need);
+  if (!host || bytes < need) return fail(c, HC_ERR_ARG, "checkpoint buffer too small");
+  const char* p = static_cast<const char*>(host);
+  int64_t hdr[2];
+  std::memcpy(hdr, p, 16);
+  if (hdr[1] != c->C.n) return fail(c, HC_ERR_ARG, "checkpoint cell count differs");
+  p += 16;
+  HC_TRY(copy_h2d(c, c->pops[c->cur], p, (size_t)19 * c->L.n * 4));
+  p += (size_t)19 * c->L.n * 4;
+  HC_TRY(copy_h2d(c, c->C.origin, p, (size_t)c->C.n * 12));
+  p += (size_t)c->C.n * 12;
+  HC_TRY(copy_h2d(c, c->C.off, p, (size_t)c->C.n * c->hm.nv * 12));
+  c->step = hdr[0];
+  return sync(c, "checkpoint restore");
+}
+
+hc_status hc_get_step(const hc_ctx* c, int64_t* step) {
+  if (!c || !step) return HC_ERR_ARG;
+  *step = c->step;
+  return HC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+"""Thin Python binding of libhemo (C ABI in include/hemo.h).
+
+Argument marshalling only: every step of the coupled update runs in the HIP
+kernels of libhemo.so.  PyTorch supplies the device workspace and the
+stream.  There is no fallback path: a missing library is an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhemo.so")
+
+HC_PERIODIC, HC_WALL = 0, 1
+HC_PHI2, HC_PHI4 = 2, 4
+STATUS = {0: "HC_OK", 1: "HC_ERR_ARG", 2: "HC_ERR_STATE", 3: "HC_ERR_DEVICE", 4: "HC_ERR_OOM",
+          5: "HC_ERR_NONFINITE", 6: "HC_ERR_UNSUPPORTED"}
+
+
+class HemoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc", C.c_int32 * 3),
+                ("tau", C.c_float), ("body_force", C.c_float * 3), ("wall_u_lo", C.c_float * 3),
+                ("wall_u_hi", C.c_float * 3), ("ibm_kernel", C.c_int32)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_vert", C.c_int32), ("n_tri", C.c_int32), ("tri", C.POINTER(C.c_int32)),
+                ("rest_pos", C.POINTER(C.c_float))]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def _declare(lib):
+    i32, i64, sz = C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "hc_create": [_P, _P, i32, _P],
+        "hc_set_stream": [_P, _P],
+        "hc_query_workspace": [_P, _P],
+        "hc_bind_workspace": [_P, _P, sz],
+        "hc_set_cells": [_P, i32, _P, _P, _P, _P],
+        "hc_init_equilibrium": [_P, C.c_float, _P],
+        "hc_step": [_P, i32],
+        "hc_sync": [_P],
+        "hc_read_populations": [_P, _P, i64],
+        "hc_write_populations": [_P, _P, i64],
+        "hc_read_macro": [_P, _P, _P, i64],
+        "hc_read_force_field": [_P, _P, i64],
+        "hc_read_vertices": [_P, _P, _P, _P, i64],
+        "hc_write_vertices": [_P, _P, _P, i64],
+        "hc_read_vertex_velocity": [_P, _P, i64],
+        "hc_compute_forces": [_P, _P, _P, i64],
+        "hc_read_bins": [_P, _P, _P, _P, i64, _P, _P, i64],
+        "hc_num_tiles": [_P, _P],
+        "hc_checkpoint_size": [_P, _P],
+        "hc_checkpoint_save": [_P, _P, sz],
+        "hc_checkpoint_restore": [_P, _P, sz],
+        "hc_get_step": [_P, _P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.hc_last_error.argtypes = [_P]
+    lib.hc_last_error.restype = C.c_char_p
+    lib.hc_destroy.argtypes = [_P]
+    lib.hc_destroy.restype = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhemo.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} not found: build it with paper_2305_02752_amd/build.py "
+                              "(there is no CPU fallback)")
+        lib = C.CDLL(path)
+        _declare(lib)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def lattice_desc(lat) -> LatticeDesc:
+    d = LatticeDesc()
+    d.nx, d.ny, d.nz = int(lat.nx), int(lat.ny), int(lat.nz)
+    for i in range(3):
+        d.bc[i] = int(lat.bc[i])
+        d.body_force[i] = float(lat.body_force[i])
+        d.wall_u_lo[i] = float(lat.wall_u_lo[i])
+        d.wall_u_hi[i] = float(lat.wall_u_hi[i])
+    d.tau = float(lat.tau)
+    d.ibm_kernel = int(lat.ibm_kernel)
+    return d
+
+
+class Simulation:
+    """One lattice with up to `max_cells` cells, driven through libhemo.
+
+    lattice: object with nx, ny, nz, bc, tau, body_force, wall_u_lo,
+    wall_u_hi, ibm_kernel.  rest_pos float32 [V,3], tri int32 [T,3].
+    """
+
+    def __init__(self, lattice, rest_pos, tri, max_cells: int, device: str = "cuda:0"):
+        import torch
+
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nz = int(lattice.nx), int(lattice.ny), int(lattice.nz)
+        self.n_sites = self.nx * self.ny * self.nz
+        self._rest = np.ascontiguousarray(rest_pos, dtype=np.float32)
+        self._tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.nv = self._rest.shape[0]
+        self._desc = lattice_desc(lattice)
+        mesh = MeshDesc(self.nv, self._tri.shape[0], self._tri.ctypes.data_as(C.POINTER(C.c_int32)),
+                        self._rest.ctypes.data_as(C.POINTER(C.c_float)))
+        ctx = C.c_void_p()
+        rc = self.lib.hc_create(C.byref(self._desc), C.byref(mesh), int(max_cells), C.byref(ctx))
+        if rc:
+            raise HemoError(rc, self.lib.hc_last_error(None).decode())
+        self.ctx = ctx
+        self.n_cells = 0
+        nbytes = C.c_size_t()
+        self._check(self.lib.hc_query_workspace(self.ctx, C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) & ~255
+            self.stream = torch.cuda.current_stream(self.device)
+            self._check(self.lib.hc_set_stream(self.ctx, C.c_void_p(self.stream.cuda_stream)))
+            self._check(self.lib.hc_bind_workspace(self.ctx, C.c_void_p(aligned), nbytes.value))
+        n = C.c_int32()
+        self._check(self.lib.hc_num_tiles(self.ctx, C.byref(n)))
+        self.n_tiles = n.value
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc):
+        if rc:
+            raise HemoError(rc, self.lib.hc_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ state
+    def set_cells(self, origin, offsets, k, traction=None):
+        origin = np.ascontiguousarray(origin, dtype=np.int32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.float32)
+        k = np.ascontiguousarray(k, dtype=np.float32)
+        n = origin.shape[0]
+        if offsets.shape != (n, self.nv, 3) or k.shape != (n, 4):
+            raise ValueError("cell array shapes")
+        tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float32).reshape(n, 3)
+        self._check(self.lib.hc_set_cells(self.ctx, n, _ptr(origin), _ptr(offsets), _ptr(k),
+                                          None if tr is None else _ptr(tr)))
+        self.n_cells = n
+
+    def init_equilibrium(self, rho0=1.0, u0=(0.0, 0.0, 0.0)):
+        u = np.ascontiguousarray(u0, dtype=np.float32)
+        self._check(self.lib.hc_init_equilibrium(self.ctx, float(rho0), _ptr(u)))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.hc_step(self.ctx, int(n)))
+
+    def sync(self):
+        self._check(self.lib.hc_sync(self.ctx))
+
+    def steps_taken(self) -> int:
+        s = C.c_int64()
+        self._check(self.lib.hc_get_step(self.ctx, C.byref(s)))
+        return s.value
+
+    # ------------------------------------------------------------------ read-out
+    def read_populations(self) -> np.ndarray:
+        out = np.empty((19, self.nz, self.ny, self.nx), dtype=np.float32)
+        self._check(self.lib.hc_read_populations(self.ctx, _ptr(out), out.size))
+        return out
+
+    def write_populations(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float32)
+        self._check(self.lib.hc_write_populations(self.ctx, _ptr(g), g.size))
+
+    def read_macro(self):
+        rho = np.empty((self.nz, self.ny, self.nx), dtype=np.float32)
+        u = np.empty((3, self.nz, self.ny, self.nx), dtype=np.float32)
+        self._check(self.lib.hc_read_macro(self.ctx, _ptr(rho), _ptr(u), self.n_sites))
+        return rho, u
+
+    def read_force_field(self):
+        f = np.empty((3, self.nz, self.ny, self.nx), dtype=np.float32)
+        self._check(self.lib.hc_read_force_field(self.ctx, _ptr(f), self.n_sites))
+        return f
+
+    def read_vertices(self):
+        o = np.empty((self.n_cells, 3), dtype=np.int32)
+        off = np.empty((self.n_cells, self.nv, 3), dtype=np.float32)
+        fv = np.empty((self.n_cells, self.nv, 3), dtype=np.float32)
+        self._check(self.lib.hc_read_vertices(self.ctx, _ptr(o), _ptr(off), _ptr(fv), self.n_cells))
+        return o, off, fv
+
+    def read_vertex_velocity(self):
+        vel = np.empty((self.n_cells, self.nv, 3), dtype=np.float32)
+        self._check(self.lib.hc_read_vertex_velocity(self.ctx, _ptr(vel), self.n_cells))
+        return vel
+
+    def write_vertices(self, origin, offsets):
+        origin = np.ascontiguousarray(origin, dtype=np.int32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.float32)
+        self._check(self.lib.hc_write_vertices(self.ctx, _ptr(origin), _ptr(offsets), self.n_cells))
+
+    def compute_forces(self):
+        a = np.empty(self.n_cells, dtype=np.float64)
+        v = np.empty(self.n_cells, dtype=np.float64)
+        self._check(self.lib.hc_compute_forces(self.ctx, _ptr(a), _ptr(v), self.n_cells))
+        _, _, fv = self.read_vertices()
+        return fv, a, v
+
+    def read_bins(self):
+        nt = self.n_tiles
+        owner = np.empty(self.n_cells * self.nv, dtype=np.int32)
+        tptr = np.empty(nt + 1, dtype=np.int32)
+        cptr = np.empty(nt + 1, dtype=np.int32)
+        cap_t = self.n_cells * self.nv * 8
+        cap_c = self.n_cells * 216
+        touch = np.empty(max(cap_t, 1), dtype=np.int32)
+        cells = np.empty(max(cap_c, 1), dtype=np.int32)
+        self._check(self.lib.hc_read_bins(self.ctx, _ptr(owner), _ptr(tptr), _ptr(touch), touch.size,
+                                          _ptr(cptr), _ptr(cells), cells.size))
+        return owner, tptr, touch[:tptr[-1]].copy(), cptr, cells[:cptr[-1]].copy()
+
+    def checkpoint_save(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self.lib.hc_checkpoint_size(self.ctx, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.hc_checkpoint_save(self.ctx, _ptr(buf), buf.size))
+        return buf
+
+    def checkpoint_restore(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.hc_checkpoint_restore(self.ctx, _ptr(buf), buf.size))

@@ -1,0 +1,233 @@
+"""Device path (libhemo through the C ABI) against the FP64 oracle.
+
+Tolerances: one step <= 1e-5 max relative error per field (populations
+compared shifted, g = f - w; vertex displacement and forces relative to
+their field maxima); many steps <= 1e-3.  Integer binning bit-exact.
+"""
+import numpy as np
+import pytest
+
+from oracle import binning, lattice, membrane, step
+from workloads import jitter_cells, random_shifted_populations, single_rbc_shear, tiny_periodic
+from workloads.configs import Lattice, place_cells, K_REF
+
+from gpu_common import make_sim, oracle_model, oracle_state, relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5
+TOL_LONG = 1e-3
+
+CASES = {
+    # name: (workload kwargs, jitter)
+    "periodic_1cell": dict(seed=5, n=(24, 20, 16), n_cells=1),
+    "periodic_3cells_body": dict(seed=6, n=(32, 24, 20), n_cells=3, body=(2e-5, -1e-5, 5e-6)),
+    "wall_z_moving": dict(seed=7, n=(24, 20, 16), n_cells=1, walls=2),
+    "wall_y_moving": dict(seed=8, n=(28, 24, 20), n_cells=1, walls=1, body=(1e-5, 0, 0)),
+    "wall_x_tau07": dict(seed=9, n=(24, 26, 28), n_cells=1, walls=0, tau=0.7),
+    "phi2_kernel": dict(seed=10, n=(24, 20, 16), n_cells=2, ibm_kernel=2),
+}
+
+
+def _one_step(name):
+    w = tiny_periodic(**CASES[name])
+    rng = np.random.default_rng(100)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    g0 = random_shifted_populations(rng, w.lattice, 1e-3)
+    sim = make_sim(w, cells)
+    sim.write_populations(g0)
+    sim.step(1)
+    sim.sync()
+    g1 = sim.read_populations()
+    rho, u = sim.read_macro()
+    F = sim.read_force_field()
+    o1, off1, fv = sim.read_vertices()
+    U = sim.read_vertex_velocity()
+    m = oracle_model(w, cells)
+    f0, X0 = oracle_state(g0, cells)
+    f1r, X1r, info = step.step(m, f0, X0)
+    X1 = o1[:, None, :].astype(np.float64) + off1.astype(np.float64)
+    _check_positions(X1, X1r, off1, info["U"])
+    return dict(g=(g1, lattice.shifted(f1r)), rho=(rho, info["rho"]), u=(u, info["u"]),
+                F=(F, info["F"]), Fv=(fv, info["Fv"]), U=(U, info["U"]))
+
+
+def _check_positions(Xg, Xr, off, Ur):
+    """Positions are stored as float32 offsets, so X^{n+1} = X^n + U carries
+    the rounding of the offset (half an ulp, <= 6e-8 |offset|) on top of the
+    error of U itself."""
+    bound = 6e-8 * np.abs(off).max() + TOL_STEP * np.abs(Ur).max()
+    assert np.abs(Xg - Xr).max() <= bound, (np.abs(Xg - Xr).max(), bound)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_step_parity(name):
+    res = _one_step(name)
+    errs = {k: relerr(a, b) for k, (a, b) in res.items()}
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= TOL_STEP, (k, e)
+
+
+def test_zero_cells_fluid_only():
+    lat = Lattice(20, 12, 16, bc=(0, 1, 0), tau=0.8, body_force=(1e-5, 0, 0))
+    from workloads import rbc_mesh
+    rest, tri = rbc_mesh()
+    from paper_2305_02752_amd import Simulation
+    sim = Simulation(lat, rest.astype(np.float32), tri, max_cells=0)
+    rng = np.random.default_rng(3)
+    g0 = random_shifted_populations(rng, lat, 1e-3)
+    sim.write_populations(g0)
+    sim.step(3)
+    sim.sync()
+    f = lattice.unshift(g0)
+    F = np.zeros((3,) + lat.shape)
+    F[0] = 1e-5
+    for _ in range(3):
+        f, _, _ = lattice.lbm_step(f, F, 0.8, bc=(0, 1, 0))
+    assert relerr(sim.read_populations(), lattice.shifted(f)) <= TOL_STEP
+
+
+def test_cell_across_periodic_corner():
+    w = tiny_periodic(seed=12, n=(24, 20, 16), n_cells=1)
+    rest64 = w.rest_pos.astype(np.float64)
+    from workloads.configs import random_rotation
+    rng = np.random.default_rng(4)
+    cells = place_cells(rest64, np.array([[0.3, 19.6, 0.2]]), random_rotation(rng)[None],
+                        K_REF[None], traction=[[1e-3, 2e-3, -1e-3]])
+    cells = jitter_cells(rng, cells, 0.05)
+    g0 = random_shifted_populations(rng, w.lattice, 1e-3)
+    sim = make_sim(w, cells)
+    sim.write_populations(g0)
+    sim.step(1)
+    sim.sync()
+    m = oracle_model(w, cells)
+    f0, X0 = oracle_state(g0, cells)
+    f1, X1, info = step.step(m, f0, X0)
+    o, off, fv = sim.read_vertices()
+    assert relerr(sim.read_populations(), lattice.shifted(f1)) <= TOL_STEP
+    assert relerr(fv, info["Fv"]) <= TOL_STEP
+    assert relerr(sim.read_vertex_velocity(), info["U"]) <= TOL_STEP
+    _check_positions(o[:, None, :] + off.astype(np.float64), X1, off, info["U"])
+
+
+def test_membrane_area_volume_fp64():
+    w = tiny_periodic(seed=13, n=(40, 40, 40), n_cells=4)
+    rng = np.random.default_rng(5)
+    cells = jitter_cells(rng, w.cells, 0.1)
+    sim = make_sim(w, cells)
+    fv, A, V = sim.compute_forces()
+    m = oracle_model(w, cells)
+    X = cells.positions64()
+    Ar, Vr = membrane.area_volume(X, m.topo.tri)
+    assert np.abs(A - Ar).max() / Ar.max() < 1e-12
+    assert np.abs(V - Vr).max() / Vr.max() < 1e-12
+    Fr = membrane.forces(X, m.k, m.topo, m.rest, m.traction)
+    assert relerr(fv, Fr) <= TOL_STEP
+
+
+@pytest.mark.parametrize("kernel,walls", [(4, -1), (4, 1), (2, 2)])
+def test_binning_bit_exact(kernel, walls):
+    n = (40, 33, 24) if walls != 2 else (40, 33, 26)
+    w = tiny_periodic(seed=14, n=n, n_cells=4 if walls < 0 else 1, walls=walls, ibm_kernel=kernel)
+    rng = np.random.default_rng(6)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    sim = make_sim(w, cells)
+    sim.step(2)
+    sim.sync()
+    owner, tptr, touch, cptr, clist = sim.read_bins()
+    o, off, _ = sim.read_vertices()
+    dims, bc = (w.lattice.nx, w.lattice.ny, w.lattice.nz), w.lattice.bc
+    ow, _, _, cptr_r, clist_r = binning.bins(o, off, dims, bc)
+    tptr_r, touch_r = binning.touch_lists(o, off, dims, bc, kernel)
+    assert np.array_equal(owner, ow)
+    assert np.array_equal(cptr, cptr_r) and np.array_equal(clist, clist_r)
+    assert np.array_equal(tptr, tptr_r) and np.array_equal(touch, touch_r)
+
+
+def test_deterministic_bitwise():
+    w = tiny_periodic(seed=15, n=(32, 24, 24), n_cells=3, body=(1e-5, 0, 0))
+    rng = np.random.default_rng(7)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    g0 = random_shifted_populations(rng, w.lattice, 1e-3)
+    outs = []
+    for _ in range(2):
+        sim = make_sim(w, cells)
+        sim.write_populations(g0)
+        sim.step(20)
+        sim.sync()
+        outs.append((sim.read_populations(), sim.read_vertices()[1]))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_checkpoint_resume_bitwise():
+    w = tiny_periodic(seed=16, n=(24, 24, 24), n_cells=2)
+    rng = np.random.default_rng(8)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    sim = make_sim(w, cells)
+    sim.step(10)
+    ck = sim.checkpoint_save()
+    sim.step(15)
+    sim.sync()
+    ref = (sim.read_populations(), sim.read_vertices()[1])
+    sim2 = make_sim(w, cells)
+    sim2.checkpoint_restore(ck)
+    assert sim2.steps_taken() == 10
+    sim2.step(15)
+    sim2.sync()
+    assert np.array_equal(sim2.read_populations(), ref[0])
+    assert np.array_equal(sim2.read_vertices()[1], ref[1])
+
+
+def test_nonfinite_flag_surfaces():
+    from paper_2305_02752_amd import HemoError
+    w = tiny_periodic(seed=17, n=(24, 24, 24), n_cells=1)
+    sim = make_sim(w)
+    o, off, _ = sim.read_vertices()
+    off = off.copy()
+    off[0, 5, 1] = np.nan
+    sim.write_vertices(o, off)
+    sim.step(1)
+    with pytest.raises(HemoError) as e:
+        sim.sync()
+    assert e.value.code == 5
+    sim.sync()          # flag cleared
+
+
+def test_multistep_single_rbc_shear_500():
+    """Single RBC in shear (32^3, moving z walls), 500 steps <= 1e-3."""
+    w = single_rbc_shear()
+    sim = make_sim(w)
+    sim.init_equilibrium()
+    sim.step(w.steps)
+    sim.sync()
+    m = oracle_model(w, w.cells)
+    f = lattice.init_equilibrium(w.lattice.shape)
+    X0 = w.cells.positions64()
+    f, X = step.run(m, f, X0, w.steps)
+    o, off, _ = sim.read_vertices()
+    Xg = o[:, None, :] + off.astype(np.float64)
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    e_x = relerr(Xg - X0, X - X0)
+    print("500 steps: pops", e_g, "displacement", e_x, flush=True)
+    assert e_g <= TOL_LONG and e_x <= TOL_LONG
+
+
+def test_multistep_1000_tiny():
+    w = tiny_periodic(seed=18, n=(24, 20, 16), n_cells=1, walls=2)
+    rng = np.random.default_rng(9)
+    cells = jitter_cells(rng, w.cells, 0.02)
+    sim = make_sim(w, cells)
+    sim.init_equilibrium()
+    sim.step(1000)
+    sim.sync()
+    m = oracle_model(w, cells)
+    f = lattice.init_equilibrium(w.lattice.shape)
+    X0 = cells.positions64()
+    f, X = step.run(m, f, X0, 1000)
+    o, off, _ = sim.read_vertices()
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    e_x = relerr(o[:, None, :] + off.astype(np.float64) - X0, X - X0)
+    print("1000 steps: pops", e_g, "displacement", e_x, flush=True)
+    assert e_g <= TOL_LONG and e_x <= TOL_LONG
