@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled D3Q19 + IBM + membrane step on one MI355X.
+
+Workload (default): the large-suspension run -- 256 x 256 x 512 fully
+periodic lattice (33.5M sites), 18,600 biconcave RBCs of 642 vertices
+(11.9M vertices, haematocrit ~44%), body force along z, tau = 1, cells
+binned to 8^3 tiles each step.  Inputs are synthetic (seeded force-bias
+packing, uniform random orientations); populations start at rest.
+
+A step is one pass of the whole coupled update through libhemo: membrane
+forces, binning, IBM spread, collide + stream, interpolation + advection.
+The timed region runs exactly --steps steps with inputs resident in HBM,
+bracketed by device synchronisation; per-kernel device time inside the same
+region comes from events recorded on the library's stream.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_SITE = 152            # 19 float32 populations read + written
+BYTES_PER_VERTEX = 24           # float32 position read + written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_stream_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_2305_02752_amd", "csrc", "lbm.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(n_sites: int):
+    """HBM bytes per launch of collide_stream from committed rocprofv3 PMC
+    counters, valid only for the kernel source they were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("n_sites") != n_sites:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def cpu_baseline(w, steps: int = 3, side: int = 64):
+    """Time the FP64 oracle on a bounded sample of the same suspension: a
+    side^3 periodic sub-box holding the cells whose centres fall inside it."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lattice, step
+    from workloads.configs import Cells, Lattice
+
+    lat = w.lattice
+    cen = w.cells.positions64().mean(axis=1)
+    sel = np.all((cen >= 0) & (cen < side), axis=1)
+    cells = Cells(origin=w.cells.origin[sel], offsets=w.cells.offsets[sel], k=w.cells.k[sel])
+    sub = Lattice(side, side, side, tau=lat.tau, body_force=lat.body_force)
+    m = step.make_model(sub, w.rest_pos.astype(np.float64), w.tri, cells.k.astype(np.float64))
+    f = lattice.init_equilibrium(sub.shape)
+    X = cells.positions64()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f, X, _ = step.step(m, f, X)
+        dt = time.perf_counter() - t0
+    nv = X.shape[0] * X.shape[1]
+    return {
+        "value": sub.n_sites * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} steps of a {side}^3 periodic sub-box with the {int(sel.sum())} cells "
+                  f"({nv} vertices) centred in it, float64 NumPy, 1 thread",
+        "vertex_updates_per_s": nv * steps / dt,
+        "s_per_step": dt / steps,
+    }
+
+
+def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """GB/s of the library's streaming copy kernel (read + write bytes)."""
+    from paper_2305_02752_amd.hemo import device_copy
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    device_copy(b.data_ptr(), a.data_ptr(), nbytes, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        device_copy(b.data_ptr(), a.data_ptr(), nbytes, s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the coupled step has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2305_02752_amd import Simulation
+    from workloads import large_suspension
+
+    t = time.time()
+    w = large_suspension(seed=args.seed)
+    lat = w.lattice
+    n_sites = lat.n_sites
+    n_vert = w.cells.n * w.rest_pos.shape[0]
+    log(f"workload {w.name}: {n_sites} sites, {w.cells.n} cells, {n_vert} vertices, "
+        f"packing residual {w.extra['pack_residual']:.2f} lu, built in {time.time() - t:.1f}s")
+
+    copy_gbps = copy_bandwidth(torch)
+    log(f"library copy kernel: {copy_gbps:.0f} GB/s")
+
+    sim = Simulation(lat, w.rest_pos, w.tri, max_cells=w.cells.n)
+    sim.set_cells(w.cells.origin, w.cells.offsets, w.cells.k, None)
+    sim.init_equilibrium()
+    log(f"workspace {sim.workspace_bytes / 2**30:.2f} GiB")
+
+    sim.step(args.warmup)
+    sim.sync()
+    log(f"warmup {args.warmup} steps done")
+
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.sync()
+    dt = t1 - t0
+    log(f"timed {args.steps} steps in {dt:.3f}s")
+    for k, (ms, n) in prof.items():
+        log(f"  {k:15s} {ms / max(n, 1):8.3f} ms/launch  ({n} launches)")
+
+    ms_step = dt / args.steps * 1e3
+    mlups = n_sites * args.steps / dt / 1e6
+    vups = n_vert * args.steps / dt
+    b_step = BYTES_PER_SITE * n_sites + BYTES_PER_VERTEX * n_vert
+    step_frac = b_step * args.steps / dt / 1e9 / PEAK_HBM_GBPS
+
+    ms_cs, n_cs = prof["collide_stream"]
+    avg_s = ms_cs / n_cs * 1e-3
+    alg_bytes = BYTES_PER_SITE * n_sites
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = measured_traffic(n_sites)
+    roofline = {"bound": "hbm", "kernel": "collide_stream", "achieved": achieved,
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
+                "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": avg_s * 1e3}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        cpu = cpu_baseline(w, steps=args.cpu_steps)
+        log(f"oracle: {cpu['value']:.3f} MLUPS ({cpu['s_per_step']:.2f} s/step)")
+
+    out = {
+        "metric": "coupled-step MLUPS",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": [lat.nx, lat.ny, lat.nz], "cells": w.cells.n,
+                   "vertices": n_vert, "tau": lat.tau, "ibm_kernel": "phi4", "tile": 8},
+        "vertex_updates_per_s": vups,
+        "step_hbm_frac": step_frac,
+        "step_algorithmic_bytes": b_step,
+        "copy_kernel_GBps": copy_gbps,
+        "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

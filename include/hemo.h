@@ -170,6 +170,28 @@ hc_status hc_checkpoint_size(const hc_ctx* ctx, size_t* bytes);
 hc_status hc_checkpoint_save(hc_ctx* ctx, void* host, size_t bytes);
 hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
 
+/* Per-kernel timing.  hc_profile(ctx, 1) clears the record and brackets
+ * every subsequent launch of the step with events on the context stream;
+ * hc_profile_read waits for the stream and returns, per kernel family
+ * (index HC_K_*), the summed device time in milliseconds and the number of
+ * launches since the last hc_profile call.  Arrays hold HC_NUM_KERNELS. */
+enum {
+  HC_K_MEMBRANE = 0,
+  HC_K_BINNING = 1,
+  HC_K_SPREAD = 2,
+  HC_K_COLLIDE_STREAM = 3,
+  HC_K_INTERP_ADVECT = 4,
+  HC_NUM_KERNELS = 5
+};
+hc_status hc_profile(hc_ctx* ctx, int32_t enable);
+hc_status hc_profile_read(hc_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Device-to-device copy of `bytes` with the library's own streaming copy
+ * kernel (16-byte vector loads and stores), enqueued on hip_stream.  Used as
+ * the measured bandwidth reference beside the roofline.  dst and src must
+ * not overlap and must be 16-byte aligned. */
+hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
 /* Steps taken since hc_set_cells / restore. */
 hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
 

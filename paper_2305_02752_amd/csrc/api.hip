@@ -53,14 +53,21 @@ struct hc_ctx {
   size_t ws_bytes = 0;
   float* pops[2] = {nullptr, nullptr};
   int cur = 0;
-  float *F = nullptr, *u = nullptr, *rho = nullptr;
+  float* F = nullptr;
+  float4* macro = nullptr;     // (ux, uy, uz, rho) per site of the last step
+  float4* partial = nullptr;   // interpolation partial sums per (vertex, touch slot)
   int *cell_cnt = nullptr, *cell_ptr = nullptr, *cell_tiles = nullptr, *cell_rank = nullptr,
       *cell_list = nullptr;
   int64_t step = 0;
   bool have_cells = false;
+  // optional per-kernel timing with events on the context stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pairs[HC_NUM_KERNELS];
+  size_t ev_next = 0;
   std::string err;
   // workspace offsets
-  size_t o_pops[2], o_F, o_u, o_rho, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
+  size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_vlp, o_vlj, o_vll, o_vtp, o_vt, o_vhp, o_vh, o_hv, o_ht, o_th0, o_pole;
   size_t o_owner, o_ttile, o_trank, o_tcnt, o_tptr, o_touch, o_flags;
   size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist;
@@ -216,8 +223,7 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_pops[0] = lay.add(19 * N * 4);
   c->o_pops[1] = lay.add(19 * N * 4);
   c->o_F = lay.add(3 * N * 4);
-  c->o_u = lay.add(3 * N * 4);
-  c->o_rho = lay.add(N * 4);
+  c->o_macro = lay.add(N * 16);
   c->o_origin = lay.add(C * 3 * 4);
   c->o_off = lay.add(C * nv * 3 * 4);
   c->o_force = lay.add(C * nv * 3 * 4);
@@ -240,11 +246,12 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_th0 = lay.add(m.theta0.size() * 4);
   c->o_pole = lay.add(m.pole.size() * 4);
   c->o_owner = lay.add(C * nv * 4);
-  c->o_ttile = lay.add(C * nv * kMaxTouch * 4);
-  c->o_trank = lay.add(C * nv * kMaxTouch * 4);
+  c->o_ttile = lay.add(C * nv * c->L.max_touch * 4);
+  c->o_trank = lay.add(C * nv * c->L.max_touch * 4);
   c->o_tcnt = lay.add((NT + 1) * 4);
   c->o_tptr = lay.add((NT + 1) * 4);
-  c->o_touch = lay.add(std::max<int64_t>(1, C * nv * kMaxTouch) * 4);
+  c->o_touch = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 4);
+  c->o_partial = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 16);
   c->o_flags = lay.add(16);
   c->o_ccnt = lay.add((NT + 1) * 4);
   c->o_cptr = lay.add((NT + 1) * 4);
@@ -270,16 +277,45 @@ hc_status copy_h2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
   return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream), "h2d copy");
 }
 
+int ev_take(hc_ctx* c) {
+  if (c->ev_next == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->ev_pool.push_back(e);
+  }
+  return (int)c->ev_next++;
+}
+
+// Launch `fn` bracketed by timing events when profiling is on.
+template <class Fn>
+hc_status timed(hc_ctx* c, int kernel, const char* what, Fn fn) {
+  if (!c->prof) return check(c, fn(), what);
+  const int a = ev_take(c), b = ev_take(c);
+  if (a < 0 || b < 0) return fail(c, HC_ERR_DEVICE, "event creation failed");
+  HC_TRY(check(c, hipEventRecord(c->ev_pool[a], c->stream), "event record"));
+  HC_TRY(check(c, fn(), what));
+  HC_TRY(check(c, hipEventRecord(c->ev_pool[b], c->stream), "event record"));
+  c->ev_pairs[kernel].push_back({a, b});
+  return HC_OK;
+}
+
 hc_status one_step(hc_ctx* c) {
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
-  HC_TRY(check(c, launch_membrane(C, c->M, c->stream), "membrane"));
-  HC_TRY(check(c, launch_bin_vertices(C, c->M, c->L, c->B, c->stream), "binning"));
-  HC_TRY(check(c, launch_spread(C, c->M, c->L, c->B, c->F, c->stream), "spread"));
-  HC_TRY(check(c, launch_collide_stream(c->pops[c->cur], c->pops[c->cur ^ 1], c->F, c->rho, c->u,
-                                        c->L, c->stream),
-               "collide_stream"));
-  HC_TRY(check(c, launch_interp_advect(C, c->M, c->L, c->u, c->B.flags, c->stream), "interp"));
+  HC_TRY(timed(c, HC_K_MEMBRANE, "membrane", [&] { return launch_membrane(C, c->M, c->stream); }));
+  HC_TRY(timed(c, HC_K_BINNING, "binning",
+               [&] { return launch_bin_vertices(C, c->M, c->L, c->B, c->stream); }));
+  HC_TRY(timed(c, HC_K_SPREAD, "spread",
+               [&] { return launch_spread(C, c->M, c->L, c->B, c->F, c->stream); }));
+  HC_TRY(timed(c, HC_K_COLLIDE_STREAM, "collide_stream", [&] {
+    return launch_collide_stream(c->pops[c->cur], c->pops[c->cur ^ 1], c->F, c->macro, c->L,
+                                 c->stream);
+  }));
+  HC_TRY(timed(c, HC_K_INTERP_ADVECT, "interp",
+               [&] {
+                 return launch_interp_advect(C, c->M, c->L, c->B, c->macro, c->partial, c->B.flags,
+                                             c->stream);
+               }));
   c->cur ^= 1;
   c->step += 1;
   return HC_OK;
@@ -301,6 +337,8 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   if (lat->ibm_kernel != HC_PHI4 && lat->ibm_kernel != HC_PHI2)
     return fail(nullptr, HC_ERR_ARG, "ibm_kernel must be HC_PHI4 or HC_PHI2");
   if (max_cells < 0) return fail(nullptr, HC_ERR_ARG, "max_cells < 0");
+  if (mesh && (int64_t)max_cells * mesh->n_vert >= ((int64_t)1 << 26))
+    return fail(nullptr, HC_ERR_UNSUPPORTED, "more than 2^26 vertices");
   int walls = 0, wall_axis = -1;
   for (int d = 0; d < 3; ++d) {
     if (lat->bc[d] != HC_PERIODIC && lat->bc[d] != HC_WALL)
@@ -338,12 +376,52 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   L.ty = (L.ny + kTile - 1) / kTile;
   L.tz = (L.nz + kTile - 1) / kTile;
   L.ntiles = L.tx * L.ty * L.tz;
+  // a K-node stencil window meets 3 tiles along a periodic axis only when the
+  // last tile is at most K-2 nodes wide; otherwise 2 (1 for a 1-tile axis)
+  L.max_touch = 1;
+  const int sides[3] = {L.nx, L.ny, L.nz};
+  for (int d = 0; d < 3; ++d) {
+    const int last = sides[d] - (sides[d] - 1) / kTile * kTile;
+    int per_axis = sides[d] <= kTile ? 1 : 2;
+    if (L.bc[d] == HC_PERIODIC && sides[d] > kTile && last <= L.kernel - 2) per_axis = 3;
+    L.max_touch *= std::min(per_axis, (sides[d] + kTile - 1) / kTile);
+  }
   c->max_cells = max_cells;
   *out = c;
   return HC_OK;
 }
 
-void hc_destroy(hc_ctx* ctx) { delete ctx; }
+void hc_destroy(hc_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+hc_status hc_profile(hc_ctx* c, int32_t enable) {
+  if (!c) return HC_ERR_ARG;
+  HC_TRY(sync(c, "profile"));
+  c->prof = enable != 0;
+  c->ev_next = 0;
+  for (auto& v : c->ev_pairs) v.clear();
+  return HC_OK;
+}
+
+hc_status hc_profile_read(hc_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return HC_ERR_ARG;
+  HC_TRY(sync(c, "profile read"));
+  for (int k = 0; k < HC_NUM_KERNELS; ++k) {
+    double sum = 0.0;
+    for (auto& pr : c->ev_pairs[k]) {
+      float ms = 0.f;
+      HC_TRY(check(c, hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]),
+                   "event time"));
+      sum += ms;
+    }
+    total_ms[k] = sum;
+    launches[k] = (int64_t)c->ev_pairs[k].size();
+  }
+  return HC_OK;
+}
 
 const char* hc_last_error(const hc_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_error.c_str();
@@ -375,8 +453,8 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   c->pops[1] = at<float>(c, c->o_pops[1]);
   c->cur = 0;
   c->F = at<float>(c, c->o_F);
-  c->u = at<float>(c, c->o_u);
-  c->rho = at<float>(c, c->o_rho);
+  c->macro = at<float4>(c, c->o_macro);
+  c->partial = at<float4>(c, c->o_partial);
   const HostMesh& m = c->hm;
   Mesh& M = c->M;
   M.nv = m.nv;
@@ -414,7 +492,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   B.touch_cnt = at<int>(c, c->o_tcnt);
   B.touch_ptr = at<int>(c, c->o_tptr);
   B.touch = at<int>(c, c->o_touch);
-  B.touch_cap = (int64_t)c->max_cells * m.nv * kMaxTouch;
+  B.touch_cap = (int64_t)c->max_cells * m.nv * c->L.max_touch;
   B.flags = at<int>(c, c->o_flags);
   c->cell_cnt = at<int>(c, c->o_ccnt);
   c->cell_ptr = at<int>(c, c->o_cptr);
@@ -485,6 +563,7 @@ hc_status hc_sync(hc_ctx* c) {
     HC_TRY(check(c, launch_fill_i32(c->B.flags, 0, 4, c->stream), "clear flags"));
     HC_TRY(sync(c, "sync"));
     if (flags[0]) return fail(c, HC_ERR_NONFINITE, "non-finite vertex position");
+    if (flags[1] & 2) return fail(c, HC_ERR_DEVICE, "touch list overflow");
     return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
   }
   return HC_OK;
@@ -507,9 +586,18 @@ hc_status hc_write_populations(hc_ctx* c, const float* host, int64_t count) {
 hc_status hc_read_macro(hc_ctx* c, float* rho, float* u, int64_t n_sites) {
   HC_TRY(need_ws(c));
   if (n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
-  if (rho) HC_TRY(copy_d2h(c, rho, c->rho, (size_t)n_sites * 4));
-  if (u) HC_TRY(copy_d2h(c, u, c->u, (size_t)n_sites * 12));
-  return sync(c, "read macro");
+  std::vector<float> tmp((size_t)n_sites * 4);
+  HC_TRY(copy_d2h(c, tmp.data(), c->macro, (size_t)n_sites * 16));
+  HC_TRY(sync(c, "read macro"));
+  for (int64_t s = 0; s < n_sites; ++s) {
+    if (u) {
+      u[s] = tmp[4 * s];
+      u[n_sites + s] = tmp[4 * s + 1];
+      u[2 * n_sites + s] = tmp[4 * s + 2];
+    }
+    if (rho) rho[s] = tmp[4 * s + 3];
+  }
+  return HC_OK;
 }
 
 hc_status hc_read_force_field(hc_ctx* c, float* f, int64_t n_sites) {
@@ -588,7 +676,10 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
   if (owner) HC_TRY(copy_d2h(c, owner, c->B.owner, (size_t)c->C.n * c->hm.nv * 4));
   if (touch) HC_TRY(copy_d2h(c, touch, c->B.touch, (size_t)touch_ptr[NT] * 4));
   if (cells) HC_TRY(copy_d2h(c, cells, c->cell_list, (size_t)cell_ptr[NT] * 4));
-  return sync(c, "read bins");
+  HC_TRY(sync(c, "read bins"));
+  if (touch)
+    for (int64_t i = 0; i < touch_ptr[NT]; ++i) touch[i] >>= 5;  // drop the slot index
+  return HC_OK;
 }
 
 hc_status hc_checkpoint_size(const hc_ctx* c, size_t* bytes) {
@@ -631,6 +722,15 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   HC_TRY(copy_h2d(c, c->C.off, p, (size_t)c->C.n * c->hm.nv * 12));
   c->step = hdr[0];
   return sync(c, "checkpoint restore");
+}
+
+hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) ||
+      (bytes & 15))
+    return fail(nullptr, HC_ERR_ARG, "copy: null or misaligned pointer / size");
+  hipError_t e = launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, HC_ERR_DEVICE, hipGetErrorString(e));
+  return HC_OK;
 }
 
 hc_status hc_get_step(const hc_ctx* c, int64_t* step) {

@@ -20,7 +20,7 @@ __device__ inline int wrap(int p, int n) {
   return p < 0 ? p + n : p;
 }
 
-// Distinct tiles (<= 2) reached along one axis by K stencil nodes starting at p0.
+// Distinct tiles (<= 3) reached along one axis by K stencil nodes starting at p0.
 __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
   int cnt = 0;
   for (int k = 0; k < K; ++k) {
@@ -33,21 +33,41 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
     const int t = p / kTile;
     bool seen = false;
     for (int q = 0; q < cnt; ++q) seen = seen || out[q] == t;
-    if (!seen && cnt < 2) out[cnt++] = t;
+    if (!seen && cnt < 3) out[cnt++] = t;
   }
   return cnt;
 }
 
+// Rank of this lane's element in the per-tile counter, with one atomic per
+// distinct tile in the wave (lanes of one cell mostly share tiles).
+__device__ inline int wave_counted_rank(int* cnt, int tile, bool active) {
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long pending = __ballot(active);
+  int rank = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int t = __shfl(tile, leader);
+    const unsigned long long mask = pending & __ballot(active && tile == t);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[t], __popcll(mask));
+    base = __shfl(base, leader);
+    if ((mask >> lane) & 1ull) rank = base + __popcll(mask & ((1ull << lane) - 1ull));
+    pending &= ~mask;
+  }
+  return rank;
+}
+
 __global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= (int64_t)C.n * M.nv) return;
+  const int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = v0 < (int64_t)C.n * M.nv;
+  const int64_t v = live ? v0 : 0;
   const int c = (int)(v / M.nv);
   const float* o = C.off + v * 3;
   const int K = L.kernel;
   const int b = K == 4 ? -1 : 0;
   int p[3];
   int n[3] = {L.nx, L.ny, L.nz};
-  int T[3][2], nT[3];
+  int T[3][3], nT[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     p[d] = C.origin[3 * c + d] + (int)floorf(o[d]);
@@ -55,27 +75,32 @@ __global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L
     int q = L.bc[d] == 1 ? min(max(p[d], 0), n[d] - 1) : wrap(p[d], n[d]);
     p[d] = q / kTile;
   }
-  B.owner[v] = (p[2] * L.ty + p[1]) * L.tx + p[0];
-  int j = 0;
-  for (int a = 0; a < nT[2]; ++a)
-    for (int bb = 0; bb < nT[1]; ++bb)
-      for (int cc = 0; cc < nT[0]; ++cc) {
-        const int tile = (T[2][a] * L.ty + T[1][bb]) * L.tx + T[0][cc];
-        B.touch_tile[v * kMaxTouch + j] = tile;
-        B.touch_rank[v * kMaxTouch + j] = atomicAdd(&B.touch_cnt[tile], 1);
-        ++j;
-      }
-  for (; j < kMaxTouch; ++j) B.touch_tile[v * kMaxTouch + j] = -1;
+  if (live) B.owner[v] = (p[2] * L.ty + p[1]) * L.tx + p[0];
+  const int ntouch = live ? nT[0] * nT[1] * nT[2] : 0;
+  if (live && ntouch > L.max_touch) atomicOr(&B.flags[1], 2);  // excluded by the bound set at create
+  // all lanes walk the same slot sequence so the wave can aggregate atomics
+  for (int j = 0; j < L.max_touch; ++j) {
+    const bool act = j < ntouch;
+    int tile = 0;
+    if (act) {
+      const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
+      tile = (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
+    }
+    const int rank = wave_counted_rank(B.touch_cnt, tile, act);
+    if (live) {
+      B.touch_tile[v * L.max_touch + j] = act ? tile : -1;
+      if (act) B.touch_rank[v * L.max_touch + j] = rank;
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_fill_touch(int64_t nvtot, Bins B) {
+__global__ __launch_bounds__(256) void k_fill_touch(int64_t nvtot, int max_touch, Bins B) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvtot) return;
-#pragma unroll
-  for (int j = 0; j < kMaxTouch; ++j) {
-    const int t = B.touch_tile[v * kMaxTouch + j];
+  for (int j = 0; j < max_touch; ++j) {
+    const int t = B.touch_tile[v * max_touch + j];
     if (t < 0) break;
-    B.touch[B.touch_ptr[t] + B.touch_rank[v * kMaxTouch + j]] = (int)v;
+    B.touch[B.touch_ptr[t] + B.touch_rank[v * max_touch + j]] = (int)(v * 32 + j);
   }
 }
 
@@ -217,7 +242,8 @@ hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, 
   }
   if ((e = launch_scan(b.touch_cnt, b.touch_ptr, L.ntiles, s)) != hipSuccess) return e;
   if (n > 0) {
-    hipLaunchKernelGGL(k_fill_touch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, b);
+    hipLaunchKernelGGL(k_fill_touch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       L.max_touch, b);
     e = hipGetLastError();
   }
   return e;

@@ -11,7 +11,8 @@ namespace hc {
 
 constexpr int kQ = 19;          // D3Q19
 constexpr int kTile = 8;        // binning tile side (lattice nodes)
-constexpr int kMaxTouch = 8;    // tiles reached by one 4-point stencil (2 per axis)
+constexpr int kMaxTouch = 27;   // tiles reached by one stencil: <= 3 per axis (a periodic
+                                // axis whose last tile is 1-2 nodes wide), else 2
 constexpr int kWave = 64;       // gfx950 wavefront width
 // Fixed-point scale of the deterministic force accumulation: 2^48 units per
 // lattice force unit (resolution 3.6e-15, range +-32768).
@@ -28,6 +29,7 @@ struct Lattice {
   int kernel;               // 4 or 2
   int64_t n;                // nx * ny * nz
   int tx, ty, tz, ntiles;   // tile grid
+  int max_touch;            // touch-list slots per vertex (product over axes)
 };
 
 // Mesh tables shared by every cell (built on the host from the rest shape).
@@ -67,7 +69,7 @@ struct Bins {
   int* touch_rank;          // [n*nv][8] slot within the tile list
   int* touch_cnt;           // [ntiles+1]
   int* touch_ptr;           // [ntiles+1]
-  int* touch;               // [capacity] vertex ids
+  int* touch;               // [capacity] vertex * 32 + slot (slot j of touch_tile)
   int64_t touch_cap;
   int* flags;               // [4]: 0 non-finite, 1 list overflow
 };
@@ -84,10 +86,11 @@ hipError_t launch_scan(const int* cnt, int* ptr, int n, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                          float* F, hipStream_t s);
-hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float* rho,
-                                 float* u, const Lattice& L, hipStream_t s);
-hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const float* u,
-                                int* flags, hipStream_t s);
+hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float4* macro,
+                                 const Lattice& L, hipStream_t s);
+hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                                const float4* macro, float4* partial, int* flags, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_init_equilibrium(float* g, float rho0, float ux, float uy, float uz,
                                    const Lattice& L, hipStream_t s);
 

@@ -7,9 +7,11 @@
 // is the product of the per-axis weights.  Periodic axes wrap; nodes past a
 // wall receive no force and read the wall velocity.
 //
-// Spreading is gather-by-tile: one work-group per 8^3 tile walks the list of
-// vertices whose stencil reaches the tile (built by the binning kernels) and
-// accumulates their contributions in LDS as 2^-48 fixed-point int64 values.
+// Spreading and interpolation are organised by tile: one work-group per 8^3
+// tile walks the list of vertices whose stencil reaches the tile (built by
+// the binning kernels).  Spreading accumulates in LDS as 2^-48 fixed-point
+// int64 values; interpolation writes one partial sum per (vertex, tile) that
+// a per-vertex pass adds up in a fixed order.
 // Integer addition is associative, so the result is bitwise independent of
 // the order in which waves and lanes arrive -- no global atomics, no
 // run-to-run drift.
@@ -36,6 +38,27 @@ __device__ inline int wrap(int p, int n) {
   return p < 0 ? p + n : p;
 }
 
+// Per-axis stencil of one vertex relative to a tile starting at t0: local
+// node index inside the tile (-1 outside the tile or beyond a wall) and weight.
+__device__ inline void axis_stencil(int base, float frac, int K, int n, int wall, int t0, int* l,
+                                    float* w) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    l[k] = -1;
+    w[k] = 0.f;
+    if (k < K) {
+      int p = base + k;
+      bool in = true;
+      if (wall) in = p >= 0 && p < n; else p = wrap(p, n);
+      l[k] = (in && p >= t0 && p < t0 + kTile) ? p - t0 : -1;
+      w[k] = stencil_w(K, frac, k);
+    }
+  }
+}
+
+// One work-group per tile; one thread per (vertex, tile) entry of the touch
+// list: the thread evaluates its 3 x K axis weights once and adds the
+// contributions of the stencil nodes inside the tile to the LDS accumulator.
 __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
                                                 float* __restrict__ F) {
   __shared__ long long acc[3][kTile * kTile * kTile];
@@ -50,42 +73,39 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
   __syncthreads();
 
   const int K = L.kernel;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int nwaves = blockDim.x / kWave;
-  const int kx = K == 4 ? (lane & 3) : (lane & 1);
-  const int ky = K == 4 ? ((lane >> 2) & 3) : ((lane >> 1) & 1);
-  const int kz = K == 4 ? (lane >> 4) : (lane >> 2);
-  const bool active = lane < K * K * K;
   const int b = K == 4 ? -1 : 0;
   const int e0 = B.touch_ptr[t], e1 = B.touch_ptr[t + 1];
-
-  for (int e = e0 + wave; e < e1; e += nwaves) {
-    const int v = __builtin_amdgcn_readfirstlane(B.touch[e]);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int v = B.touch[e] >> 5;
     const int c = v / M.nv;
     const float* o = C.off + (int64_t)v * 3;
     const float* fv = C.force + (int64_t)v * 3;
     const float ox = o[0], oy = o[1], oz = o[2];
+    const float fx = fv[0], fy = fv[1], fz = fv[2];
     const float flx = floorf(ox), fly = floorf(oy), flz = floorf(oz);
-    int px = C.origin[3 * c + 0] + (int)flx + b + kx;
-    int py = C.origin[3 * c + 1] + (int)fly + b + ky;
-    int pz = C.origin[3 * c + 2] + (int)flz + b + kz;
-    bool ok = active;
-    if (L.bc[0] == 1) ok = ok && px >= 0 && px < L.nx; else px = wrap(px, L.nx);
-    if (L.bc[1] == 1) ok = ok && py >= 0 && py < L.ny; else py = wrap(py, L.ny);
-    if (L.bc[2] == 1) ok = ok && pz >= 0 && pz < L.nz; else pz = wrap(pz, L.nz);
-    ok = ok && px >= x0 && px < x0 + kTile && py >= y0 && py < y0 + kTile && pz >= z0 &&
-         pz < z0 + kTile;
-    if (ok) {
-      const float w = stencil_w(K, ox - flx, kx) * stencil_w(K, oy - fly, ky) *
-                      stencil_w(K, oz - flz, kz);
-      const int li = ((pz - z0) * kTile + (py - y0)) * kTile + (px - x0);
-      atomicAdd((unsigned long long*)&acc[0][li],
-                (unsigned long long)__double2ll_rn((double)(w * fv[0]) * kFixScale));
-      atomicAdd((unsigned long long*)&acc[1][li],
-                (unsigned long long)__double2ll_rn((double)(w * fv[1]) * kFixScale));
-      atomicAdd((unsigned long long*)&acc[2][li],
-                (unsigned long long)__double2ll_rn((double)(w * fv[2]) * kFixScale));
+    int lx[4], ly[4], lz[4];
+    float wx[4], wy[4], wz[4];
+    axis_stencil(C.origin[3 * c + 0] + (int)flx + b, ox - flx, K, L.nx, L.bc[0] == 1, x0, lx, wx);
+    axis_stencil(C.origin[3 * c + 1] + (int)fly + b, oy - fly, K, L.ny, L.bc[1] == 1, y0, ly, wy);
+    axis_stencil(C.origin[3 * c + 2] + (int)flz + b, oz - flz, K, L.nz, L.bc[2] == 1, z0, lz, wz);
+    for (int kz = 0; kz < K; ++kz) {
+      if (lz[kz] < 0) continue;
+      for (int ky = 0; ky < K; ++ky) {
+        if (ly[ky] < 0) continue;
+        const float wzy = wz[kz] * wy[ky];
+        const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+        for (int kx = 0; kx < K; ++kx) {
+          if (lx[kx] < 0) continue;
+          const float w = wzy * wx[kx];
+          const int li = row + lx[kx];
+          atomicAdd((unsigned long long*)&acc[0][li],
+                    (unsigned long long)__float2ll_rn(w * fx * (float)kFixScale));
+          atomicAdd((unsigned long long*)&acc[1][li],
+                    (unsigned long long)__float2ll_rn(w * fy * (float)kFixScale));
+          atomicAdd((unsigned long long*)&acc[2][li],
+                    (unsigned long long)__float2ll_rn(w * fz * (float)kFixScale));
+        }
+      }
     }
   }
   __syncthreads();
@@ -102,58 +122,97 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
   }
 }
 
-__global__ __launch_bounds__(256) void k_interp_advect(Cells C, Mesh M, Lattice L,
-                                                       const float* __restrict__ u,
-                                                       int* __restrict__ flags) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= (int64_t)C.n * M.nv) return;
-  const int c = (int)(v / M.nv);
+// Interpolation, first half: one work-group per tile stages the tile's
+// velocities in LDS; each (vertex, tile) entry sums w * u over its stencil
+// nodes inside the tile and stores the partial sum in the vertex's slot.
+__global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattice L, Bins B,
+                                                         const float4* __restrict__ macro,
+                                                         float4* __restrict__ partial) {
+  __shared__ float4 su[kTile * kTile * kTile];
+  const int t = blockIdx.x;
+  const int tx = t % L.tx, ty = (t / L.tx) % L.ty, tz = t / (L.tx * L.ty);
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  const int e0 = B.touch_ptr[t], e1 = B.touch_ptr[t + 1];
+  if (e0 == e1) return;
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
+    const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
+    su[i] = (x < L.nx && y < L.ny && z < L.nz) ? macro[((int64_t)z * L.ny + y) * L.nx + x]
+                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
   const int K = L.kernel;
   const int b = K == 4 ? -1 : 0;
-  float* o = C.off + v * 3;
-  const float ox = o[0], oy = o[1], oz = o[2];
-  const float flx = floorf(ox), fly = floorf(oy), flz = floorf(oz);
-  const float fx = ox - flx, fy = oy - fly, fz = oz - flz;
-  const int bx = C.origin[3 * c + 0] + (int)flx + b;
-  const int by = C.origin[3 * c + 1] + (int)fly + b;
-  const int bz = C.origin[3 * c + 2] + (int)flz + b;
-  float wx[4], wy[4], wz[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    wx[k] = k < K ? stencil_w(K, fx, k) : 0.f;
-    wy[k] = k < K ? stencil_w(K, fy, k) : 0.f;
-    wz[k] = k < K ? stencil_w(K, fz, k) : 0.f;
-  }
-  const int64_t N = L.n;
-  float Ux = 0.f, Uy = 0.f, Uz = 0.f;
-  for (int kz = 0; kz < K; ++kz) {
-    int pz = bz + kz;
-    int side_z = 0;
-    if (L.bc[2] == 1) side_z = pz < 0 ? 1 : (pz >= L.nz ? 2 : 0); else pz = wrap(pz, L.nz);
-    for (int ky = 0; ky < K; ++ky) {
-      int py = by + ky;
-      int side_y = 0;
-      if (L.bc[1] == 1) side_y = py < 0 ? 1 : (py >= L.ny ? 2 : 0); else py = wrap(py, L.ny);
-      for (int kx = 0; kx < K; ++kx) {
-        int px = bx + kx;
-        int side_x = 0;
-        if (L.bc[0] == 1) side_x = px < 0 ? 1 : (px >= L.nx ? 2 : 0); else px = wrap(px, L.nx);
-        const float w = wx[kx] * wy[ky] * wz[kz];
-        const int side = side_x | side_y | side_z;
-        float vx, vy, vz;
-        if (side == 1) {
-          vx = L.ulo[0]; vy = L.ulo[1]; vz = L.ulo[2];
-        } else if (side == 2) {
-          vx = L.uhi[0]; vy = L.uhi[1]; vz = L.uhi[2];
-        } else {
-          const int64_t s = ((int64_t)pz * L.ny + py) * L.nx + px;
-          vx = u[s]; vy = u[N + s]; vz = u[2 * N + s];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int code = B.touch[e];
+    const int v = code >> 5, j = code & 31;
+    const int c = v / M.nv;
+    const float* o = C.off + (int64_t)v * 3;
+    const float ox = o[0], oy = o[1], oz = o[2];
+    const float flx = floorf(ox), fly = floorf(oy), flz = floorf(oz);
+    int lx[4], ly[4], lz[4];
+    float wx[4], wy[4], wz[4];
+    axis_stencil(C.origin[3 * c + 0] + (int)flx + b, ox - flx, K, L.nx, L.bc[0] == 1, x0, lx, wx);
+    axis_stencil(C.origin[3 * c + 1] + (int)fly + b, oy - fly, K, L.ny, L.bc[1] == 1, y0, ly, wy);
+    axis_stencil(C.origin[3 * c + 2] + (int)flz + b, oz - flz, K, L.nz, L.bc[2] == 1, z0, lz, wz);
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    for (int kz = 0; kz < K; ++kz) {
+      if (lz[kz] < 0) continue;
+      for (int ky = 0; ky < K; ++ky) {
+        if (ly[ky] < 0) continue;
+        const float wzy = wz[kz] * wy[ky];
+        const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+        for (int kx = 0; kx < K; ++kx) {
+          if (lx[kx] < 0) continue;
+          const float w = wzy * wx[kx];
+          const float4 q = su[row + lx[kx]];
+          ux += w * q.x;
+          uy += w * q.y;
+          uz += w * q.z;
         }
-        Ux += w * vx;
-        Uy += w * vy;
-        Uz += w * vz;
       }
     }
+    partial[(int64_t)v * L.max_touch + j] = make_float4(ux, uy, uz, 0.f);
+  }
+}
+
+// Interpolation, second half, and explicit Euler advection: one thread per
+// vertex sums its tile partials in slot order (fixed, so the result is
+// reproducible), adds stencil nodes beyond a wall at the wall velocity, and
+// moves the vertex.
+__global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins B,
+                                                const float4* __restrict__ partial,
+                                                int* __restrict__ flags) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (int64_t)C.n * M.nv) return;
+  float Ux = 0.f, Uy = 0.f, Uz = 0.f;
+  for (int j = 0; j < L.max_touch; ++j) {
+    if (B.touch_tile[v * L.max_touch + j] < 0) break;
+    const float4 q = partial[v * L.max_touch + j];
+    Ux += q.x;
+    Uy += q.y;
+    Uz += q.z;
+  }
+  float* o = C.off + v * 3;
+  const float ox = o[0], oy = o[1], oz = o[2];
+  if (L.wall_axis >= 0) {
+    // the other two axes' weights sum to one, so a node layer beyond the
+    // wall contributes its axis weight times the wall velocity
+    const int d = L.wall_axis;
+    const int c = (int)(v / M.nv);
+    const int K = L.kernel;
+    const float od = d == 0 ? ox : (d == 1 ? oy : oz);
+    const float fl = floorf(od);
+    const int n = d == 0 ? L.nx : (d == 1 ? L.ny : L.nz);
+    const int base = C.origin[3 * c + d] + (int)fl + (K == 4 ? -1 : 0);
+    float wlo = 0.f, whi = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const int p = base + k;
+      if (p < 0) wlo += stencil_w(K, od - fl, k);
+      if (p >= n) whi += stencil_w(K, od - fl, k);
+    }
+    Ux += wlo * L.ulo[0] + whi * L.uhi[0];
+    Uy += wlo * L.ulo[1] + whi * L.uhi[1];
+    Uz += wlo * L.ulo[2] + whi * L.uhi[2];
   }
   const float nx = ox + Ux, ny = oy + Uy, nz = oz + Uz;
   if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
@@ -174,12 +233,16 @@ hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const 
   return hipGetLastError();
 }
 
-hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const float* u,
-                                int* flags, hipStream_t s) {
+hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                                const float4* macro, float4* partial, int* flags, hipStream_t s) {
   const int64_t n = (int64_t)c.n * m.nv;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_advect, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, m, L,
-                     u, flags);
+  hipLaunchKernelGGL(k_interp_partials, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_advect, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, m, L, b,
+                     partial, flags);
   return hipGetLastError();
 }
 

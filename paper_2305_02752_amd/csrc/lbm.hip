@@ -26,8 +26,8 @@ __device__ constexpr int opp[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14
 __global__ __launch_bounds__(256) void k_collide_stream(const float* __restrict__ gin,
                                                         float* __restrict__ gout,
                                                         const float* __restrict__ F,
-                                                        float* __restrict__ rho_out,
-                                                        float* __restrict__ u_out, Lattice L) {
+                                                        float4* __restrict__ macro,
+                                                        Lattice L) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = L.n;
   if (s >= N) return;
@@ -59,12 +59,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(const float* __restrict_
   const float ux = (jx + 0.5f * fx) * inv;
   const float uy = (jy + 0.5f * fy) * inv;
   const float uz = (jz + 0.5f * fz) * inv;
-  if (u_out) {
-    u_out[s] = ux;
-    u_out[N + s] = uy;
-    u_out[2 * N + s] = uz;
-  }
-  if (rho_out) rho_out[s] = rho;
+  if (macro) macro[s] = make_float4(ux, uy, uz, rho);
 
   const float om = L.omega;
   const float src = 1.f - 0.5f * om;
@@ -110,13 +105,31 @@ __global__ void k_init_equilibrium(float* __restrict__ g, float rho0, float ux, 
   }
 }
 
+// Streaming copy used as the measured bandwidth reference.
+__global__ __launch_bounds__(256) void k_copy16(float4* __restrict__ dst,
+                                                const float4* __restrict__ src, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
 }  // namespace
 
-hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float* rho,
-                                 float* u, const Lattice& L, hipStream_t s) {
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (float4*)dst,
+                     (const float4*)src, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float4* macro,
+                                 const Lattice& L, hipStream_t s) {
   const int64_t blocks = (L.n + 255) / 256;
-  hipLaunchKernelGGL(k_collide_stream, dim3((unsigned)blocks), dim3(256), 0, s, gin, gout, F, rho,
-                     u, L);
+  hipLaunchKernelGGL(k_collide_stream, dim3((unsigned)blocks), dim3(256), 0, s, gin, gout, F, macro,
+                     L);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhemo.so")
 
 HC_PERIODIC, HC_WALL = 0, 1
 HC_PHI2, HC_PHI4 = 2, 4
+KERNELS = ("membrane", "binning", "spread", "collide_stream", "interp_advect")
 STATUS = {0: "HC_OK", 1: "HC_ERR_ARG", 2: "HC_ERR_STATE", 3: "HC_ERR_DEVICE", 4: "HC_ERR_OOM",
           5: "HC_ERR_NONFINITE", 6: "HC_ERR_UNSUPPORTED"}
 
@@ -66,6 +67,9 @@ def _declare(lib):
         "hc_checkpoint_save": [_P, _P, sz],
         "hc_checkpoint_restore": [_P, _P, sz],
         "hc_get_step": [_P, _P],
+        "hc_profile": [_P, i32],
+        "hc_profile_read": [_P, _P, _P],
+        "hc_device_copy": [_P, _P, sz, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -242,13 +246,22 @@ class Simulation:
         owner = np.empty(self.n_cells * self.nv, dtype=np.int32)
         tptr = np.empty(nt + 1, dtype=np.int32)
         cptr = np.empty(nt + 1, dtype=np.int32)
-        cap_t = self.n_cells * self.nv * 8
+        cap_t = self.n_cells * self.nv * 27
         cap_c = self.n_cells * 216
         touch = np.empty(max(cap_t, 1), dtype=np.int32)
         cells = np.empty(max(cap_c, 1), dtype=np.int32)
         self._check(self.lib.hc_read_bins(self.ctx, _ptr(owner), _ptr(tptr), _ptr(touch), touch.size,
                                           _ptr(cptr), _ptr(cells), cells.size))
         return owner, tptr, touch[:tptr[-1]].copy(), cptr, cells[:cptr[-1]].copy()
+
+    def profile(self, enable: bool = True):
+        self._check(self.lib.hc_profile(self.ctx, int(enable)))
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(len(KERNELS), dtype=np.float64)
+        n = np.zeros(len(KERNELS), dtype=np.int64)
+        self._check(self.lib.hc_profile_read(self.ctx, _ptr(ms), _ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def checkpoint_save(self) -> bytes:
         n = C.c_size_t()
@@ -260,3 +273,11 @@ class Simulation:
     def checkpoint_restore(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(self.lib.hc_checkpoint_restore(self.ctx, _ptr(buf), buf.size))
+
+
+def device_copy(dst, src, nbytes: int, stream_handle: int):
+    """Library streaming copy (bandwidth reference) between two device buffers."""
+    lib = load_library()
+    rc = lib.hc_device_copy(C.c_void_p(dst), C.c_void_p(src), int(nbytes), C.c_void_p(stream_handle))
+    if rc:
+        raise HemoError(rc, lib.hc_last_error(None).decode())

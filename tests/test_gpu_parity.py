@@ -26,6 +26,8 @@ CASES = {
     "wall_y_moving": dict(seed=8, n=(28, 24, 20), n_cells=1, walls=1, body=(1e-5, 0, 0)),
     "wall_x_tau07": dict(seed=9, n=(24, 26, 28), n_cells=1, walls=0, tau=0.7),
     "phi2_kernel": dict(seed=10, n=(24, 20, 16), n_cells=2, ibm_kernel=2),
+    # last tile 1 node wide on x and z: a stencil window meets 3 tiles per axis
+    "ragged_tiles_33_25": dict(seed=11, n=(33, 20, 25), n_cells=3),
 }
 
 
@@ -126,7 +128,7 @@ def test_membrane_area_volume_fp64():
     assert relerr(fv, Fr) <= TOL_STEP
 
 
-@pytest.mark.parametrize("kernel,walls", [(4, -1), (4, 1), (2, 2)])
+@pytest.mark.parametrize("kernel,walls", [(4, -1), (4, 1), (2, 2), (2, -1)])
 def test_binning_bit_exact(kernel, walls):
     n = (40, 33, 24) if walls != 2 else (40, 33, 26)
     w = tiny_periodic(seed=14, n=n, n_cells=4 if walls < 0 else 1, walls=walls, ibm_kernel=kernel)
