@@ -24,9 +24,9 @@ constexpr int kMaxCellTiles = 216;   // 6 tiles per axis per cell
 thread_local std::string g_create_error;
 
 struct HostMesh {
-  int nv = 0, nt = 0, nh = 0;
-  std::vector<int> tri, vlink_ptr, vlink_j, vtri_ptr, vtri, vhinge_ptr, vhinge, hinge_v, hinge_t;
-  std::vector<float> vlink_L0, theta0, pole;
+  int nv = 0, nt = 0, ne = 0, nh = 0;
+  std::vector<int> tri, edge, hinge_v;
+  std::vector<float> L0, theta0, pole;
   double A0 = 0, V0 = 0;
 };
 
@@ -48,6 +48,9 @@ struct hc_ctx {
   Cells C{};
   Bins B{};
   int max_cells = 0;
+  int list_cap = 0;            // entries per tile list
+  int* touch_ptr = nullptr;    // CSR form of the tile lists (read-out only)
+  int* touch_csr = nullptr;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -68,8 +71,8 @@ struct hc_ctx {
   std::string err;
   // workspace offsets
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
-  size_t o_tri, o_vlp, o_vlj, o_vll, o_vtp, o_vt, o_vhp, o_vh, o_hv, o_ht, o_th0, o_pole;
-  size_t o_owner, o_ttile, o_trank, o_tcnt, o_tptr, o_touch, o_flags;
+  size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
+  size_t o_owner, o_ntouch, o_scan, o_slot, o_tcnt, o_tptr, o_touch, o_csr, o_flags;
   size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist;
 };
 
@@ -110,18 +113,19 @@ std::string build_mesh(const hc_mesh_desc* d, HostMesh& m) {
         return "mesh: repeated directed edge (inconsistent orientation)";
     }
   }
-  std::vector<std::vector<int>> vl(nv), vh(nv);
-  std::vector<std::vector<int>> vt(nv);
+  std::vector<int> degree(nv, 0);
   for (auto& kv : dir) {
     const int p = kv.first.first, q = kv.first.second;
     auto rev = dir.find(std::make_pair(q, p));
     if (rev == dir.end()) return "mesh: open edge (surface not closed)";
-    vl[p].push_back(q);
+    ++degree[p];
     if (p < q) {
-      const int h = m.nh++;
       const int k = kv.second.second, l = rev->second.second;
+      double s = 0;
+      for (int a = 0; a < 3; ++a) s += (P(q, a) - P(p, a)) * (P(q, a) - P(p, a));
+      m.edge.insert(m.edge.end(), {p, q});
+      m.L0.push_back((float)std::sqrt(s));
       m.hinge_v.insert(m.hinge_v.end(), {p, q, k, l});
-      m.hinge_t.insert(m.hinge_t.end(), {kv.second.first, rev->second.first});
       // rest dihedral angle, float64
       double e[3], u1[3], v1[3], u2[3], v2[3], n1[3], n2[3];
       for (int a = 0; a < 3; ++a) {
@@ -150,33 +154,12 @@ std::string build_mesh(const hc_mesh_desc* d, HostMesh& m) {
       const double sn = x[0] * e[0] + x[1] * e[1] + x[2] * e[2];
       const double cs = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
       m.theta0.push_back((float)std::atan2(sn, cs));
-      const int roles[4] = {p, q, k, l};
-      for (int r = 0; r < 4; ++r) vh[roles[r]].push_back(h * 4 + r);
     }
   }
-  for (int t = 0; t < nt; ++t)
-    for (int r = 0; r < 3; ++r) {
-      const int v = m.tri[3 * t + r];
-      vt[v].insert(vt[v].end(), {t, m.tri[3 * t + (r + 1) % 3], m.tri[3 * t + (r + 2) % 3]});
-    }
-  m.vlink_ptr.push_back(0);
-  m.vtri_ptr.push_back(0);
-  m.vhinge_ptr.push_back(0);
-  for (int v = 0; v < nv; ++v) {
-    if (vl[v].empty()) return "mesh: isolated vertex";
-    std::sort(vl[v].begin(), vl[v].end());
-    for (int j : vl[v]) {
-      double s = 0;
-      for (int a = 0; a < 3; ++a) s += (P(j, a) - P(v, a)) * (P(j, a) - P(v, a));
-      m.vlink_j.push_back(j);
-      m.vlink_L0.push_back((float)std::sqrt(s));
-    }
-    m.vlink_ptr.push_back((int)m.vlink_j.size());
-    m.vtri.insert(m.vtri.end(), vt[v].begin(), vt[v].end());
-    m.vtri_ptr.push_back((int)(m.vtri.size() / 3));
-    m.vhinge.insert(m.vhinge.end(), vh[v].begin(), vh[v].end());
-    m.vhinge_ptr.push_back((int)m.vhinge.size());
-  }
+  for (int v = 0; v < nv; ++v)
+    if (degree[v] == 0) return "mesh: isolated vertex";
+  m.ne = (int)m.L0.size();
+  m.nh = m.ne;
   // rest area and volume (float64, divergence theorem)
   double A = 0, V = 0;
   for (int t = 0; t < nt; ++t) {
@@ -234,23 +217,19 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_vol = lay.add(C * 8);
   const HostMesh& m = c->hm;
   c->o_tri = lay.add(m.tri.size() * 4);
-  c->o_vlp = lay.add(m.vlink_ptr.size() * 4);
-  c->o_vlj = lay.add(m.vlink_j.size() * 4);
-  c->o_vll = lay.add(m.vlink_L0.size() * 4);
-  c->o_vtp = lay.add(m.vtri_ptr.size() * 4);
-  c->o_vt = lay.add(m.vtri.size() * 4);
-  c->o_vhp = lay.add(m.vhinge_ptr.size() * 4);
-  c->o_vh = lay.add(m.vhinge.size() * 4);
+  c->o_edge = lay.add(m.edge.size() * 4);
+  c->o_L0 = lay.add(m.L0.size() * 4);
   c->o_hv = lay.add(m.hinge_v.size() * 4);
-  c->o_ht = lay.add(m.hinge_t.size() * 4);
   c->o_th0 = lay.add(m.theta0.size() * 4);
   c->o_pole = lay.add(m.pole.size() * 4);
   c->o_owner = lay.add(C * nv * 4);
-  c->o_ttile = lay.add(C * nv * c->L.max_touch * 4);
-  c->o_trank = lay.add(C * nv * c->L.max_touch * 4);
+  c->o_ntouch = lay.add(C * nv * 4);
+  c->o_scan = lay.add(((NT + 4095) / 4096 + 1) * 4);
+  c->o_slot = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 4);
   c->o_tcnt = lay.add((NT + 1) * 4);
   c->o_tptr = lay.add((NT + 1) * 4);
-  c->o_touch = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 4);
+  c->o_touch = lay.add(NT * (int64_t)c->list_cap * 4);
+  c->o_csr = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 4);
   c->o_partial = lay.add(std::max<int64_t>(1, C * nv * c->L.max_touch) * 16);
   c->o_flags = lay.add(16);
   c->o_ccnt = lay.add((NT + 1) * 4);
@@ -387,6 +366,11 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     L.max_touch *= std::min(per_axis, (sides[d] + kTile - 1) / kTile);
   }
   c->max_cells = max_cells;
+  // tile-list capacity: 4 entries per tile node (about 4x the densest
+  // suspension's mean), capped by what all vertices could ever need
+  c->list_cap = (int)std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)4 * kTile * kTile * kTile,
+                           (int64_t)max_cells * c->hm.nv * L.max_touch));
   *out = c;
   return HC_OK;
 }
@@ -459,17 +443,12 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   Mesh& M = c->M;
   M.nv = m.nv;
   M.nt = m.nt;
+  M.ne = m.ne;
   M.nh = m.nh;
   M.tri = at<int>(c, c->o_tri);
-  M.vlink_ptr = at<int>(c, c->o_vlp);
-  M.vlink_j = at<int>(c, c->o_vlj);
-  M.vlink_L0 = at<float>(c, c->o_vll);
-  M.vtri_ptr = at<int>(c, c->o_vtp);
-  M.vtri = at<int>(c, c->o_vt);
-  M.vhinge_ptr = at<int>(c, c->o_vhp);
-  M.vhinge = at<int>(c, c->o_vh);
+  M.edge = at<int>(c, c->o_edge);
+  M.L0 = at<float>(c, c->o_L0);
   M.hinge_v = at<int>(c, c->o_hv);
-  M.hinge_t = at<int>(c, c->o_ht);
   M.theta0 = at<float>(c, c->o_th0);
   M.pole = at<float>(c, c->o_pole);
   M.inv_npole = 1.0f / kNPole;
@@ -487,12 +466,14 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   C.volume = at<double>(c, c->o_vol);
   Bins& B = c->B;
   B.owner = at<int>(c, c->o_owner);
-  B.touch_tile = at<int>(c, c->o_ttile);
-  B.touch_rank = at<int>(c, c->o_trank);
+  B.ntouch = at<int>(c, c->o_ntouch);
+  B.scan_tmp = at<int>(c, c->o_scan);
+  B.slot = at<int>(c, c->o_slot);
   B.touch_cnt = at<int>(c, c->o_tcnt);
-  B.touch_ptr = at<int>(c, c->o_tptr);
   B.touch = at<int>(c, c->o_touch);
-  B.touch_cap = (int64_t)c->max_cells * m.nv * c->L.max_touch;
+  B.cap = c->list_cap;
+  c->touch_ptr = at<int>(c, c->o_tptr);
+  c->touch_csr = at<int>(c, c->o_csr);
   B.flags = at<int>(c, c->o_flags);
   c->cell_cnt = at<int>(c, c->o_ccnt);
   c->cell_ptr = at<int>(c, c->o_cptr);
@@ -500,15 +481,9 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   c->cell_rank = at<int>(c, c->o_crank);
   c->cell_list = at<int>(c, c->o_clist);
   HC_TRY(copy_h2d(c, (void*)M.tri, m.tri.data(), m.tri.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vlink_ptr, m.vlink_ptr.data(), m.vlink_ptr.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vlink_j, m.vlink_j.data(), m.vlink_j.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vlink_L0, m.vlink_L0.data(), m.vlink_L0.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vtri_ptr, m.vtri_ptr.data(), m.vtri_ptr.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vtri, m.vtri.data(), m.vtri.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vhinge_ptr, m.vhinge_ptr.data(), m.vhinge_ptr.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.vhinge, m.vhinge.data(), m.vhinge.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.edge, m.edge.data(), m.edge.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.L0, m.L0.data(), m.L0.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.hinge_v, m.hinge_v.data(), m.hinge_v.size() * 4));
-  HC_TRY(copy_h2d(c, (void*)M.hinge_t, m.hinge_t.data(), m.hinge_t.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.theta0, m.theta0.data(), m.theta0.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
   HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
@@ -563,7 +538,9 @@ hc_status hc_sync(hc_ctx* c) {
     HC_TRY(check(c, launch_fill_i32(c->B.flags, 0, 4, c->stream), "clear flags"));
     HC_TRY(sync(c, "sync"));
     if (flags[0]) return fail(c, HC_ERR_NONFINITE, "non-finite vertex position");
-    if (flags[1] & 2) return fail(c, HC_ERR_DEVICE, "touch list overflow");
+    if (flags[1] & 2) return fail(c, HC_ERR_DEVICE, "touch slots overflow");
+    if (flags[1] & 4) return fail(c, HC_ERR_UNSUPPORTED, "a tile list exceeded its capacity");
+    if (flags[1] & 8) return fail(c, HC_ERR_UNSUPPORTED, "a cell reaches more than 256 tiles");
     return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
   }
   return HC_OK;
@@ -655,26 +632,28 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
   if (!touch_ptr || !cell_ptr) return fail(c, HC_ERR_ARG, "null pointer array");
   const int NT = c->L.ntiles;
   HC_TRY(check(c, launch_bin_vertices(c->C, c->M, c->L, c->B, c->stream), "binning"));
-  HC_TRY(check(c, launch_sort_segments(c->B.touch_ptr, c->B.touch, c->B.touch_rank, NT, c->stream),
+  HC_TRY(check(c, launch_touch_csr(c->L, c->B, c->cell_cnt, c->touch_ptr, c->touch_csr, c->stream),
+               "tile lists"));
+  HC_TRY(check(c, launch_sort_segments(c->touch_ptr, c->touch_csr, c->B.slot, NT, c->stream),
                "sort"));
   HC_TRY(check(c, launch_bin_cells(c->C, c->M, c->L, c->cell_cnt, c->cell_ptr, c->cell_rank,
                                    c->cell_tiles, c->cell_list,
                                    (int64_t)c->max_cells * kMaxCellTiles, kMaxCellTiles,
-                                   c->B.flags, c->stream),
+                                   c->B.flags, c->B.scan_tmp, c->stream),
                "cell binning"));
   HC_TRY(check(c, launch_sort_segments(c->cell_ptr, c->cell_list, c->cell_rank, NT, c->stream),
                "sort"));
-  HC_TRY(copy_d2h(c, touch_ptr, c->B.touch_ptr, (size_t)(NT + 1) * 4));
+  HC_TRY(copy_d2h(c, touch_ptr, c->touch_ptr, (size_t)(NT + 1) * 4));
   HC_TRY(copy_d2h(c, cell_ptr, c->cell_ptr, (size_t)(NT + 1) * 4));
   HC_TRY(sync(c, "read bins"));
   int flags[4];
   HC_TRY(copy_d2h(c, flags, c->B.flags, sizeof(flags)));
   HC_TRY(sync(c, "read bins"));
-  if (flags[1]) return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
+  if (flags[1]) return fail(c, HC_ERR_UNSUPPORTED, "tile-list or cell-cover capacity exceeded");
   if (touch_ptr[NT] > cap_touch || cell_ptr[NT] > cap_cells)
     return fail(c, HC_ERR_ARG, "bin capacity too small");
   if (owner) HC_TRY(copy_d2h(c, owner, c->B.owner, (size_t)c->C.n * c->hm.nv * 4));
-  if (touch) HC_TRY(copy_d2h(c, touch, c->B.touch, (size_t)touch_ptr[NT] * 4));
+  if (touch) HC_TRY(copy_d2h(c, touch, c->touch_csr, (size_t)touch_ptr[NT] * 4));
   if (cells) HC_TRY(copy_d2h(c, cells, c->cell_list, (size_t)cell_ptr[NT] * 4));
   HC_TRY(sync(c, "read bins"));
   if (touch)

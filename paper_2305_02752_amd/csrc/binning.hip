@@ -38,70 +38,102 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
   return cnt;
 }
 
-// Rank of this lane's element in the per-tile counter, with one atomic per
-// distinct tile in the wave (lanes of one cell mostly share tiles).
-__device__ inline int wave_counted_rank(int* cnt, int tile, bool active) {
-  const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long pending = __ballot(active);
-  int rank = 0;
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int t = __shfl(tile, leader);
-    const unsigned long long mask = pending & __ballot(active && tile == t);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&cnt[t], __popcll(mask));
-    base = __shfl(base, leader);
-    if ((mask >> lane) & 1ull) rank = base + __popcll(mask & ((1ull << lane) - 1ull));
-    pending &= ~mask;
-  }
-  return rank;
-}
-
-__global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
-  const int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = v0 < (int64_t)C.n * M.nv;
-  const int64_t v = live ? v0 : 0;
+// Tiles reached by the stencil of vertex v, per axis, and its owner tile.
+__device__ inline int vertex_tiles(const Cells& C, const Mesh& M, const Lattice& L, int64_t v,
+                                   int (&T)[3][3], int (&nT)[3]) {
   const int c = (int)(v / M.nv);
   const float* o = C.off + v * 3;
   const int K = L.kernel;
   const int b = K == 4 ? -1 : 0;
-  int p[3];
-  int n[3] = {L.nx, L.ny, L.nz};
-  int T[3][3], nT[3];
+  const int n[3] = {L.nx, L.ny, L.nz};
+  int own[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    p[d] = C.origin[3 * c + d] + (int)floorf(o[d]);
-    nT[d] = axis_tiles(p[d] + b, K, n[d], L.bc[d] == 1, T[d]);
-    int q = L.bc[d] == 1 ? min(max(p[d], 0), n[d] - 1) : wrap(p[d], n[d]);
-    p[d] = q / kTile;
+    const int p = C.origin[3 * c + d] + (int)floorf(o[d]);
+    nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
+    own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : wrap(p, n[d])) / kTile;
   }
-  if (live) B.owner[v] = (p[2] * L.ty + p[1]) * L.tx + p[0];
-  const int ntouch = live ? nT[0] * nT[1] * nT[2] : 0;
-  if (live && ntouch > L.max_touch) atomicOr(&B.flags[1], 2);  // excluded by the bound set at create
-  // all lanes walk the same slot sequence so the wave can aggregate atomics
-  for (int j = 0; j < L.max_touch; ++j) {
-    const bool act = j < ntouch;
-    int tile = 0;
-    if (act) {
-      const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
-      tile = (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
+  return (own[2] * L.ty + own[1]) * L.tx + own[0];
+}
+
+__device__ inline int slot_tile(const Lattice& L, const int (&T)[3][3], const int (&nT)[3], int j) {
+  const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
+  return (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
+}
+
+constexpr int kHash = 256;   // distinct tiles one cell may reach
+
+// One work-group per cell.  Every (vertex, reached tile) pair gets a local
+// rank in an LDS hash table keyed by tile; then one global atomic per
+// distinct tile reserves a contiguous block of that tile's list, and the
+// pairs are written at block base + local rank.  Tile lists have a fixed
+// capacity of B.cap entries; an overflow raises flags[1] bit 4.
+__global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
+  __shared__ int keys[kHash], count[kHash], base[kHash];
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < kHash; i += blockDim.x) {
+    keys[i] = -1;
+    count[i] = 0;
+  }
+  __syncthreads();
+  for (int vl = threadIdx.x; vl < M.nv; vl += blockDim.x) {
+    const int64_t v = (int64_t)c * M.nv + vl;
+    int T[3][3], nT[3];
+    B.owner[v] = vertex_tiles(C, M, L, v, T, nT);
+    int ntouch = nT[0] * nT[1] * nT[2];
+    if (ntouch > L.max_touch) {  // excluded by the per-axis bound set at create
+      atomicOr(&B.flags[1], 2);
+      ntouch = L.max_touch;
     }
-    const int rank = wave_counted_rank(B.touch_cnt, tile, act);
-    if (live) {
-      B.touch_tile[v * L.max_touch + j] = act ? tile : -1;
-      if (act) B.touch_rank[v * L.max_touch + j] = rank;
+    B.ntouch[v] = ntouch;
+    for (int j = 0; j < ntouch; ++j) {
+      const int tile = slot_tile(L, T, nT, j);
+      int h = (int)(((unsigned)tile * 2654435761u) >> 24);
+      int probe = 0;
+      for (; probe < kHash; ++probe) {
+        const int prev = atomicCAS(&keys[h], -1, tile);
+        if (prev == -1 || prev == tile) break;
+        h = (h + 1) & (kHash - 1);
+      }
+      if (probe == kHash) {
+        atomicOr(&B.flags[1], 8);
+        B.slot[v * L.max_touch + j] = -1;
+        continue;
+      }
+      B.slot[v * L.max_touch + j] = (h << 16) | atomicAdd(&count[h], 1);
+    }
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kHash; h += blockDim.x) {
+    if (keys[h] < 0) continue;
+    base[h] = atomicAdd(&B.touch_cnt[keys[h]], count[h]);
+    if (base[h] + count[h] > B.cap) atomicOr(&B.flags[1], 4);
+  }
+  __syncthreads();
+  for (int vl = threadIdx.x; vl < M.nv; vl += blockDim.x) {
+    const int64_t v = (int64_t)c * M.nv + vl;
+    const int ntouch = B.ntouch[v];
+    for (int j = 0; j < ntouch; ++j) {
+      const int packed = B.slot[v * L.max_touch + j];
+      if (packed < 0) continue;
+      const int h = packed >> 16;
+      const int pos = base[h] + (packed & 0xffff);
+      if (pos < B.cap) B.touch[(int64_t)keys[h] * B.cap + pos] = (int)(v * 32 + j);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_fill_touch(int64_t nvtot, int max_touch, Bins B) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvtot) return;
-  for (int j = 0; j < max_touch; ++j) {
-    const int t = B.touch_tile[v * max_touch + j];
-    if (t < 0) break;
-    B.touch[B.touch_ptr[t] + B.touch_rank[v * max_touch + j]] = (int)(v * 32 + j);
-  }
+// Copy the fixed-capacity tile lists into CSR form (read-out path).
+__global__ __launch_bounds__(256) void k_compact_touch(Bins B, const int* __restrict__ ptr,
+                                                       int* __restrict__ out) {
+  const int t = blockIdx.x;
+  const int n = ptr[t + 1] - ptr[t];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[ptr[t] + i] = B.touch[(int64_t)t * B.cap + i];
+}
+
+__global__ void k_clamp_counts(const int* __restrict__ cnt, int* __restrict__ out, int cap, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = min(cnt[i], cap);
 }
 
 // One wave per cell: stencil bounding box -> covered tiles, counted per tile.
@@ -172,29 +204,68 @@ __global__ void k_fill_cells(int ncells, int max_per_cell, const int* tiles, con
   list[ptr[t] + rank[i]] = (int)(i / max_per_cell);
 }
 
-// Exclusive scan of n counts into ptr[0..n] with one work-group.
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int* __restrict__ ptr,
-                                               int n) {
-  __shared__ int part[1024];
+// Exclusive scan of n counts into ptr[0..n]: per-block scan of 4096
+// entries (coalesced), a one-block scan of the block sums, then the offsets.
+constexpr int kScanBlock = 1024, kScanItems = 4;
+
+__device__ inline int block_exclusive_scan(int x, int* part, int* total) {
   const int tid = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int a = min(n, tid * chunk), b = min(n, a + chunk);
-  int sum = 0;
-  for (int i = a; i < b; ++i) sum += cnt[i];
-  part[tid] = sum;
+  part[tid] = x;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = tid >= off ? part[tid - off] : 0;
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const int y = tid >= off ? part[tid - off] : 0;
     __syncthreads();
-    part[tid] += v;
+    part[tid] += y;
     __syncthreads();
   }
-  int run = part[tid] - sum;
-  for (int i = a; i < b; ++i) {
-    ptr[i] = run;
-    run += cnt[i];
+  const int incl = part[tid];
+  *total = part[kScanBlock - 1];
+  __syncthreads();
+  return incl - x;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(const int* __restrict__ cnt,
+                                                            int* __restrict__ ptr,
+                                                            int* __restrict__ sums, int n) {
+  __shared__ int part[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock * kScanItems;
+  int x[kScanItems], s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    x[k] = i < n ? cnt[i] : 0;
+    s += x[k];
   }
-  if (tid == 1023) ptr[n] = part[1023];
+  int total;
+  int run = block_exclusive_scan(s, part, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    if (i < n) ptr[i] = run;
+    run += x[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int* __restrict__ sums, int nb,
+                                                          int* __restrict__ ptr, int n) {
+  __shared__ int part[kScanBlock];
+  int carry = 0;
+  for (int a = 0; a < nb; a += kScanBlock) {
+    const int i = a + threadIdx.x;
+    const int x = i < nb ? sums[i] : 0;
+    int total;
+    const int ex = block_exclusive_scan(x, part, &total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) ptr[n] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int* __restrict__ ptr, const int* __restrict__ sums,
+                                                  int n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ptr[i] += sums[i / (kScanBlock * kScanItems)];
 }
 
 // Sort every segment [ptr[s], ptr[s+1]) of distinct ints by rank counting.
@@ -225,33 +296,36 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const int* cnt, int* ptr, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, ptr, n);
+hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s) {
+  const int nb = (n + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanBlock), 0, s, cnt, ptr, sums, n);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, sums, nb, ptr, n);
+  hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, ptr, sums, n);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                                hipStream_t s) {
-  hipError_t e = launch_fill_i32(b.touch_cnt, 0, L.ntiles + 1, s);
+  hipError_t e = launch_fill_i32(b.touch_cnt, 0, L.ntiles, s);
+  if (e != hipSuccess || c.n == 0) return e;
+  hipLaunchKernelGGL(k_bin_vertices, dim3(c.n), dim3(256), 0, s, c, m, L, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_touch_csr(const Lattice& L, const Bins& b, int* cnt_tmp, int* ptr, int* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_clamp_counts, dim3((L.ntiles + 255) / 256), dim3(256), 0, s, b.touch_cnt,
+                     cnt_tmp, b.cap, L.ntiles);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t n = (int64_t)c.n * m.nv;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_bin_vertices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, m, L,
-                       b);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  if ((e = launch_scan(b.touch_cnt, b.touch_ptr, L.ntiles, s)) != hipSuccess) return e;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_fill_touch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       L.max_touch, b);
-    e = hipGetLastError();
-  }
-  return e;
+  if ((e = launch_scan(cnt_tmp, ptr, b.scan_tmp, L.ntiles, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_touch, dim3(L.ntiles), dim3(256), 0, s, b, ptr, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_bin_cells(const Cells& c, const Mesh& m, const Lattice& L, int* cnt, int* ptr,
                             int* rank, int* tiles, int* list, int64_t cap, int max_per_cell,
-                            int* flags, hipStream_t s) {
+                            int* flags, int* scan_tmp, hipStream_t s) {
   (void)cap;
   hipError_t e = launch_fill_i32(cnt, 0, L.ntiles + 1, s);
   if (e != hipSuccess) return e;
@@ -260,7 +334,7 @@ hipError_t launch_bin_cells(const Cells& c, const Mesh& m, const Lattice& L, int
                        max_per_cell, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(cnt, ptr, L.ntiles, s)) != hipSuccess) return e;
+  if ((e = launch_scan(cnt, ptr, scan_tmp, L.ntiles, s)) != hipSuccess) return e;
   const int64_t n = (int64_t)c.n * max_per_cell;
   if (n > 0) {
     hipLaunchKernelGGL(k_fill_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.n,

@@ -14,10 +14,38 @@ constexpr int kTile = 8;        // binning tile side (lattice nodes)
 constexpr int kMaxTouch = 27;   // tiles reached by one stencil: <= 3 per axis (a periodic
                                 // axis whose last tile is 1-2 nodes wide), else 2
 constexpr int kWave = 64;       // gfx950 wavefront width
-// Fixed-point scale of the deterministic force accumulation: 2^48 units per
-// lattice force unit (resolution 3.6e-15, range +-32768).
-constexpr double kFixScale = 281474976710656.0;
-constexpr double kFixInv = 1.0 / 281474976710656.0;
+// Fixed-point scale of the deterministic force accumulation: 2^40 units per
+// lattice force unit (resolution 9.1e-13, accumulator range +-8.4e6).
+constexpr double kFixScale = 1099511627776.0;
+constexpr float kFixScaleF = 1099511627776.0f;
+constexpr double kFixInv = 1.0 / 1099511627776.0;
+
+// Largest float below 2^31: scaled contributions under it take the native
+// 32-bit conversion; larger ones the 64-bit one.  Both give the same integer
+// (round to nearest even of the same float), so the choice never changes a
+// result.
+constexpr float kFix32Max = 2147483520.0f;
+
+[[maybe_unused]] static __device__ __noinline__ void fix_add3_wide(long long* a0, long long* a1,
+                                                                   long long* a2, float x, float y,
+                                                                   float z) {
+  atomicAdd((unsigned long long*)a0, (unsigned long long)__float2ll_rn(x));
+  atomicAdd((unsigned long long*)a1, (unsigned long long)__float2ll_rn(y));
+  atomicAdd((unsigned long long*)a2, (unsigned long long)__float2ll_rn(z));
+}
+
+// acc[k] += round(q_k) for three scaled components; the wide path is a real
+// branch, taken only by lanes holding a contribution of 2^31 or more.
+__device__ inline void fix_add3(long long* a0, long long* a1, long long* a2, float x, float y,
+                                float z) {
+  if (fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z))) < kFix32Max) {
+    atomicAdd((unsigned long long*)a0, (unsigned long long)(long long)__float2int_rn(x));
+    atomicAdd((unsigned long long*)a1, (unsigned long long)(long long)__float2int_rn(y));
+    atomicAdd((unsigned long long*)a2, (unsigned long long)(long long)__float2int_rn(z));
+  } else {
+    fix_add3_wide(a0, a1, a2, x, y, z);
+  }
+}
 
 struct Lattice {
   int nx, ny, nz;
@@ -34,17 +62,11 @@ struct Lattice {
 
 // Mesh tables shared by every cell (built on the host from the rest shape).
 struct Mesh {
-  int nv, nt, nh;
+  int nv, nt, ne, nh;
   const int* tri;           // [nt][3]
-  const int* vlink_ptr;     // [nv+1]  per-vertex neighbour list
-  const int* vlink_j;
-  const float* vlink_L0;    // rest length of that link
-  const int* vtri_ptr;      // [nv+1]  per-vertex incident triangles
-  const int* vtri;          // [.][3]  (t, j, k): t = (v, j, k) counter-clockwise
-  const int* vhinge_ptr;    // [nv+1]  per-vertex hinge roles
-  const int* vhinge;        // h * 4 + role, role 0..3 = i, j, k, l
-  const int* hinge_v;       // [nh][4] (i, j, k, l)
-  const int* hinge_t;       // [nh][2] triangles (i, j, k) and (j, i, l)
+  const int* edge;          // [ne][2] (i < j)
+  const float* L0;          // [ne] rest length
+  const int* hinge_v;       // [nh][4] (i, j, k, l): i->j in (i, j, k), j->i in (j, i, l)
   const float* theta0;      // [nh]
   const float* pole;        // [nv] +1 / -1 / 0: pole traction sign
   float inv_npole;          // 1 / |P+|
@@ -65,13 +87,13 @@ struct Cells {
 
 struct Bins {
   int* owner;               // [n*nv]
-  int* touch_tile;          // [n*nv][8] tile ids reached (-1 unused)
-  int* touch_rank;          // [n*nv][8] slot within the tile list
-  int* touch_cnt;           // [ntiles+1]
-  int* touch_ptr;           // [ntiles+1]
-  int* touch;               // [capacity] vertex * 32 + slot (slot j of touch_tile)
-  int64_t touch_cap;
+  int* ntouch;              // [n*nv] tiles reached by the vertex's stencil
+  int* slot;                // [n*nv][max_touch] hash slot << 16 | rank (binning scratch)
+  int* touch_cnt;           // [ntiles] entries in each tile list
+  int* touch;               // [ntiles][cap] vertex * 32 + j (its j-th reached tile)
+  int cap;                  // fixed capacity of one tile list
   int* flags;               // [4]: 0 non-finite, 1 list overflow
+  int* scan_tmp;            // block sums of the tile scan
 };
 
 // Launchers (one per kernel family); all enqueue on `s`.
@@ -80,9 +102,11 @@ hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, 
                                hipStream_t s);
 hipError_t launch_bin_cells(const Cells& c, const Mesh& m, const Lattice& L, int* cnt, int* ptr,
                             int* rank, int* tiles, int* list, int64_t cap, int max_per_cell,
-                            int* flags, hipStream_t s);
+                            int* flags, int* scan_tmp, hipStream_t s);
+hipError_t launch_touch_csr(const Lattice& L, const Bins& b, int* cnt_tmp, int* ptr, int* out,
+                            hipStream_t s);
 hipError_t launch_sort_segments(const int* ptr, int* list, int* tmp, int nseg, hipStream_t s);
-hipError_t launch_scan(const int* cnt, int* ptr, int n, hipStream_t s);
+hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                          float* F, hipStream_t s);

@@ -9,7 +9,7 @@
 //
 // Spreading and interpolation are organised by tile: one work-group per 8^3
 // tile walks the list of vertices whose stencil reaches the tile (built by
-// the binning kernels).  Spreading accumulates in LDS as 2^-48 fixed-point
+// the binning kernels).  Spreading accumulates in LDS as 2^-40 fixed-point
 // int64 values; interpolation writes one partial sum per (vertex, tile) that
 // a per-vertex pass adds up in a fixed order.
 // Integer addition is associative, so the result is bitwise independent of
@@ -28,7 +28,8 @@ __device__ inline float phi4(float r) {
 }
 
 // Weight of stencil node k (0..K-1) for fractional position f in [0, 1).
-__device__ inline float stencil_w(int K, float f, int k) {
+template <int K>
+__device__ inline float stencil_w(float f, int k) {
   if (K == 4) return phi4(f + 1.f - (float)k);
   return k == 0 ? 1.f - f : f;
 }
@@ -39,32 +40,66 @@ __device__ inline int wrap(int p, int n) {
 }
 
 // Per-axis stencil of one vertex relative to a tile starting at t0: local
-// node index inside the tile (-1 outside the tile or beyond a wall) and weight.
-__device__ inline void axis_stencil(int base, float frac, int K, int n, int wall, int t0, int* l,
-                                    float* w) {
+// node index inside the tile (-1 outside the tile or beyond a wall) and
+// weight; the first node is floor(X) - 1 (K = 4) or floor(X) (K = 2).
+template <int K>
+__device__ inline void axis_stencil(int origin, float x, int n, int wall, int t0, int (&l)[K],
+                                    float (&w)[K]) {
+  const float fl = floorf(x);
+  const int base = origin + (int)fl - (K == 4 ? 1 : 0);
+  const float f = x - fl;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    l[k] = -1;
-    w[k] = 0.f;
-    if (k < K) {
-      int p = base + k;
-      bool in = true;
-      if (wall) in = p >= 0 && p < n; else p = wrap(p, n);
-      l[k] = (in && p >= t0 && p < t0 + kTile) ? p - t0 : -1;
-      w[k] = stencil_w(K, frac, k);
-    }
+  for (int k = 0; k < K; ++k) {
+    int p = base + k;
+    bool in = true;
+    if (wall) in = p >= 0 && p < n; else p = wrap(p, n);
+    l[k] = (in && p >= t0 && p < t0 + kTile) ? p - t0 : -1;
+    w[k] = stencil_w<K>(f, k);
   }
 }
 
-// One work-group per tile; one thread per (vertex, tile) entry of the touch
+// Rotate a K-entry stencil by r so that lanes holding nearby vertices visit
+// different nodes at the same time (fewer LDS same-address conflicts).
+template <int K>
+__device__ inline void rotate(int (&l)[K], float (&w)[K], int r) {
+  int l2[K];
+  float w2[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int src = (k + r) & (K - 1);
+    l2[k] = l[0];
+    w2[k] = w[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) {
+      if (src == q) {
+        l2[k] = l[q];
+        w2[k] = w[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    l[k] = l2[k];
+    w[k] = w2[k];
+  }
+}
+
+__device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, int& z0) {
+  x0 = (t % L.tx) * kTile;
+  y0 = ((t / L.tx) % L.ty) * kTile;
+  z0 = (t / (L.tx * L.ty)) * kTile;
+}
+
+// One work-group per tile; one thread per (vertex, tile) entry of the tile's
 // list: the thread evaluates its 3 x K axis weights once and adds the
 // contributions of the stencil nodes inside the tile to the LDS accumulator.
+template <int K>
 __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
                                                 float* __restrict__ F) {
   __shared__ long long acc[3][kTile * kTile * kTile];
   const int t = blockIdx.x;
-  const int tx = t % L.tx, ty = (t / L.tx) % L.ty, tz = t / (L.tx * L.ty);
-  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  int x0, y0, z0;
+  tile_origin(L, t, x0, y0, z0);
   for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
     acc[0][i] = 0;
     acc[1][i] = 0;
@@ -72,38 +107,36 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
   }
   __syncthreads();
 
-  const int K = L.kernel;
-  const int b = K == 4 ? -1 : 0;
-  const int e0 = B.touch_ptr[t], e1 = B.touch_ptr[t + 1];
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+  const int64_t e0 = (int64_t)t * B.cap;
+  const int64_t e1 = e0 + min(B.touch_cnt[t], B.cap);
+  const int rot = threadIdx.x;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int v = B.touch[e] >> 5;
     const int c = v / M.nv;
     const float* o = C.off + (int64_t)v * 3;
     const float* fv = C.force + (int64_t)v * 3;
-    const float ox = o[0], oy = o[1], oz = o[2];
-    const float fx = fv[0], fy = fv[1], fz = fv[2];
-    const float flx = floorf(ox), fly = floorf(oy), flz = floorf(oz);
-    int lx[4], ly[4], lz[4];
-    float wx[4], wy[4], wz[4];
-    axis_stencil(C.origin[3 * c + 0] + (int)flx + b, ox - flx, K, L.nx, L.bc[0] == 1, x0, lx, wx);
-    axis_stencil(C.origin[3 * c + 1] + (int)fly + b, oy - fly, K, L.ny, L.bc[1] == 1, y0, ly, wy);
-    axis_stencil(C.origin[3 * c + 2] + (int)flz + b, oz - flz, K, L.nz, L.bc[2] == 1, z0, lz, wz);
+    const float fx = fv[0] * kFixScaleF, fy = fv[1] * kFixScaleF, fz = fv[2] * kFixScaleF;
+    int lx[K], ly[K], lz[K];
+    float wx[K], wy[K], wz[K];
+    axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
+    axis_stencil<K>(C.origin[3 * c + 1], o[1], L.ny, L.bc[1] == 1, y0, ly, wy);
+    axis_stencil<K>(C.origin[3 * c + 2], o[2], L.nz, L.bc[2] == 1, z0, lz, wz);
+    rotate<K>(lx, wx, rot);
+    rotate<K>(ly, wy, rot >> 2);
+#pragma unroll
     for (int kz = 0; kz < K; ++kz) {
       if (lz[kz] < 0) continue;
+#pragma unroll
       for (int ky = 0; ky < K; ++ky) {
         if (ly[ky] < 0) continue;
         const float wzy = wz[kz] * wy[ky];
         const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+#pragma unroll
         for (int kx = 0; kx < K; ++kx) {
           if (lx[kx] < 0) continue;
           const float w = wzy * wx[kx];
           const int li = row + lx[kx];
-          atomicAdd((unsigned long long*)&acc[0][li],
-                    (unsigned long long)__float2ll_rn(w * fx * (float)kFixScale));
-          atomicAdd((unsigned long long*)&acc[1][li],
-                    (unsigned long long)__float2ll_rn(w * fy * (float)kFixScale));
-          atomicAdd((unsigned long long*)&acc[2][li],
-                    (unsigned long long)__float2ll_rn(w * fz * (float)kFixScale));
+          fix_add3(&acc[0][li], &acc[1][li], &acc[2][li], w * fx, w * fy, w * fz);
         }
       }
     }
@@ -112,8 +145,7 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
 
   const int64_t N = L.n;
   for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
-    const int lx = i % kTile, ly = (i / kTile) % kTile, lz = i / (kTile * kTile);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
     if (x >= L.nx || y >= L.ny || z >= L.nz) continue;
     const int64_t s = ((int64_t)z * L.ny + y) * L.nx + x;
     F[s] = L.g[0] + (float)((double)acc[0][i] * kFixInv);
@@ -125,42 +157,43 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
 // Interpolation, first half: one work-group per tile stages the tile's
 // velocities in LDS; each (vertex, tile) entry sums w * u over its stencil
 // nodes inside the tile and stores the partial sum in the vertex's slot.
+template <int K>
 __global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattice L, Bins B,
                                                          const float4* __restrict__ macro,
                                                          float4* __restrict__ partial) {
   __shared__ float4 su[kTile * kTile * kTile];
   const int t = blockIdx.x;
-  const int tx = t % L.tx, ty = (t / L.tx) % L.ty, tz = t / (L.tx * L.ty);
-  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
-  const int e0 = B.touch_ptr[t], e1 = B.touch_ptr[t + 1];
-  if (e0 == e1) return;
+  const int cnt = min(B.touch_cnt[t], B.cap);
+  if (cnt == 0) return;
+  int x0, y0, z0;
+  tile_origin(L, t, x0, y0, z0);
   for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
     const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
     su[i] = (x < L.nx && y < L.ny && z < L.nz) ? macro[((int64_t)z * L.ny + y) * L.nx + x]
                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
-  const int K = L.kernel;
-  const int b = K == 4 ? -1 : 0;
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+  const int64_t e0 = (int64_t)t * B.cap, e1 = e0 + cnt;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int code = B.touch[e];
     const int v = code >> 5, j = code & 31;
     const int c = v / M.nv;
     const float* o = C.off + (int64_t)v * 3;
-    const float ox = o[0], oy = o[1], oz = o[2];
-    const float flx = floorf(ox), fly = floorf(oy), flz = floorf(oz);
-    int lx[4], ly[4], lz[4];
-    float wx[4], wy[4], wz[4];
-    axis_stencil(C.origin[3 * c + 0] + (int)flx + b, ox - flx, K, L.nx, L.bc[0] == 1, x0, lx, wx);
-    axis_stencil(C.origin[3 * c + 1] + (int)fly + b, oy - fly, K, L.ny, L.bc[1] == 1, y0, ly, wy);
-    axis_stencil(C.origin[3 * c + 2] + (int)flz + b, oz - flz, K, L.nz, L.bc[2] == 1, z0, lz, wz);
+    int lx[K], ly[K], lz[K];
+    float wx[K], wy[K], wz[K];
+    axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
+    axis_stencil<K>(C.origin[3 * c + 1], o[1], L.ny, L.bc[1] == 1, y0, ly, wy);
+    axis_stencil<K>(C.origin[3 * c + 2], o[2], L.nz, L.bc[2] == 1, z0, lz, wz);
     float ux = 0.f, uy = 0.f, uz = 0.f;
+#pragma unroll
     for (int kz = 0; kz < K; ++kz) {
       if (lz[kz] < 0) continue;
+#pragma unroll
       for (int ky = 0; ky < K; ++ky) {
         if (ly[ky] < 0) continue;
         const float wzy = wz[kz] * wy[ky];
         const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+#pragma unroll
         for (int kx = 0; kx < K; ++kx) {
           if (lx[kx] < 0) continue;
           const float w = wzy * wx[kx];
@@ -179,14 +212,15 @@ __global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattic
 // vertex sums its tile partials in slot order (fixed, so the result is
 // reproducible), adds stencil nodes beyond a wall at the wall velocity, and
 // moves the vertex.
+template <int K>
 __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins B,
                                                 const float4* __restrict__ partial,
                                                 int* __restrict__ flags) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
-  for (int j = 0; j < L.max_touch; ++j) {
-    if (B.touch_tile[v * L.max_touch + j] < 0) break;
+  const int nt = B.ntouch[v];
+  for (int j = 0; j < nt; ++j) {
     const float4 q = partial[v * L.max_touch + j];
     Ux += q.x;
     Uy += q.y;
@@ -199,16 +233,16 @@ __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins
     // wall contributes its axis weight times the wall velocity
     const int d = L.wall_axis;
     const int c = (int)(v / M.nv);
-    const int K = L.kernel;
     const float od = d == 0 ? ox : (d == 1 ? oy : oz);
     const float fl = floorf(od);
     const int n = d == 0 ? L.nx : (d == 1 ? L.ny : L.nz);
-    const int base = C.origin[3 * c + d] + (int)fl + (K == 4 ? -1 : 0);
+    const int base = C.origin[3 * c + d] + (int)fl - (K == 4 ? 1 : 0);
     float wlo = 0.f, whi = 0.f;
+#pragma unroll
     for (int k = 0; k < K; ++k) {
       const int p = base + k;
-      if (p < 0) wlo += stencil_w(K, od - fl, k);
-      if (p >= n) whi += stencil_w(K, od - fl, k);
+      if (p < 0) wlo += stencil_w<K>(od - fl, k);
+      if (p >= n) whi += stencil_w<K>(od - fl, k);
     }
     Ux += wlo * L.ulo[0] + whi * L.uhi[0];
     Uy += wlo * L.ulo[1] + whi * L.uhi[1];
@@ -229,7 +263,10 @@ __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins
 
 hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b, float* F,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_spread, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, F);
+  if (L.kernel == 4)
+    hipLaunchKernelGGL(k_spread<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, F);
+  else
+    hipLaunchKernelGGL(k_spread<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, F);
   return hipGetLastError();
 }
 
@@ -237,12 +274,16 @@ hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L,
                                 const float4* macro, float4* partial, int* flags, hipStream_t s) {
   const int64_t n = (int64_t)c.n * m.nv;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_partials, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
-                     partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_advect, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, m, L, b,
-                     partial, flags);
+  const dim3 gv((unsigned)((n + 255) / 256));
+  if (L.kernel == 4) {
+    hipLaunchKernelGGL(k_interp_partials<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
+                       partial);
+    hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
+  } else {
+    hipLaunchKernelGGL(k_interp_partials<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
+                       partial);
+    hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
+  }
   return hipGetLastError();
 }
 

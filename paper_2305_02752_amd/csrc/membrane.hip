@@ -11,15 +11,15 @@
 // plus a pole traction +-F/32 on the 32 rest-frame x-extreme vertices.
 // Non-linear arguments are clamped to +-0.99 of their poles.
 //
-// Layout of the work in the wave:
+// Work in the wave, element-parallel with no per-vertex table walks:
 //  1. the cell's vertex offsets are staged in LDS;
-//  2. per triangle: float32 normal into LDS, and the cell area and volume
-//     accumulated in float64 (volume is a sum of 1280 signed terms whose
-//     relative change of 1e-4..1e-2 drives F_volume) with a fixed-order
-//     wave reduction;
-//  3. per hinge: dihedral angle and bending magnitude into LDS;
-//  4. per vertex: deterministic gather of link, area, volume and bending
-//     terms over the vertex's own adjacency lists -- no atomics.
+//  2. per triangle: cell area and volume accumulated in float64 (the volume
+//     is a sum of 1280 signed terms whose relative change of 1e-4..1e-2
+//     drives F_volume) and reduced across the wave in a fixed order;
+//  3. per triangle, edge and hinge: force contributions to its vertices
+//     added to a per-vertex LDS accumulator in 2^-40 fixed point -- integer
+//     addition is associative, so the forces are bitwise reproducible;
+//  4. per vertex: accumulator + traction written out.
 #include "common.h"
 
 namespace hc {
@@ -47,25 +47,28 @@ __device__ inline float nonlin(float s, float lim) {
   return s + s / (lim * lim - s * s);
 }
 
+__device__ inline void add_force(long long* acc, int v, f3 f) {
+  fix_add3(&acc[3 * v], &acc[3 * v + 1], &acc[3 * v + 2], f.x * kFixScaleF, f.y * kFixScaleF,
+           f.z * kFixScaleF);
+}
+
 __global__ __launch_bounds__(64) void k_membrane(Cells C, Mesh M) {
-  extern __shared__ float lds[];
-  float* sp = lds;                 // [nv][3] positions (cell-local offsets)
-  float* sN = sp + 3 * M.nv;       // [nt][3] unnormalised triangle normals
-  float* sm = sN + 3 * M.nt;       // [nh]    bending magnitude -k_b g_b(d)
+  extern __shared__ long long lds64[];
+  long long* acc = lds64;                                   // [nv][3] fixed-point forces
+  float* sp = reinterpret_cast<float*>(lds64 + 3 * M.nv);   // [nv][3] positions
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   const float* off = C.off + (int64_t)c * M.nv * 3;
-  for (int i = lane; i < 3 * M.nv; i += kWave) sp[i] = off[i];
+  for (int i = lane; i < 3 * M.nv; i += kWave) {
+    sp[i] = off[i];
+    acc[i] = 0;
+  }
   __syncthreads();
 
+  // cell area and volume, float64 accumulation of float32 positions
   double A = 0.0, V = 0.0;
   for (int t = lane; t < M.nt; t += kWave) {
-    const int a = M.tri[3 * t], b = M.tri[3 * t + 1], d = M.tri[3 * t + 2];
-    const f3 xa = ld3(sp, a), xb = ld3(sp, b), xc = ld3(sp, d);
-    const f3 n = cross(xb - xa, xc - xa);
-    sN[3 * t] = n.x;
-    sN[3 * t + 1] = n.y;
-    sN[3 * t + 2] = n.z;
+    const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
     const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
     const double cx = xc.x, cy = xc.y, cz = xc.z;
     const double ux = bx - ax, uy = by - ay, uz = bz - az, vx = cx - ax, vy = cy - ay, vz = cz - az;
@@ -82,68 +85,64 @@ __global__ __launch_bounds__(64) void k_membrane(Cells C, Mesh M) {
     C.volume[c] = V;
   }
   const float kl = C.k[4 * c + 0], kb = C.k[4 * c + 1], ka = C.k[4 * c + 2], kv = C.k[4 * c + 3];
-  const float ca = -ka * (float)((A - M.A0) / M.A0);        // force = ca * dA/dx
-  const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // force = cv * 6 dV/dx
-  __syncthreads();
+  const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
+  const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
 
+  // area and volume: for triangle (v, j, k), dA/dx_v = n_hat x (x_k - x_j) / 2
+  // and 6 dV/dx_v = x_j x x_k (cell-local coordinates)
+  for (int t = lane; t < M.nt; t += kWave) {
+    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+    const f3 xa = ld3(sp, ia), xb = ld3(sp, ib), xc = ld3(sp, ic);
+    const f3 n = cross(xb - xa, xc - xa);
+    const float h = 0.5f * ca * rsqrtf(dot(n, n));
+    add_force(acc, ia, h * cross(n, xc - xb) + cv * cross(xb, xc));
+    add_force(acc, ib, h * cross(n, xa - xc) + cv * cross(xc, xa));
+    add_force(acc, ic, h * cross(n, xb - xa) + cv * cross(xa, xb));
+  }
+  // links
+  for (int e = lane; e < M.ne; e += kWave) {
+    const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
+    const f3 d = ld3(sp, j) - ld3(sp, i);
+    const float L = sqrtf(dot(d, d));
+    const float L0 = M.L0[e];
+    const f3 f = (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
+    add_force(acc, i, f);
+    add_force(acc, j, -1.f * f);
+  }
+  // bending hinges (i, j, k, l): edge i->j in (i, j, k), j->i in (j, i, l)
   for (int h = lane; h < M.nh; h += kWave) {
     const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
-    const f3 n1 = ld3(sN, M.hinge_t[2 * h]), n2 = ld3(sN, M.hinge_t[2 * h + 1]);
-    const f3 e = ld3(sp, j) - ld3(sp, i);
-    const float r1 = rsqrtf(dot(n1, n1)), r2 = rsqrtf(dot(n2, n2)), re = rsqrtf(dot(e, e));
-    const float sn = dot(cross(r1 * n1, r2 * n2), re * e);
-    const float cs = dot(r1 * n1, r2 * n2);
-    const float theta = atan2f(sn, cs);
-    sm[h] = -kb * nonlin(theta - M.theta0[h], kTauBend);
+    const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
+    const f3 xi = ld3(sp, i), xj = ld3(sp, j), xk = ld3(sp, k), xl = ld3(sp, l);
+    const f3 e = xj - xi;
+    const f3 n1 = cross(e, xk - xi);
+    const f3 n2 = cross(xi - xj, xl - xj);
+    const float n1s = dot(n1, n1), n2s = dot(n2, n2), el2 = dot(e, e);
+    const float r1 = rsqrtf(n1s), r2 = rsqrtf(n2s), re = rsqrtf(el2);
+    const float theta = atan2f(dot(cross(r1 * n1, r2 * n2), re * e), r1 * r2 * dot(n1, n2));
+    const float m = -kb * nonlin(theta - M.theta0[h], kTauBend);
+    const float el = el2 * re;
+    // d theta / d x: wings move along their face normals, edge vertices take
+    // the complementary shares so that the four gradients sum to zero
+    const f3 gk = (-el / n1s) * n1;
+    const f3 gl = (-el / n2s) * n2;
+    const float ak = dot(xk - xi, e) / el2, al = dot(xl - xi, e) / el2;
+    add_force(acc, k, m * gk);
+    add_force(acc, l, m * gl);
+    add_force(acc, i, m * ((ak - 1.f) * gk + (al - 1.f) * gl));
+    add_force(acc, j, m * ((-ak) * gk + (-al) * gl));
   }
   __syncthreads();
 
   const float* trac = C.traction ? C.traction + 3 * c : nullptr;
+  float* out = C.force + (int64_t)c * M.nv * 3;
   for (int v = lane; v < M.nv; v += kWave) {
-    const f3 xv = ld3(sp, v);
-    f3 F = {0.f, 0.f, 0.f};
-    for (int q = M.vlink_ptr[v]; q < M.vlink_ptr[v + 1]; ++q) {
-      const f3 d = ld3(sp, M.vlink_j[q]) - xv;
-      const float L = sqrtf(dot(d, d));
-      const float L0 = M.vlink_L0[q];
-      F = F + (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
-    }
-    for (int q = M.vtri_ptr[v]; q < M.vtri_ptr[v + 1]; ++q) {
-      const int t = M.vtri[3 * q], j = M.vtri[3 * q + 1], k = M.vtri[3 * q + 2];
-      const f3 xj = ld3(sp, j), xk = ld3(sp, k), n = ld3(sN, t);
-      const float rn = rsqrtf(dot(n, n));
-      F = F + (0.5f * ca * rn) * cross(n, xk - xj);
-      F = F + cv * cross(xj, xk);
-    }
-    for (int q = M.vhinge_ptr[v]; q < M.vhinge_ptr[v + 1]; ++q) {
-      const int h = M.vhinge[q] >> 2, role = M.vhinge[q] & 3;
-      const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
-      const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
-      const f3 xi = ld3(sp, i), e = ld3(sp, j) - xi;
-      const f3 n1 = ld3(sN, M.hinge_t[2 * h]), n2 = ld3(sN, M.hinge_t[2 * h + 1]);
-      const float el2 = dot(e, e), el = sqrtf(el2);
-      const f3 gk = (-el / dot(n1, n1)) * n1;
-      const f3 gl = (-el / dot(n2, n2)) * n2;
-      f3 g;
-      if (role == 2) {
-        g = gk;
-      } else if (role == 3) {
-        g = gl;
-      } else {
-        const float ak = dot(ld3(sp, k) - xi, e) / el2;
-        const float al = dot(ld3(sp, l) - xi, e) / el2;
-        g = role == 0 ? (-(1.f - ak)) * gk + (-(1.f - al)) * gl : (-ak) * gk + (-al) * gl;
-      }
-      F = F + sm[h] * g;
-    }
-    if (trac) {
-      const float p = M.pole[v] * M.inv_npole;
-      F = F + p * f3{trac[0], trac[1], trac[2]};
-    }
-    float* out = C.force + ((int64_t)c * M.nv + v) * 3;
-    out[0] = F.x;
-    out[1] = F.y;
-    out[2] = F.z;
+    f3 F = {(float)((double)acc[3 * v] * kFixInv), (float)((double)acc[3 * v + 1] * kFixInv),
+            (float)((double)acc[3 * v + 2] * kFixInv)};
+    if (trac) F = F + (M.pole[v] * M.inv_npole) * f3{trac[0], trac[1], trac[2]};
+    out[3 * v] = F.x;
+    out[3 * v + 1] = F.y;
+    out[3 * v + 2] = F.z;
   }
 }
 
@@ -151,7 +150,7 @@ __global__ __launch_bounds__(64) void k_membrane(Cells C, Mesh M) {
 
 hipError_t launch_membrane(const Cells& c, const Mesh& m, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
-  const size_t lds = (size_t)(3 * m.nv + 3 * m.nt + m.nh) * sizeof(float);
+  const size_t lds = (size_t)m.nv * 3 * (sizeof(long long) + sizeof(float));
   hipLaunchKernelGGL(k_membrane, dim3(c.n), dim3(kWave), lds, s, c, m);
   return hipGetLastError();
 }
