@@ -195,6 +195,55 @@ hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* hip_str
 /* Steps taken since hc_set_cells / restore. */
 hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: n_boxes independent boxes, one cell each, advanced together
+ * by ONE persistent kernel launch per hc_batch_run (replayed from a captured
+ * hipGraph).  This is the calibration use of the model (Sec. 2.3 fits the
+ * membrane parameters to single-cell stretching and shearing experiments):
+ * every box may have its own size, boundaries, tau, stiffness and traction.
+ * Each box is stepped exactly as hc_step steps a single lattice.
+ *
+ * Work split: every box owns a group of work-groups, sized in proportion to
+ * its node count and kept on one XCD; tiles are full x rows by ty x tz rows.
+ * hc_batch_set_tiling / hc_batch_autotune choose ty, tz and the work-group
+ * size (256, 512 or 1024).  The grid never exceeds the resident capacity
+ * reported by the occupancy API; group barriers spin with a bound, and a
+ * timed-out barrier aborts the whole launch and surfaces at hc_batch_sync as
+ * HC_ERR_DEVICE.  All boxes must use the same ibm_kernel.
+ * Layouts per box: as for a single lattice.  Cell arrays are per box:
+ * origin [B][3], offsets [B][V][3], k [B][4], traction [B][3] (or NULL).
+ * ------------------------------------------------------------------------- */
+typedef struct hc_batch hc_batch;
+hc_status hc_batch_create(int32_t n_boxes, const hc_lattice_desc* boxes, const hc_mesh_desc* mesh,
+                          hc_batch** out);
+void hc_batch_destroy(hc_batch* b);
+const char* hc_batch_last_error(const hc_batch* b);
+hc_status hc_batch_set_stream(hc_batch* b, void* hip_stream);
+hc_status hc_batch_query_workspace(const hc_batch* b, size_t* bytes);
+/* Populations start at rest (f = w) when the workspace is bound. */
+hc_status hc_batch_bind_workspace(hc_batch* b, void* dev_ptr, size_t bytes);
+hc_status hc_batch_set_cells(hc_batch* b, const int32_t* origin, const float* offsets,
+                             const float* k, const float* traction);
+hc_status hc_batch_set_tiling(hc_batch* b, int32_t ty, int32_t tz, int32_t block);
+hc_status hc_batch_get_tiling(const hc_batch* b, int32_t* ty, int32_t* tz, int32_t* block,
+                              int32_t* grid);
+/* Time every candidate tiling for trial_steps steps (the state is saved and
+ * restored around each trial), keep the fastest and append it to the text
+ * file cache_path (NULL: no cache) keyed by architecture and batch shape; a
+ * cached entry is applied without timing. */
+hc_status hc_batch_autotune(hc_batch* b, const char* cache_path, int32_t trial_steps, int32_t* ty,
+                            int32_t* tz, int32_t* block);
+/* Enqueue n_steps steps of every box: one kernel launch (graph replay). */
+hc_status hc_batch_run(hc_batch* b, int32_t n_steps);
+hc_status hc_batch_sync(hc_batch* b);
+hc_status hc_batch_box_steps(hc_batch* b, int32_t box, int64_t* steps);
+hc_status hc_batch_read_populations(hc_batch* b, int32_t box, float* host, int64_t count);
+hc_status hc_batch_write_populations(hc_batch* b, int32_t box, const float* host, int64_t count);
+/* Any pointer may be NULL; offsets/force/vel are [V][3] of the box's cell. */
+hc_status hc_batch_read_vertices(hc_batch* b, int32_t box, int32_t* origin, float* offsets,
+                                 float* force, float* vel);
+hc_status hc_batch_launches(const hc_batch* b, int64_t* graph_launches);
+
 #ifdef __cplusplus
 }
 #endif

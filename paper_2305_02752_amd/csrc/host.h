@@ -1,0 +1,26 @@
+// Host-side helpers shared by the single-lattice and batched C ABI layers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/hemo.h"
+#include "common.h"
+
+namespace hc {
+
+constexpr int kNPole = 32;   // vertices per traction pole
+
+struct HostMesh {
+  int nv = 0, nt = 0, ne = 0, nh = 0;
+  std::vector<int> tri, edge, hinge_v;
+  std::vector<float> L0, theta0, pole;
+  double A0 = 0, V0 = 0;
+};
+
+// Validate a closed, consistently oriented mesh and derive the rest state
+// (edge lengths, dihedral angles, area, volume, traction poles) in float64.
+// Returns an empty string on success, else the reason.
+std::string build_mesh(const hc_mesh_desc* d, HostMesh& m);
+
+}  // namespace hc

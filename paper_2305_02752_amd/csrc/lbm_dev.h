@@ -1,0 +1,86 @@
+// D3Q19 BGK collision with Guo forcing for one node, shared by the
+// single-lattice and batched kernels (Sec. 2.2: LBGK update, moments,
+// second-order equilibrium; forcing after Guo, Zheng & Shi 2002).
+//
+// Populations are shifted, g_i = f_i - w_i.  Returns the post-collision
+// shifted values, the density and the velocity (which carries half the
+// force).
+#pragma once
+
+#include "common.h"
+
+namespace hc {
+namespace lbm {
+
+__device__ constexpr int cx[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int cy[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int cz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__device__ constexpr float wq[kQ] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18,
+                                     1.f / 18, 1.f / 18, 1.f / 36, 1.f / 36, 1.f / 36,
+                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
+                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+__device__ constexpr int opp[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+// g: shifted populations in, post-collision shifted populations out.
+__device__ inline void collide(float (&g)[kQ], float fx, float fy, float fz, float omega,
+                               float& rho, float& ux, float& uy, float& uz) {
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    drho += g[i];
+    jx += cx[i] * g[i];
+    jy += cy[i] * g[i];
+    jz += cz[i] * g[i];
+  }
+  rho = 1.f + drho;
+  const float inv = 1.f / rho;
+  ux = (jx + 0.5f * fx) * inv;
+  uy = (jy + 0.5f * fy) * inv;
+  uz = (jz + 0.5f * fz) * inv;
+  const float src = 1.f - 0.5f * omega;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * fx + uy * fy + uz * fz;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float eu = cx[i] * ux + cy[i] * uy + cz[i] * uz;
+    const float eF = cx[i] * fx + cy[i] * fy + cz[i] * fz;
+    const float geq = wq[i] * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+    g[i] = g[i] - omega * (g[i] - geq) + src * wq[i] * (3.f * (eF - uF) + 9.f * eu * eF);
+  }
+}
+
+// Where population i leaving node (x, y, z) lands.  Periodic axes wrap; on
+// the wall axis a population leaving the fluid returns to its own node in
+// the opposite direction (half-way bounce-back), and *dw receives Ladd's
+// moving-wall correction -6 w_i rho (e_i . u_wall) to add to it.
+// Returns the destination population index; *dst the destination node.
+struct Walls {
+  int axis;                 // -1: none
+  float lo[3], hi[3];       // lower / upper wall velocity
+};
+
+__device__ inline int stream_target(int i, int x, int y, int z, int nx, int ny, int nz,
+                                    const Walls& W, float rho, int64_t* dst, float* dw) {
+  const int wall_axis = W.axis;
+  int xt = x + cx[i], yt = y + cy[i], zt = z + cz[i];
+  int crossed = 0;  // 0 none, 1 lower wall, 2 upper wall
+  if (wall_axis == 0 && cx[i] != 0) crossed = xt < 0 ? 1 : (xt >= nx ? 2 : 0);
+  if (wall_axis == 1 && cy[i] != 0) crossed = yt < 0 ? 1 : (yt >= ny ? 2 : 0);
+  if (wall_axis == 2 && cz[i] != 0) crossed = zt < 0 ? 1 : (zt >= nz ? 2 : 0);
+  if (crossed) {
+    const float uw = crossed == 1 ? cx[i] * W.lo[0] + cy[i] * W.lo[1] + cz[i] * W.lo[2]
+                                  : cx[i] * W.hi[0] + cy[i] * W.hi[1] + cz[i] * W.hi[2];
+    *dw = -6.f * wq[i] * rho * uw;
+    *dst = ((int64_t)z * ny + y) * nx + x;
+    return opp[i];
+  }
+  xt = xt < 0 ? xt + nx : (xt >= nx ? xt - nx : xt);
+  yt = yt < 0 ? yt + ny : (yt >= ny ? yt - ny : yt);
+  zt = zt < 0 ? zt + nz : (zt >= nz ? zt - nz : zt);
+  *dw = 0.f;
+  *dst = ((int64_t)zt * ny + yt) * nx + xt;
+  return i;
+}
+
+}  // namespace lbm
+}  // namespace hc

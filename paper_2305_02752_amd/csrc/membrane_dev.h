@@ -1,0 +1,162 @@
+// Membrane constitutive forces, one wavefront per cell (Sec. 2.3:
+// F_total = F_link + F_bend + F_area + F_volume, linear at small and strongly
+// non-linear at large deformation, relative to the stress-free rest shape).
+//
+// Forms (the paper defers them to a reference it does not reproduce; these
+// are minus the gradients of the energies below):
+//   link   k_l L0 [s^2/2 - ln(1 - s^2/3^2)/2],          s = (L - L0)/L0
+//   bend   k_b [d^2/2 - ln(1 - d^2/(pi/6)^2)/2],         d = theta - theta0
+//   area   k_a A0 a^2/2,  a = (A - A0)/A0  (cell area)
+//   volume k_v V0 v^2/2,  v = (V - V0)/V0  (cell volume)
+// plus a pole traction +-F/32 on the 32 rest-frame x-extreme vertices.
+// Non-linear arguments are clamped to +-0.99 of their poles.
+//
+// Work per cell, element-parallel with no per-vertex table walks:
+//  1. the cell's vertex offsets are staged in LDS;
+//  2. per triangle: cell area and volume accumulated in float64 (the volume
+//     is a sum of 1280 signed terms whose relative change of 1e-4..1e-2
+//     drives F_volume) and reduced across threads in a fixed order;
+//  3. per triangle, edge and hinge: force contributions to its vertices
+//     added to a per-vertex LDS accumulator in 2^-40 fixed point -- integer
+//     addition is associative, so the forces are bitwise reproducible;
+//  4. per vertex: accumulator + traction written out.
+#pragma once
+
+#include "common.h"
+
+namespace hc {
+namespace mem {
+
+constexpr float kTauLink = 3.0f;
+constexpr float kTauBend = 0.52359877559829887f;  // pi / 6
+constexpr float kClamp = 0.99f;
+
+struct f3 {
+  float x, y, z;
+};
+__device__ inline f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ inline f3 ld3(const float* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+
+__device__ inline float nonlin(float s, float lim) {
+  const float m = kClamp * lim;
+  s = fminf(fmaxf(s, -m), m);
+  return s + s / (lim * lim - s * s);
+}
+
+__device__ inline void add_force(long long* acc, int v, f3 f) {
+  fix_add3(&acc[3 * v], &acc[3 * v + 1], &acc[3 * v + 2], f.x * kFixScaleF, f.y * kFixScaleF,
+           f.z * kFixScaleF);
+}
+
+// Forces on one cell with `nthr` cooperating threads (thread `tid`).
+// acc: LDS [nv][3] int64, sp: LDS [nv][3] float, red: LDS [2 * nthr / 64]
+// double.  Writes area/volume (float64) and the per-vertex forces.
+__device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ off,
+                                     const float* __restrict__ k4, const float* trac,
+                                     float* __restrict__ out, double* area, double* volume,
+                                     long long* acc, float* sp, double* red, int tid, int nthr) {
+  for (int i = tid; i < 3 * M.nv; i += nthr) {
+    sp[i] = off[i];
+    acc[i] = 0;
+  }
+  __syncthreads();
+
+  // cell area and volume, float64 accumulation of float32 positions
+  double A = 0.0, V = 0.0;
+  for (int t = tid; t < M.nt; t += nthr) {
+    const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
+    const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
+    const double cx = xc.x, cy = xc.y, cz = xc.z;
+    const double ux = bx - ax, uy = by - ay, uz = bz - az, vx = cx - ax, vy = cy - ay, vz = cz - az;
+    const double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+    A += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+    V += (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx)) / 6.0;
+  }
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    A += __shfl_xor(A, m);
+    V += __shfl_xor(V, m);
+  }
+  const int nw = nthr / kWave;
+  if ((tid & (kWave - 1)) == 0) {
+    red[tid / kWave] = A;
+    red[nw + tid / kWave] = V;
+  }
+  __syncthreads();
+  A = 0.0;
+  V = 0.0;
+  for (int w = 0; w < nw; ++w) {   // fixed order: reproducible sums
+    A += red[w];
+    V += red[nw + w];
+  }
+  if (tid == 0) {
+    *area = A;
+    *volume = V;
+  }
+  const float kl = k4[0], kb = k4[1], ka = k4[2], kv = k4[3];
+  const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
+  const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
+
+  // area and volume: for triangle (v, j, k), dA/dx_v = n_hat x (x_k - x_j) / 2
+  // and 6 dV/dx_v = x_j x x_k (cell-local coordinates)
+  for (int t = tid; t < M.nt; t += nthr) {
+    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+    const f3 xa = ld3(sp, ia), xb = ld3(sp, ib), xc = ld3(sp, ic);
+    const f3 n = cross(xb - xa, xc - xa);
+    const float h = 0.5f * ca * rsqrtf(dot(n, n));
+    add_force(acc, ia, h * cross(n, xc - xb) + cv * cross(xb, xc));
+    add_force(acc, ib, h * cross(n, xa - xc) + cv * cross(xc, xa));
+    add_force(acc, ic, h * cross(n, xb - xa) + cv * cross(xa, xb));
+  }
+  // links
+  for (int e = tid; e < M.ne; e += nthr) {
+    const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
+    const f3 d = ld3(sp, j) - ld3(sp, i);
+    const float L = sqrtf(dot(d, d));
+    const float L0 = M.L0[e];
+    const f3 f = (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
+    add_force(acc, i, f);
+    add_force(acc, j, -1.f * f);
+  }
+  // bending hinges (i, j, k, l): edge i->j in (i, j, k), j->i in (j, i, l)
+  for (int h = tid; h < M.nh; h += nthr) {
+    const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
+    const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
+    const f3 xi = ld3(sp, i), xj = ld3(sp, j), xk = ld3(sp, k), xl = ld3(sp, l);
+    const f3 e = xj - xi;
+    const f3 n1 = cross(e, xk - xi);
+    const f3 n2 = cross(xi - xj, xl - xj);
+    const float n1s = dot(n1, n1), n2s = dot(n2, n2), el2 = dot(e, e);
+    const float r1 = rsqrtf(n1s), r2 = rsqrtf(n2s), re = rsqrtf(el2);
+    const float theta = atan2f(dot(cross(r1 * n1, r2 * n2), re * e), r1 * r2 * dot(n1, n2));
+    const float m = -kb * nonlin(theta - M.theta0[h], kTauBend);
+    const float el = el2 * re;
+    // d theta / d x: wings move along their face normals, edge vertices take
+    // the complementary shares so that the four gradients sum to zero
+    const f3 gk = (-el / n1s) * n1;
+    const f3 gl = (-el / n2s) * n2;
+    const float ak = dot(xk - xi, e) / el2, al = dot(xl - xi, e) / el2;
+    add_force(acc, k, m * gk);
+    add_force(acc, l, m * gl);
+    add_force(acc, i, m * ((ak - 1.f) * gk + (al - 1.f) * gl));
+    add_force(acc, j, m * ((-ak) * gk + (-al) * gl));
+  }
+  __syncthreads();
+
+  for (int v = tid; v < M.nv; v += nthr) {
+    f3 F = {(float)((double)acc[3 * v] * kFixInv), (float)((double)acc[3 * v + 1] * kFixInv),
+            (float)((double)acc[3 * v + 2] * kFixInv)};
+    if (trac) F = F + (M.pole[v] * M.inv_npole) * f3{trac[0], trac[1], trac[2]};
+    out[3 * v] = F.x;
+    out[3 * v + 1] = F.y;
+    out[3 * v + 2] = F.z;
+  }
+}
+
+}  // namespace mem
+}  // namespace hc

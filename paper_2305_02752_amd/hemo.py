@@ -281,3 +281,142 @@ def device_copy(dst, src, nbytes: int, stream_handle: int):
     rc = lib.hc_device_copy(C.c_void_p(dst), C.c_void_p(src), int(nbytes), C.c_void_p(stream_handle))
     if rc:
         raise HemoError(rc, lib.hc_last_error(None).decode())
+
+
+def _declare_batch(lib):
+    i32, i64, sz = C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "hc_batch_create": [i32, _P, _P, _P],
+        "hc_batch_set_stream": [_P, _P],
+        "hc_batch_query_workspace": [_P, _P],
+        "hc_batch_bind_workspace": [_P, _P, sz],
+        "hc_batch_set_cells": [_P, _P, _P, _P, _P],
+        "hc_batch_set_tiling": [_P, i32, i32, i32],
+        "hc_batch_get_tiling": [_P, _P, _P, _P, _P],
+        "hc_batch_autotune": [_P, C.c_char_p, i32, _P, _P, _P],
+        "hc_batch_run": [_P, i32],
+        "hc_batch_sync": [_P],
+        "hc_batch_box_steps": [_P, i32, _P],
+        "hc_batch_read_populations": [_P, i32, _P, i64],
+        "hc_batch_write_populations": [_P, i32, _P, i64],
+        "hc_batch_read_vertices": [_P, i32, _P, _P, _P, _P],
+        "hc_batch_launches": [_P, _P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.hc_batch_last_error.argtypes = [_P]
+    lib.hc_batch_last_error.restype = C.c_char_p
+    lib.hc_batch_destroy.argtypes = [_P]
+    lib.hc_batch_destroy.restype = None
+
+
+class Batch:
+    """Independent single-cell boxes advanced by one persistent launch per run."""
+
+    def __init__(self, lattices, rest_pos, tri, device: str = "cuda:0"):
+        import torch
+
+        self.lib = load_library()
+        if not hasattr(self.lib, "_batch_declared"):
+            _declare_batch(self.lib)
+            self.lib._batch_declared = True
+        self.device = torch.device(device)
+        self.lats = list(lattices)
+        self.n_boxes = len(self.lats)
+        self._rest = np.ascontiguousarray(rest_pos, dtype=np.float32)
+        self._tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.nv = self._rest.shape[0]
+        descs = (LatticeDesc * self.n_boxes)(*[lattice_desc(l) for l in self.lats])
+        self._descs = descs
+        mesh = MeshDesc(self.nv, self._tri.shape[0], self._tri.ctypes.data_as(C.POINTER(C.c_int32)),
+                        self._rest.ctypes.data_as(C.POINTER(C.c_float)))
+        h = C.c_void_p()
+        rc = self.lib.hc_batch_create(self.n_boxes, C.cast(descs, C.c_void_p), C.byref(mesh), C.byref(h))
+        if rc:
+            raise HemoError(rc, self.lib.hc_batch_last_error(None).decode())
+        self.h = h
+        nbytes = C.c_size_t()
+        self._check(self.lib.hc_batch_query_workspace(self.h, C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self._ws.data_ptr() + 255) & ~255
+            self.stream = torch.cuda.current_stream(self.device)
+            self._check(self.lib.hc_batch_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)))
+            self._check(self.lib.hc_batch_bind_workspace(self.h, C.c_void_p(aligned), nbytes.value))
+
+    def _check(self, rc):
+        if rc:
+            raise HemoError(rc, self.lib.hc_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_cells(self, origin, offsets, k, traction=None):
+        origin = np.ascontiguousarray(origin, dtype=np.int32).reshape(self.n_boxes, 3)
+        offsets = np.ascontiguousarray(offsets, dtype=np.float32).reshape(self.n_boxes, self.nv, 3)
+        k = np.ascontiguousarray(k, dtype=np.float32).reshape(self.n_boxes, 4)
+        tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float32).reshape(self.n_boxes, 3)
+        self._check(self.lib.hc_batch_set_cells(self.h, _ptr(origin), _ptr(offsets), _ptr(k),
+                                                None if tr is None else _ptr(tr)))
+
+    def set_tiling(self, ty, tz, block=256):
+        self._check(self.lib.hc_batch_set_tiling(self.h, int(ty), int(tz), int(block)))
+
+    def tiling(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(self.lib.hc_batch_get_tiling(self.h, *[C.byref(x) for x in v]))
+        return {"ty": v[0].value, "tz": v[1].value, "block": v[2].value, "grid": v[3].value}
+
+    def autotune(self, cache_path=None, trial_steps=10):
+        v = [C.c_int32() for _ in range(3)]
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.hc_batch_autotune(self.h, path, int(trial_steps), *[C.byref(x) for x in v]))
+        return {"ty": v[0].value, "tz": v[1].value, "block": v[2].value}
+
+    def run(self, n):
+        self._check(self.lib.hc_batch_run(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.hc_batch_sync(self.h))
+
+    def box_steps(self, box):
+        s = C.c_int64()
+        self._check(self.lib.hc_batch_box_steps(self.h, int(box), C.byref(s)))
+        return s.value
+
+    def launches(self):
+        s = C.c_int64()
+        self._check(self.lib.hc_batch_launches(self.h, C.byref(s)))
+        return s.value
+
+    def _shape(self, box):
+        l = self.lats[box]
+        return (19, l.nz, l.ny, l.nx)
+
+    def read_populations(self, box):
+        out = np.empty(self._shape(box), dtype=np.float32)
+        self._check(self.lib.hc_batch_read_populations(self.h, int(box), _ptr(out), out.size))
+        return out
+
+    def write_populations(self, box, g):
+        g = np.ascontiguousarray(g, dtype=np.float32)
+        self._check(self.lib.hc_batch_write_populations(self.h, int(box), _ptr(g), g.size))
+
+    def read_vertices(self, box):
+        o = np.empty(3, dtype=np.int32)
+        off = np.empty((self.nv, 3), dtype=np.float32)
+        f = np.empty((self.nv, 3), dtype=np.float32)
+        vel = np.empty((self.nv, 3), dtype=np.float32)
+        self._check(self.lib.hc_batch_read_vertices(self.h, int(box), _ptr(o), _ptr(off), _ptr(f), _ptr(vel)))
+        return o, off, f, vel

@@ -1,0 +1,116 @@
+"""Batched single-cell boxes (one persistent launch) against the FP64 oracle.
+
+Every box is an independent coupled simulation; the oracle steps each box
+on its own.  Tiling only changes how nodes are grouped, and every sum that
+crosses tiles is fixed point, so different tilings must agree bitwise.
+"""
+import numpy as np
+import pytest
+
+from oracle import lattice, step
+from workloads import jitter_cells, random_shifted_populations, rbc_mesh
+from workloads.configs import Lattice, PN200_LU, log_uniform_k, place_cells, small_rotation
+
+from gpu_common import relerr
+
+pytestmark = pytest.mark.gpu
+
+SIDES = [(24, 24, 24), (17, 20, 19), (26, 18, 22), (20, 20, 20), (25, 23, 17)]
+
+
+def _boxes(seed=0, walls_box=2, kernel=4):
+    rng = np.random.default_rng(seed)
+    rest64, tri = rbc_mesh()
+    lats, cells = [], []
+    for b, (nx, ny, nz) in enumerate(SIDES):
+        tau = float(rng.uniform(0.8, 1.2))
+        if b == walls_box:
+            lat = Lattice(nx, ny, nz, bc=(0, 0, 1), tau=tau, wall_u_lo=(-0.01, 0, 0),
+                          wall_u_hi=(0.01, 0, 0), ibm_kernel=kernel)
+        else:
+            lat = Lattice(nx, ny, nz, tau=tau, body_force=(1e-5 * (b % 2), 0.0, 0.0), ibm_kernel=kernel)
+        lats.append(lat)
+        centre = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2]) + rng.uniform(-0.5, 0.5, 3)
+        R = small_rotation(rng, 8.0)
+        c = place_cells(rest64, centre[None], R[None], log_uniform_k(rng, 1),
+                        traction=[[rng.uniform(0, PN200_LU), 0.0, 0.0]])
+        cells.append(jitter_cells(rng, c, 0.04))
+    return lats, rest64.astype(np.float32), tri, cells
+
+
+def _make(lats, rest, tri, cells, tiling=None):
+    from paper_2305_02752_amd import Batch
+    bt = Batch(lats, rest, tri)
+    if tiling:
+        bt.set_tiling(*tiling)
+    bt.set_cells(np.concatenate([c.origin for c in cells]), np.concatenate([c.offsets for c in cells]),
+                 np.concatenate([c.k for c in cells]), np.concatenate([c.traction for c in cells]))
+    return bt
+
+
+@pytest.mark.parametrize("kernel", [4, 2])
+def test_batch_one_step_parity(kernel):
+    lats, rest, tri, cells = _boxes(1, kernel=kernel)
+    bt = _make(lats, rest, tri, cells)
+    rng = np.random.default_rng(5)
+    g0 = [random_shifted_populations(rng, l, 1e-3) for l in lats]
+    for b, g in enumerate(g0):
+        bt.write_populations(b, g)
+    bt.run(1)
+    bt.sync()
+    assert bt.launches() == 1
+    for b, l in enumerate(lats):
+        m = step.make_model(l, rest.astype(np.float64), tri, cells[b].k, cells[b].traction)
+        X0 = cells[b].positions64()
+        f1, X1, info = step.step(m, lattice.unshift(g0[b]), X0)
+        o, off, fv, vel = bt.read_vertices(b)
+        errs = {"g": relerr(bt.read_populations(b), lattice.shifted(f1)),
+                "Fv": relerr(fv, info["Fv"][0]), "U": relerr(vel, info["U"][0])}
+        print(b, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-5, (b, k, e)
+
+
+def test_batch_multistep_parity():
+    lats, rest, tri, cells = _boxes(2)
+    bt = _make(lats, rest, tri, cells)
+    n = 150
+    bt.run(n)
+    bt.sync()
+    for b, l in enumerate(lats):
+        assert bt.box_steps(b) == n
+        m = step.make_model(l, rest.astype(np.float64), tri, cells[b].k, cells[b].traction)
+        X0 = cells[b].positions64()
+        f, X = step.run(m, lattice.init_equilibrium(l.shape), X0, n)
+        o, off, _, _ = bt.read_vertices(b)
+        e_g = relerr(bt.read_populations(b), lattice.shifted(f))
+        e_x = relerr(o[None, :] + off.astype(np.float64) - X0[0], X[0] - X0[0])
+        print(b, e_g, e_x, flush=True)
+        assert e_g <= 1e-3 and e_x <= 1e-3
+
+
+def test_batch_tilings_agree_bitwise_and_autotune_preserves_state(tmp_path):
+    lats, rest, tri, cells = _boxes(3)
+    outs = []
+    for tiling in [(2, 2, 256), (8, 8, 512), (4, 2, 1024)]:
+        bt = _make(lats, rest, tri, cells, tiling)
+        bt.run(7)
+        bt.run(5)
+        bt.sync()
+        outs.append([(bt.read_populations(b), bt.read_vertices(b)[1]) for b in range(len(lats))])
+        bt.close()
+    for o in outs[1:]:
+        for b in range(len(lats)):
+            assert np.array_equal(o[b][0], outs[0][b][0]) and np.array_equal(o[b][1], outs[0][b][1])
+    bt = _make(lats, rest, tri, cells)
+    bt.run(12)
+    bt.sync()
+    before = [bt.read_populations(b) for b in range(len(lats))]
+    choice = bt.autotune(tmp_path / "tune.txt", trial_steps=3)
+    assert choice["ty"] >= 1 and choice["block"] in (256, 512)
+    after = [bt.read_populations(b) for b in range(len(lats))]
+    for b in range(len(lats)):
+        assert np.array_equal(before[b], after[b])
+        assert np.array_equal(after[b], outs[0][b][0])
+    again = bt.autotune(tmp_path / "tune.txt", trial_steps=3)   # served from the cache
+    assert again == choice
