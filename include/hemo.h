@@ -195,6 +195,34 @@ hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* hip_str
 /* Steps taken since hc_set_cells / restore. */
 hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
 
+/* Replace the stiffnesses k [C][4] (NULL: keep) and the relaxation time. */
+hc_status hc_set_params(hc_ctx* ctx, const float* k, float tau);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint form.  The membrane parameters are fitted to single-cell
+ * stretching and shearing measurements (Sec. 2.3); these calls give the
+ * exact gradient of a cell-shape loss with respect to the stiffnesses and
+ * the relaxation time by a hand-written reverse sweep of the coupled step.
+ *
+ * Loss per cell c after n steps: (D_A - D_A*)^2 + (D_T - D_T*)^2 with
+ * D_A = max x - min x and D_T = max y - min y over its vertices.
+ * hc_adj_forward runs n steps from the current state (checkpointing every
+ * ckpt_every steps) and returns the loss; the context then holds the final
+ * state, as after hc_step(n).  hc_adj_backward recomputes one segment at a
+ * time from its checkpoint, keeping every state, and sweeps it backwards.
+ * grad [C][5] = dL_c/d(k_link, k_bend, k_area, k_volume) of cell c, and in
+ * column 4 dL/dtau, where L is the sum of all cells' losses (tau is shared
+ * by the lattice).  Needs the 4-point kernel.  The adjoint workspace is
+ * separate from the main one and sized by hc_adj_query_workspace.
+ * ------------------------------------------------------------------------- */
+hc_status hc_adj_query_workspace(const hc_ctx* ctx, int32_t n_steps, int32_t ckpt_every,
+                                 size_t* bytes);
+hc_status hc_adj_bind_workspace(hc_ctx* ctx, void* dev_ptr, size_t bytes, int32_t n_steps,
+                                int32_t ckpt_every);
+/* targets [C][2] = (D_A*, D_T*); loss [C] float64. */
+hc_status hc_adj_forward(hc_ctx* ctx, const double* targets, double* loss);
+hc_status hc_adj_backward(hc_ctx* ctx, double* grad);
+
 /* ---------------------------------------------------------------------------
  * Batched form: n_boxes independent boxes, one cell each, advanced together
  * by ONE persistent kernel launch per hc_batch_run (replayed from a captured

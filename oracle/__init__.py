@@ -23,4 +23,4 @@ step (uniform translation).  Parity unpinned: agreement of the membrane force
 forms with the paper's own implementation, whose formulas are in a reference
 that is not reproduced in the paper.
 """
-from . import lattice, ibm, membrane, binning, step  # noqa: F401
+from . import lattice, ibm, membrane, binning, step, adjoint  # noqa: F401

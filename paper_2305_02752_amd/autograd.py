@@ -1,0 +1,65 @@
+"""torch.autograd wrapper of the adjoint form.
+
+CoupledStepFn.apply(params, runner) returns the per-box losses of a batch of
+independent single-cell boxes after n coupled steps; its backward returns
+dL/dparams from the library's hand-written reverse sweep (checkpointed
+recomputation), not from torch autograd.  params is a [B, 5] float64 tensor
+of (k_link, k_bend, k_area, k_volume, tau) per box.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .hemo import Simulation
+
+
+class AdjointBoxes:
+    """One Simulation per box, each on its own stream, with a fixed initial
+    state that every forward evaluation restarts from."""
+
+    def __init__(self, lattices, rest_pos, tri, cells, targets, n_steps, ckpt_every, device="cuda:0"):
+        self.n_steps, self.ckpt_every = int(n_steps), int(ckpt_every)
+        self.targets = np.asarray(targets, dtype=np.float64).reshape(len(lattices), 2)
+        self.sims, self.streams, self.start = [], [], []
+        for b, lat in enumerate(lattices):
+            s = torch.cuda.Stream(device=device)
+            with torch.cuda.stream(s):
+                sim = Simulation(lat, rest_pos, tri, max_cells=1, device=device)
+                c = cells[b]
+                sim.set_cells(c.origin, c.offsets, c.k, c.traction)
+                sim.init_equilibrium()
+                sim.adj_bind(self.n_steps, self.ckpt_every)
+                self.start.append(sim.checkpoint_save())
+            self.sims.append(sim)
+            self.streams.append(s)
+
+    def forward(self, params: np.ndarray) -> np.ndarray:
+        loss = np.empty(len(self.sims))
+        for b, sim in enumerate(self.sims):
+            with torch.cuda.stream(self.streams[b]):
+                sim.checkpoint_restore(self.start[b])
+                sim.set_params(k=params[b, :4], tau=params[b, 4])
+                loss[b] = sim.adj_forward(self.targets[b])[0]
+        return loss
+
+    def backward(self) -> np.ndarray:
+        g = np.empty((len(self.sims), 5))
+        for b, sim in enumerate(self.sims):
+            with torch.cuda.stream(self.streams[b]):
+                g[b] = sim.adj_backward()[0]
+        return g
+
+
+class CoupledStepFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, runner: AdjointBoxes):
+        loss = runner.forward(params.detach().cpu().numpy().astype(np.float64))
+        ctx.runner = runner
+        return torch.as_tensor(loss, dtype=params.dtype, device=params.device)
+
+    @staticmethod
+    def backward(ctx, grad_loss: torch.Tensor):
+        g = ctx.runner.backward()
+        gl = grad_loss.detach().cpu().numpy()[:, None]
+        return torch.as_tensor(gl * g, dtype=grad_loss.dtype, device=grad_loss.device), None

@@ -1,0 +1,434 @@
+// Hand-written reverse mode of the coupled step (cotangent "lam" of every
+// state variable), used to differentiate a cell-shape loss with respect to
+// the membrane stiffnesses and the relaxation time.
+//
+// One forward step n maps (f^n, X^n) to (f^{n+1}, X^{n+1}) through
+//   F_v = Fmem(X; k) + T                      (Sec. 2.3 force sum)
+//   F(x) = g + sum_v F_v delta(x - X_v)       (Sec. 2.3 spreading)
+//   rho, u = moments(f, F)                    (Sec. 2.2, half force in u)
+//   U_v = sum_x u(x) delta(x - X_v)           (Sec. 2.3 interpolation)
+//   f* = f - omega (f - f_eq) + (1 - omega/2) S(u, F);  f^{n+1} = stream(f*)
+//   X^{n+1} = X^n + U                          (Sec. 2.6 Euler)
+// Its transpose, given lam_f^{n+1} and lam_X^{n+1}, is evaluated by:
+//   spread of lam_U = lam_X^{n+1}        -> lam_u(x)        (k_spread, reused)
+//   k_adj_collide: pull lam* from the streamed positions, then the
+//     collision VJP -> lam_f^n, lam_F(x), and d/d omega partial sums;
+//   k_adj_vertex: lam_{F_v} = sum_x lam_F(x) delta, plus the kernel-gradient
+//     terms sum_x (lam_U.u(x) + F_v.lam_F(x)) grad delta for lam_X;
+//   k_adj_membrane: lam_X += (dF_v/dX) lam_{F_v} by forward-mode duals (the
+//     force is minus an energy gradient, so its Jacobian is symmetric), and
+//     dL/dk_j += sum_v lam_{F_v} . F_v^(j) / k_j per force term.
+// The IBM kernel must be the 4-point phi4 (C^1); the linear hat has no
+// derivative at the nodes.
+#include "common.h"
+#include "lbm_dev.h"
+#include "membrane_dev.h"
+
+namespace hc {
+namespace {
+
+using lbm::cx;
+using lbm::cy;
+using lbm::cz;
+using lbm::opp;
+using lbm::wq;
+
+__device__ inline float phi4(float r) {
+  r = fabsf(r);
+  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
+  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
+  return 0.f;
+}
+
+// d phi4 / dr.
+__device__ inline float dphi4(float r) {
+  const float a = fabsf(r), s = r < 0.f ? -1.f : 1.f;
+  if (a <= 1.f) return s * 0.25f * (-1.f + (1.f - 2.f * a) / sqrtf(1.f + 4.f * a - 4.f * a * a));
+  if (a < 2.f) return s * 0.25f * (-1.f - (3.f - 2.f * a) / sqrtf(-7.f + 12.f * a - 4.f * a * a));
+  return 0.f;
+}
+
+__device__ inline int wrap(int p, int n) {
+  p %= n;
+  return p < 0 ? p + n : p;
+}
+
+__global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ lam1,
+                                                     float* __restrict__ lam0,
+                                                     const float* __restrict__ g0,
+                                                     const float* __restrict__ F,
+                                                     const float* __restrict__ lamu,
+                                                     float* __restrict__ lamF,
+                                                     double* __restrict__ domega_part, Lattice L) {
+  __shared__ double red[4];
+  const int64_t N = L.n;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dom = 0.0;
+  if (s < N) {
+    const int x = (int)(s % L.nx);
+    const int64_t r = s / L.nx;
+    const int y = (int)(r % L.ny), z = (int)(r / L.ny);
+    // cotangent of the post-collision values, pulled from where streaming put them
+    float ls[kQ];
+    float lrho = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      int xt = x + cx[i], yt = y + cy[i], zt = z + cz[i];
+      int crossed = 0;
+      if (L.wall_axis == 0 && cx[i] != 0) crossed = xt < 0 ? 1 : (xt >= L.nx ? 2 : 0);
+      if (L.wall_axis == 1 && cy[i] != 0) crossed = yt < 0 ? 1 : (yt >= L.ny ? 2 : 0);
+      if (L.wall_axis == 2 && cz[i] != 0) crossed = zt < 0 ? 1 : (zt >= L.nz ? 2 : 0);
+      if (crossed) {
+        ls[i] = lam1[opp[i] * N + s];
+        const float uw = crossed == 1 ? cx[i] * L.ulo[0] + cy[i] * L.ulo[1] + cz[i] * L.ulo[2]
+                                      : cx[i] * L.uhi[0] + cy[i] * L.uhi[1] + cz[i] * L.uhi[2];
+        lrho += -6.f * wq[i] * uw * ls[i];   // moving-wall term depends on rho(x)
+      } else {
+        xt = xt < 0 ? xt + L.nx : (xt >= L.nx ? xt - L.nx : xt);
+        yt = yt < 0 ? yt + L.ny : (yt >= L.ny ? yt - L.ny : yt);
+        zt = zt < 0 ? zt + L.nz : (zt >= L.nz ? zt - L.nz : zt);
+        ls[i] = lam1[i * N + ((int64_t)zt * L.ny + yt) * L.nx + xt];
+      }
+    }
+    float g[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) g[i] = g0[i * N + s];
+    const float fx = F[s], fy = F[N + s], fz = F[2 * N + s];
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      drho += g[i];
+      jx += cx[i] * g[i];
+      jy += cy[i] * g[i];
+      jz += cz[i] * g[i];
+    }
+    const float rho = 1.f + drho, inv = 1.f / rho;
+    const float ux = (jx + 0.5f * fx) * inv, uy = (jy + 0.5f * fy) * inv, uz = (jz + 0.5f * fz) * inv;
+    const float om = L.omega, src = 1.f - 0.5f * om;
+    const float uu = ux * ux + uy * uy + uz * uz, uF = ux * fx + uy * fy + uz * fz;
+    float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
+#pragma unroll
+    for (int j = 0; j < kQ; ++j) {
+      const float eu = cx[j] * ux + cy[j] * uy + cz[j] * uz;
+      const float eF = cx[j] * fx + cy[j] * fy + cz[j] * fz;
+      const float phi = 1.f + 3.f * eu + 4.5f * eu * eu - 1.5f * uu;
+      A += ls[j] * wq[j] * phi;                       // d f_eq / d rho at fixed u
+      const float cu = om * wq[j] * rho, cs = src * wq[j];
+      // omega d f_eq/du + (1 - omega/2) dS/du
+      Bx += ls[j] * (cu * (3.f * cx[j] + 9.f * eu * cx[j] - 3.f * ux) + cs * (-3.f * fx + 9.f * eF * cx[j]));
+      By += ls[j] * (cu * (3.f * cy[j] + 9.f * eu * cy[j] - 3.f * uy) + cs * (-3.f * fy + 9.f * eF * cy[j]));
+      Bz += ls[j] * (cu * (3.f * cz[j] + 9.f * eu * cz[j] - 3.f * uz) + cs * (-3.f * fz + 9.f * eF * cz[j]));
+      // (1 - omega/2) dS/dF at fixed u
+      Gx += ls[j] * cs * (3.f * (cx[j] - ux) + 9.f * eu * cx[j]);
+      Gy += ls[j] * cs * (3.f * (cy[j] - uy) + 9.f * eu * cy[j]);
+      Gz += ls[j] * cs * (3.f * (cz[j] - uz) + 9.f * eu * cz[j]);
+      const float geq = wq[j] * (drho + rho * (phi - 1.f));
+      const float S = wq[j] * (3.f * (eF - uF) + 9.f * eu * eF);
+      dom += (double)(ls[j] * (-(g[j] - geq) - 0.5f * S));
+    }
+    A = om * A + lrho;
+    Bx += lamu[s];
+    By += lamu[N + s];
+    Bz += lamu[2 * N + s];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      lam0[i * N + s] = (1.f - om) * ls[i] + A +
+                        (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
+    lamF[s] = Gx + 0.5f * Bx * inv;
+    lamF[N + s] = Gy + 0.5f * By * inv;
+    lamF[2 * N + s] = Gz + 0.5f * Bz * inv;
+  }
+  for (int m = kWave / 2; m > 0; m >>= 1) dom += __shfl_xor(dom, m);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = dom;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+    domega_part[blockIdx.x] += t;   // each block owns its slot across steps
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
+                                                    const float* __restrict__ lamX1,
+                                                    const float4* __restrict__ macro,
+                                                    const float* __restrict__ lamF,
+                                                    float* __restrict__ lamFv,
+                                                    float* __restrict__ lamX0) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (int64_t)C.n * M.nv) return;
+  const int c = (int)(v / M.nv);
+  const int64_t N = L.n;
+  const int n3[3] = {L.nx, L.ny, L.nz};
+  int base[3];
+  float w[3][4], dw[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float x = C.off[v * 3 + d];
+    const float fl = floorf(x);
+    base[d] = C.origin[3 * c + d] + (int)fl - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[d][k] = phi4(x - fl + 1.f - (float)k);
+      dw[d][k] = dphi4(x - fl + 1.f - (float)k);
+    }
+  }
+  const float lux = lamX1[3 * v], luy = lamX1[3 * v + 1], luz = lamX1[3 * v + 2];
+  const float Fx = C.force[3 * v], Fy = C.force[3 * v + 1], Fz = C.force[3 * v + 2];
+  float sFx = 0.f, sFy = 0.f, sFz = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+  for (int kz = 0; kz < 4; ++kz) {
+    int pz = base[2] + kz, side = 0;
+    if (L.bc[2] == 1) side |= pz < 0 ? 1 : (pz >= n3[2] ? 2 : 0); else pz = wrap(pz, n3[2]);
+    for (int ky = 0; ky < 4; ++ky) {
+      int py = base[1] + ky, sy = 0;
+      if (L.bc[1] == 1) sy = py < 0 ? 1 : (py >= n3[1] ? 2 : 0); else py = wrap(py, n3[1]);
+      for (int kx = 0; kx < 4; ++kx) {
+        int px = base[0] + kx, sx = 0;
+        if (L.bc[0] == 1) sx = px < 0 ? 1 : (px >= n3[0] ? 2 : 0); else px = wrap(px, n3[0]);
+        const int sd = side | sy | sx;
+        float ux, uy, uz, lFx = 0.f, lFy = 0.f, lFz = 0.f;
+        if (sd == 1) {
+          ux = L.ulo[0]; uy = L.ulo[1]; uz = L.ulo[2];
+        } else if (sd == 2) {
+          ux = L.uhi[0]; uy = L.uhi[1]; uz = L.uhi[2];
+        } else {
+          const int64_t s = ((int64_t)pz * L.ny + py) * L.nx + px;
+          const float4 q = macro[s];
+          ux = q.x; uy = q.y; uz = q.z;
+          lFx = lamF[s]; lFy = lamF[N + s]; lFz = lamF[2 * N + s];
+        }
+        const float W = w[0][kx] * w[1][ky] * w[2][kz];
+        sFx += W * lFx;
+        sFy += W * lFy;
+        sFz += W * lFz;
+        const float a = lux * ux + luy * uy + luz * uz + Fx * lFx + Fy * lFy + Fz * lFz;
+        gx += a * dw[0][kx] * w[1][ky] * w[2][kz];
+        gy += a * w[0][kx] * dw[1][ky] * w[2][kz];
+        gz += a * w[0][kx] * w[1][ky] * dw[2][kz];
+      }
+    }
+  }
+  lamFv[3 * v] = sFx;
+  lamFv[3 * v + 1] = sFy;
+  lamFv[3 * v + 2] = sFz;
+  lamX0[3 * v] = lux + gx;
+  lamX0[3 * v + 1] = luy + gy;
+  lamX0[3 * v + 2] = luz + gz;
+}
+
+__device__ inline V3<Dual> ldd(const float* p, const float* t, int i) {
+  return {{p[3 * i], t[3 * i]}, {p[3 * i + 1], t[3 * i + 1]}, {p[3 * i + 2], t[3 * i + 2]}};
+}
+__device__ inline void add_tangent(long long* acc, int v, V3<Dual> f) {
+  fix_add3(&acc[3 * v], &acc[3 * v + 1], &acc[3 * v + 2], f.x.d * kFixScaleF, f.y.d * kFixScaleF,
+           f.z.d * kFixScaleF);
+}
+__device__ inline double dotv(V3<Dual> f, const float* lam, int v) {
+  return (double)f.x.v * lam[3 * v] + (double)f.y.v * lam[3 * v + 1] + (double)f.z.v * lam[3 * v + 2];
+}
+__device__ inline double dotf(mem::f3 f, const float* lam, int v) {
+  return (double)f.x * lam[3 * v] + (double)f.y * lam[3 * v + 1] + (double)f.z * lam[3 * v + 2];
+}
+
+// One wave per cell.  LDS: positions, tangents (= lam_{F_v}), int64
+// accumulator of the Jacobian-vector product.
+__global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const float* __restrict__ lamFv,
+                                                     float* __restrict__ lamX, double* __restrict__ dk) {
+  extern __shared__ long long lds64[];
+  long long* acc = lds64;
+  float* sp = reinterpret_cast<float*>(lds64 + 3 * M.nv);
+  float* st = sp + 3 * M.nv;
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t b3 = (int64_t)c * M.nv * 3;
+  for (int i = tid; i < 3 * M.nv; i += kWave) {
+    sp[i] = C.off[b3 + i];
+    st[i] = lamFv[b3 + i];
+    acc[i] = 0;
+  }
+  __syncthreads();
+  // area and volume with their directional derivatives (float64)
+  double A = 0, V = 0, dA = 0, dV = 0;
+  for (int t = tid; t < M.nt; t += kWave) {
+    const int a = M.tri[3 * t], b = M.tri[3 * t + 1], e = M.tri[3 * t + 2];
+    double x[3][3], dx[3][3];
+    for (int d = 0; d < 3; ++d) {
+      x[0][d] = sp[3 * a + d]; x[1][d] = sp[3 * b + d]; x[2][d] = sp[3 * e + d];
+      dx[0][d] = st[3 * a + d]; dx[1][d] = st[3 * b + d]; dx[2][d] = st[3 * e + d];
+    }
+    double u[3], w[3], du[3], dw2[3];
+    for (int d = 0; d < 3; ++d) {
+      u[d] = x[1][d] - x[0][d];
+      w[d] = x[2][d] - x[0][d];
+      du[d] = dx[1][d] - dx[0][d];
+      dw2[d] = dx[2][d] - dx[0][d];
+    }
+    const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const double dn[3] = {du[1] * w[2] - du[2] * w[1] + u[1] * dw2[2] - u[2] * dw2[1],
+                          du[2] * w[0] - du[0] * w[2] + u[2] * dw2[0] - u[0] * dw2[2],
+                          du[0] * w[1] - du[1] * w[0] + u[0] * dw2[1] - u[1] * dw2[0]};
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    A += 0.5 * nn;
+    dA += 0.5 * (n[0] * dn[0] + n[1] * dn[1] + n[2] * dn[2]) / nn;
+    // V term: x0 . (x1 x x2) / 6 and its derivative
+    auto trip = [](const double* p, const double* q, const double* r) {
+      return p[0] * (q[1] * r[2] - q[2] * r[1]) + p[1] * (q[2] * r[0] - q[0] * r[2]) +
+             p[2] * (q[0] * r[1] - q[1] * r[0]);
+    };
+    V += trip(x[0], x[1], x[2]) / 6.0;
+    dV += (trip(dx[0], x[1], x[2]) + trip(x[0], dx[1], x[2]) + trip(x[0], x[1], dx[2])) / 6.0;
+  }
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    A += __shfl_xor(A, m);
+    V += __shfl_xor(V, m);
+    dA += __shfl_xor(dA, m);
+    dV += __shfl_xor(dV, m);
+  }
+  const float kl = C.k[4 * c], kb = C.k[4 * c + 1], ka = C.k[4 * c + 2], kv = C.k[4 * c + 3];
+  const float a_rel = (float)((A - M.A0) / M.A0), v_rel = (float)((V - M.V0) / M.V0);
+  const Dual ca = {-ka * a_rel, -ka * (float)(dA / M.A0)};
+  const Dual cv = {-kv * v_rel / 6.f, -kv * (float)(dV / M.V0) / 6.f};
+  double sl = 0, sb = 0, sa = 0, sv = 0;   // sum_v lam_{F_v} . F_v^(term) / k_term
+  for (int t = tid; t < M.nt; t += kWave) {
+    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+    V3<Dual> fa, fb, fc;
+    mem::tri_forces<Dual>(ldd(sp, st, ia), ldd(sp, st, ib), ldd(sp, st, ic), ca, cv, fa, fb, fc);
+    add_tangent(acc, ia, fa);
+    add_tangent(acc, ib, fb);
+    add_tangent(acc, ic, fc);
+    mem::f3 pa, pb, pc;
+    mem::tri_forces<float>(mem::ld3(sp, ia), mem::ld3(sp, ib), mem::ld3(sp, ic), -a_rel, 0.f, pa, pb, pc);
+    sa += dotf(pa, st, ia) + dotf(pb, st, ib) + dotf(pc, st, ic);
+    mem::tri_forces<float>(mem::ld3(sp, ia), mem::ld3(sp, ib), mem::ld3(sp, ic), 0.f, -v_rel / 6.f, pa,
+                           pb, pc);
+    sv += dotf(pa, st, ia) + dotf(pb, st, ib) + dotf(pc, st, ic);
+  }
+  for (int e = tid; e < M.ne; e += kWave) {
+    const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
+    const V3<Dual> f = mem::link_force<Dual>(ldd(sp, st, i), ldd(sp, st, j), M.L0[e], kl);
+    add_tangent(acc, i, f);
+    add_tangent(acc, j, -1.f * f);
+    sl += (dotv(f, st, i) - dotv(f, st, j)) / kl;
+  }
+  for (int h = tid; h < M.nh; h += kWave) {
+    const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
+    const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
+    V3<Dual> fi, fj, fk, fl;
+    mem::hinge_forces<Dual>(ldd(sp, st, i), ldd(sp, st, j), ldd(sp, st, k), ldd(sp, st, l), M.theta0[h],
+                            kb, fi, fj, fk, fl);
+    add_tangent(acc, i, fi);
+    add_tangent(acc, j, fj);
+    add_tangent(acc, k, fk);
+    add_tangent(acc, l, fl);
+    sb += (dotv(fi, st, i) + dotv(fj, st, j) + dotv(fk, st, k) + dotv(fl, st, l)) / kb;
+  }
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    sl += __shfl_xor(sl, m);
+    sb += __shfl_xor(sb, m);
+    sa += __shfl_xor(sa, m);
+    sv += __shfl_xor(sv, m);
+  }
+  if (tid == 0) {
+    dk[4 * c] += sl;
+    dk[4 * c + 1] += sb;
+    dk[4 * c + 2] += sa;
+    dk[4 * c + 3] += sv;
+  }
+  __syncthreads();
+  for (int i = tid; i < 3 * M.nv; i += kWave) lamX[b3 + i] += (float)((double)acc[i] * kFixInv);
+}
+
+// Loss (D_A - D_A*)^2 + (D_T - D_T*)^2 of every cell from its extents along
+// x and y, and the seed cotangent lam_X = dL/dX (extreme vertices only;
+// ties go to the lower vertex index).  One wave per cell.
+__global__ __launch_bounds__(64) void k_loss_seed(Cells C, Mesh M, const double* __restrict__ targets,
+                                                  double* __restrict__ loss, float* __restrict__ lamX) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t b = (int64_t)c * M.nv;
+  double mx[2] = {-1e300, -1e300}, mn[2] = {1e300, 1e300};
+  int imx[2] = {0, 0}, imn[2] = {0, 0};
+  for (int v = tid; v < M.nv; v += kWave) {
+    for (int d = 0; d < 2; ++d) {
+      const double x = (double)C.origin[3 * c + d] + (double)C.off[(b + v) * 3 + d];
+      if (x > mx[d]) { mx[d] = x; imx[d] = v; }
+      if (x < mn[d]) { mn[d] = x; imn[d] = v; }
+    }
+  }
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    for (int d = 0; d < 2; ++d) {
+      const double omx = __shfl_xor(mx[d], m), omn = __shfl_xor(mn[d], m);
+      const int oimx = __shfl_xor(imx[d], m), oimn = __shfl_xor(imn[d], m);
+      if (omx > mx[d] || (omx == mx[d] && oimx < imx[d])) { mx[d] = omx; imx[d] = oimx; }
+      if (omn < mn[d] || (omn == mn[d] && oimn < imn[d])) { mn[d] = omn; imn[d] = oimn; }
+    }
+  }
+  for (int i = tid; i < 3 * M.nv; i += kWave) lamX[b * 3 + i] = 0.f;
+  __syncthreads();
+  if (tid == 0) {
+    const double ea = (mx[0] - mn[0]) - targets[2 * c], et = (mx[1] - mn[1]) - targets[2 * c + 1];
+    loss[c] = ea * ea + et * et;
+    lamX[(b + imx[0]) * 3 + 0] += (float)(2.0 * ea);
+    lamX[(b + imn[0]) * 3 + 0] -= (float)(2.0 * ea);
+    lamX[(b + imx[1]) * 3 + 1] += (float)(2.0 * et);
+    lamX[(b + imn[1]) * 3 + 1] -= (float)(2.0 * et);
+  }
+}
+
+__global__ void k_sum_parts(const double* __restrict__ parts, int n, double* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += parts[i];   // fixed order
+    *out = t;
+  }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
+                              const float* lamu, float* lamF, double* domega_part, const Lattice& L,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, lam1, lam0,
+                     g0, F, lamu, lamF, domega_part, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_vertex(const Cells& c, const Mesh& m, const Lattice& L, const float* lamX1,
+                             const float4* macro, const float* lamF, float* lamFv, float* lamX0,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)c.n * m.nv;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_vertex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, m, L, lamX1,
+                     macro, lamF, lamFv, lamX0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_membrane(const Cells& c, const Mesh& m, const float* lamFv, float* lamX, double* dk,
+                               hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  const size_t lds = (size_t)m.nv * 3 * (8 + 4 + 4);
+  hipLaunchKernelGGL(k_adj_membrane, dim3(c.n), dim3(kWave), lds, s, c, m, lamFv, lamX, dk);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_seed(const Cells& c, const Mesh& m, const double* targets, double* loss,
+                            float* lamX, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loss_seed, dim3(c.n), dim3(kWave), 0, s, c, m, targets, loss, lamX);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, parts, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace hc

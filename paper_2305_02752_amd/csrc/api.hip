@@ -62,6 +62,16 @@ struct hc_ctx {
   std::vector<std::pair<int, int>> ev_pairs[HC_NUM_KERNELS];
   size_t ev_next = 0;
   std::string err;
+  // reverse mode: checkpoints, one recomputed segment, cotangents
+  char* adj_ws = nullptr;
+  int adj_n = 0, adj_ck = 0, adj_nseg = 0;
+  bool adj_ready = false;
+  float *ck_pops = nullptr, *ck_off = nullptr;
+  float *sg_pops = nullptr, *sg_off = nullptr, *sg_F = nullptr, *sg_Fv = nullptr;
+  float4* sg_macro = nullptr;
+  float *lam_f[2] = {nullptr, nullptr}, *lam_X[2] = {nullptr, nullptr};
+  float *lam_Fv = nullptr, *lam_u = nullptr, *lam_F = nullptr, *vel_scratch = nullptr;
+  double *dom_part = nullptr, *dk = nullptr, *loss = nullptr, *targets = nullptr, *scal = nullptr;
   // workspace offsets
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
@@ -171,6 +181,11 @@ hc_status timed(hc_ctx* c, int kernel, const char* what, Fn fn) {
   return HC_OK;
 }
 
+hc_status copy_d2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return HC_OK;
+  return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "d2d copy");
+}
+
 hc_status one_step(hc_ctx* c) {
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
@@ -190,6 +205,88 @@ hc_status one_step(hc_ctx* c) {
                }));
   c->cur ^= 1;
   c->step += 1;
+  return HC_OK;
+}
+
+struct AdjPlan {
+  size_t total = 0;
+  size_t ck_pops, ck_off, sg_pops, sg_off, sg_F, sg_macro, sg_Fv, lf0, lf1, lx0, lx1, lfv, lu, lF, vel,
+      dom, dk, loss, tg, scal;
+};
+
+AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
+  AdjPlan p;
+  Layout L;
+  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->max_cells * c->hm.nv * 3;
+  const int64_t nck = (n + ck - 1) / ck, C = c->max_cells;
+  p.ck_pops = L.add(nck * P * 4);
+  p.ck_off = L.add(nck * X * 4);
+  p.sg_pops = L.add((ck + 1) * P * 4);
+  p.sg_off = L.add((ck + 1) * X * 4);
+  p.sg_F = L.add(ck * 3 * N * 4);
+  p.sg_macro = L.add(ck * N * 16);
+  p.sg_Fv = L.add(ck * X * 4);
+  p.lf0 = L.add(P * 4);
+  p.lf1 = L.add(P * 4);
+  p.lx0 = L.add(X * 4);
+  p.lx1 = L.add(X * 4);
+  p.lfv = L.add(X * 4);
+  p.lu = L.add(3 * N * 4);
+  p.lF = L.add(3 * N * 4);
+  p.vel = L.add(X * 4);
+  p.dom = L.add(((N + 255) / 256) * 8);
+  p.dk = L.add(C * 4 * 8);
+  p.loss = L.add(C * 8);
+  p.tg = L.add(C * 2 * 8);
+  p.scal = L.add(64);
+  p.total = L.total;
+  return p;
+}
+
+// One forward step of the recomputed segment, from slot i to slot i + 1,
+// keeping everything the reverse sweep reads.
+hc_status adj_forward_into(hc_ctx* c, int i) {
+  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  Cells Ci = c->C;
+  Ci.off = c->sg_off + i * X;
+  Ci.force = c->sg_Fv + i * X;
+  Ci.vel = c->vel_scratch;
+  float* Fi = c->sg_F + i * 3 * N;
+  float4* Mi = c->sg_macro + i * N;
+  HC_TRY(check(c, launch_membrane(Ci, c->M, c->stream), "membrane"));
+  HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
+  HC_TRY(check(c, launch_spread(Ci, c->M, c->L, c->B, Fi, c->stream), "spread"));
+  HC_TRY(check(c, launch_collide_stream(c->sg_pops + i * P, c->sg_pops + (i + 1) * P, Fi, Mi, c->L,
+                                        c->stream),
+               "collide"));
+  Cells Cn = Ci;
+  Cn.off = c->sg_off + (i + 1) * X;
+  HC_TRY(copy_d2d(c, Cn.off, Ci.off, (size_t)X * 4));
+  HC_TRY(check(c, launch_interp_advect(Cn, c->M, c->L, c->B, Mi, c->partial, c->B.flags, c->stream),
+               "interp"));
+  return HC_OK;
+}
+
+// Reverse of step i of the segment: (lam_f, lam_X)^{i+1} -> (lam_f, lam_X)^i.
+hc_status adj_reverse_step(hc_ctx* c, int i, int a) {
+  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  Cells Ci = c->C;
+  Ci.off = c->sg_off + i * X;
+  Ci.force = c->sg_Fv + i * X;
+  Ci.vel = c->vel_scratch;
+  float* lf1 = c->lam_f[a];
+  float* lf0 = c->lam_f[a ^ 1];
+  float* lx1 = c->lam_X[a];
+  float* lx0 = c->lam_X[a ^ 1];
+  HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
+  HC_TRY(check(c, launch_spread_vec(Ci, c->M, c->L, c->B, lx1, 0.f, c->lam_u, c->stream), "spread"));
+  HC_TRY(check(c, launch_adj_collide(lf1, lf0, c->sg_pops + i * P, c->sg_F + i * 3 * N, c->lam_u,
+                                     c->lam_F, c->dom_part, c->L, c->stream),
+               "adjoint collide"));
+  HC_TRY(check(c, launch_adj_vertex(Ci, c->M, c->L, lx1, c->sg_macro + i * N, c->lam_F, c->lam_Fv, lx0,
+                                    c->stream),
+               "adjoint ibm"));
+  HC_TRY(check(c, launch_adj_membrane(Ci, c->M, c->lam_Fv, lx0, c->dk, c->stream), "adjoint membrane"));
   return HC_OK;
 }
 
@@ -602,6 +699,114 @@ hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* stream)
     return fail(nullptr, HC_ERR_ARG, "copy: null or misaligned pointer / size");
   hipError_t e = launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(nullptr, HC_ERR_DEVICE, hipGetErrorString(e));
+  return HC_OK;
+}
+
+hc_status hc_set_params(hc_ctx* c, const float* k, float tau) {
+  HC_TRY(need_ws(c));
+  if (!(tau > 0.5f)) return fail(c, HC_ERR_ARG, "tau must exceed 1/2");
+  if (k) HC_TRY(copy_h2d(c, (void*)c->C.k, k, (size_t)c->C.n * 16));
+  c->L.tau = tau;
+  c->L.omega = 1.0f / tau;
+  return sync(c, "set params");
+}
+
+hc_status hc_adj_query_workspace(const hc_ctx* c, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
+  if (!c || !bytes || n_steps < 1 || ckpt_every < 1) return HC_ERR_ARG;
+  *bytes = adj_plan(c, n_steps, std::min(ckpt_every, n_steps)).total;
+  return HC_OK;
+}
+
+hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_steps,
+                                int32_t ckpt_every) {
+  HC_TRY(need_ws(c));
+  if (!dev || n_steps < 1 || ckpt_every < 1) return fail(c, HC_ERR_ARG, "adjoint: bad arguments");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(c, HC_ERR_ARG, "workspace not 256-aligned");
+  if (c->L.kernel != HC_PHI4)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
+  const int ck = std::min(ckpt_every, n_steps);
+  const AdjPlan p = adj_plan(c, n_steps, ck);
+  if (bytes < p.total) return fail(c, HC_ERR_OOM, "adjoint workspace too small");
+  char* w = static_cast<char*>(dev);
+  c->adj_ws = w;
+  c->adj_n = n_steps;
+  c->adj_ck = ck;
+  c->adj_nseg = (n_steps + ck - 1) / ck;
+  c->ck_pops = reinterpret_cast<float*>(w + p.ck_pops);
+  c->ck_off = reinterpret_cast<float*>(w + p.ck_off);
+  c->sg_pops = reinterpret_cast<float*>(w + p.sg_pops);
+  c->sg_off = reinterpret_cast<float*>(w + p.sg_off);
+  c->sg_F = reinterpret_cast<float*>(w + p.sg_F);
+  c->sg_macro = reinterpret_cast<float4*>(w + p.sg_macro);
+  c->sg_Fv = reinterpret_cast<float*>(w + p.sg_Fv);
+  c->lam_f[0] = reinterpret_cast<float*>(w + p.lf0);
+  c->lam_f[1] = reinterpret_cast<float*>(w + p.lf1);
+  c->lam_X[0] = reinterpret_cast<float*>(w + p.lx0);
+  c->lam_X[1] = reinterpret_cast<float*>(w + p.lx1);
+  c->lam_Fv = reinterpret_cast<float*>(w + p.lfv);
+  c->lam_u = reinterpret_cast<float*>(w + p.lu);
+  c->lam_F = reinterpret_cast<float*>(w + p.lF);
+  c->vel_scratch = reinterpret_cast<float*>(w + p.vel);
+  c->dom_part = reinterpret_cast<double*>(w + p.dom);
+  c->dk = reinterpret_cast<double*>(w + p.dk);
+  c->loss = reinterpret_cast<double*>(w + p.loss);
+  c->targets = reinterpret_cast<double*>(w + p.tg);
+  c->scal = reinterpret_cast<double*>(w + p.scal);
+  c->adj_ready = false;
+  return HC_OK;
+}
+
+hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
+  HC_TRY(need_ws(c));
+  if (!c->adj_ws) return fail(c, HC_ERR_STATE, "no adjoint workspace bound");
+  if (!c->have_cells || !targets || !loss) return fail(c, HC_ERR_STATE, "adjoint: no cells or targets");
+  const int64_t P = 19 * c->L.n, X = (int64_t)c->C.n * c->hm.nv * 3;
+  HC_TRY(copy_h2d(c, c->targets, targets, (size_t)c->C.n * 16));
+  for (int s = 0; s < c->adj_n; ++s) {
+    if (s % c->adj_ck == 0) {
+      const int k = s / c->adj_ck;
+      HC_TRY(copy_d2d(c, c->ck_pops + k * P, c->pops[c->cur], (size_t)P * 4));
+      HC_TRY(copy_d2d(c, c->ck_off + k * X, c->C.off, (size_t)X * 4));
+    }
+    HC_TRY(one_step(c));
+  }
+  HC_TRY(check(c, launch_loss_seed(c->C, c->M, c->targets, c->loss, c->lam_X[0], c->stream), "loss"));
+  HC_TRY(copy_d2h(c, loss, c->loss, (size_t)c->C.n * 8));
+  HC_TRY(sync(c, "adjoint forward"));
+  c->adj_ready = true;
+  return HC_OK;
+}
+
+hc_status hc_adj_backward(hc_ctx* c, double* grad) {
+  HC_TRY(need_ws(c));
+  if (!c->adj_ready || !grad) return fail(c, HC_ERR_STATE, "hc_adj_forward must run first");
+  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  const int nblk = (int)((N + 255) / 256);
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));
+  HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));
+  HC_TRY(check(c, launch_zero_f64(c->dom_part, nblk, c->stream), "zero"));
+  int a = 0;   // lam_f[a], lam_X[a] hold the cotangents of the later state
+  for (int seg = c->adj_nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * c->adj_ck, len = std::min(c->adj_ck, c->adj_n - s0);
+    HC_TRY(copy_d2d(c, c->sg_pops, c->ck_pops + seg * P, (size_t)P * 4));
+    HC_TRY(copy_d2d(c, c->sg_off, c->ck_off + seg * X, (size_t)X * 4));
+    for (int i = 0; i < len; ++i) HC_TRY(adj_forward_into(c, i));
+    for (int i = len - 1; i >= 0; --i) {
+      HC_TRY(adj_reverse_step(c, i, a));
+      a ^= 1;
+    }
+  }
+  HC_TRY(check(c, launch_sum_parts(c->dom_part, nblk, c->scal, c->stream), "sum"));
+  std::vector<double> dk((size_t)c->C.n * 4);
+  double dom = 0.0;
+  HC_TRY(copy_d2h(c, dk.data(), c->dk, dk.size() * 8));
+  HC_TRY(copy_d2h(c, &dom, c->scal, 8));
+  HC_TRY(sync(c, "adjoint backward"));
+  const double om = c->L.omega;
+  for (int i = 0; i < c->C.n; ++i) {
+    for (int j = 0; j < 4; ++j) grad[5 * i + j] = dk[4 * i + j];
+    grad[5 * i + 4] = -om * om * dom;   // tau = 1/omega
+  }
   return HC_OK;
 }
 

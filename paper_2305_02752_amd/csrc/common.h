@@ -110,6 +110,22 @@ hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                          float* F, hipStream_t s);
+// spread an arbitrary per-vertex vector field (vec [n*nv][3]) plus body * g
+hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                             const float* vec, float body, float* F, hipStream_t s);
+// adjoint kernels
+hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
+                              const float* lamu, float* lamF, double* domega_part, const Lattice& L,
+                              hipStream_t s);
+hipError_t launch_adj_vertex(const Cells& c, const Mesh& m, const Lattice& L, const float* lamX1,
+                             const float4* macro, const float* lamF, float* lamFv, float* lamX0,
+                             hipStream_t s);
+hipError_t launch_adj_membrane(const Cells& c, const Mesh& m, const float* lamFv, float* lamX,
+                               double* dk, hipStream_t s);
+hipError_t launch_loss_seed(const Cells& c, const Mesh& m, const double* targets, double* loss,
+                            float* lamX, hipStream_t s);
+hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float4* macro,
                                  const Lattice& L, hipStream_t s);
 hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,

@@ -95,6 +95,7 @@ __device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, in
 // contributions of the stencil nodes inside the tile to the LDS accumulator.
 template <int K>
 __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
+                                                const float* __restrict__ vec, float body,
                                                 float* __restrict__ F) {
   __shared__ long long acc[3][kTile * kTile * kTile];
   const int t = blockIdx.x;
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
     const int v = B.touch[e] >> 5;
     const int c = v / M.nv;
     const float* o = C.off + (int64_t)v * 3;
-    const float* fv = C.force + (int64_t)v * 3;
+    const float* fv = vec + (int64_t)v * 3;
     const float fx = fv[0] * kFixScaleF, fy = fv[1] * kFixScaleF, fz = fv[2] * kFixScaleF;
     int lx[K], ly[K], lz[K];
     float wx[K], wy[K], wz[K];
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
     const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
     if (x >= L.nx || y >= L.ny || z >= L.nz) continue;
     const int64_t s = ((int64_t)z * L.ny + y) * L.nx + x;
-    F[s] = L.g[0] + (float)((double)acc[0][i] * kFixInv);
-    F[N + s] = L.g[1] + (float)((double)acc[1][i] * kFixInv);
-    F[2 * N + s] = L.g[2] + (float)((double)acc[2][i] * kFixInv);
+    F[s] = body * L.g[0] + (float)((double)acc[0][i] * kFixInv);
+    F[N + s] = body * L.g[1] + (float)((double)acc[1][i] * kFixInv);
+    F[2 * N + s] = body * L.g[2] + (float)((double)acc[2][i] * kFixInv);
   }
 }
 
@@ -263,10 +264,15 @@ __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins
 
 hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b, float* F,
                          hipStream_t s) {
+  return launch_spread_vec(c, m, L, b, c.force, 1.f, F, s);
+}
+
+hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                             const float* vec, float body, float* F, hipStream_t s) {
   if (L.kernel == 4)
-    hipLaunchKernelGGL(k_spread<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, F);
+    hipLaunchKernelGGL(k_spread<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
   else
-    hipLaunchKernelGGL(k_spread<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, F);
+    hipLaunchKernelGGL(k_spread<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
   return hipGetLastError();
 }
 

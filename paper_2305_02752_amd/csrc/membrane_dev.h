@@ -1,6 +1,6 @@
-// Membrane constitutive forces, one wavefront per cell (Sec. 2.3:
-// F_total = F_link + F_bend + F_area + F_volume, linear at small and strongly
-// non-linear at large deformation, relative to the stress-free rest shape).
+// Membrane constitutive forces (Sec. 2.3: F_total = F_link + F_bend +
+// F_area + F_volume, linear at small and strongly non-linear at large
+// deformation, relative to the stress-free rest shape).
 //
 // Forms (the paper defers them to a reference it does not reproduce; these
 // are minus the gradients of the energies below):
@@ -10,6 +10,9 @@
 //   volume k_v V0 v^2/2,  v = (V - V0)/V0  (cell volume)
 // plus a pole traction +-F/32 on the 32 rest-frame x-extreme vertices.
 // Non-linear arguments are clamped to +-0.99 of their poles.
+//
+// The per-element force formulas are templates over the scalar type: float
+// for the forward step, Dual for the Jacobian-vector products of the adjoint.
 //
 // Work per cell, element-parallel with no per-vertex table walks:
 //  1. the cell's vertex offsets are staged in LDS;
@@ -23,6 +26,7 @@
 #pragma once
 
 #include "common.h"
+#include "dual.h"
 
 namespace hc {
 namespace mem {
@@ -31,22 +35,64 @@ constexpr float kTauLink = 3.0f;
 constexpr float kTauBend = 0.52359877559829887f;  // pi / 6
 constexpr float kClamp = 0.99f;
 
-struct f3 {
-  float x, y, z;
-};
-__device__ inline f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ inline f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ inline f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ inline float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ inline f3 cross(f3 a, f3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
+using f3 = V3<float>;
 __device__ inline f3 ld3(const float* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
 
+// g(s) = s + s / (lim^2 - s^2), argument clamped to +-0.99 lim (constant,
+// zero derivative, beyond the clamp).
 __device__ inline float nonlin(float s, float lim) {
   const float m = kClamp * lim;
   s = fminf(fmaxf(s, -m), m);
   return s + s / (lim * lim - s * s);
+}
+__device__ inline Dual nonlin(Dual s, float lim) {
+  const float m = kClamp * lim;
+  if (s.v > m || s.v < -m) return {nonlin(s.v, lim), 0.f};
+  return s + s / (lim * lim - s * s);
+}
+
+// Link force on i (the force on j is its negative).
+template <class T>
+__device__ inline V3<T> link_force(V3<T> xi, V3<T> xj, float L0, float kl) {
+  const V3<T> d = xj - xi;
+  const T L = sqrt_(dot(d, d));
+  return (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
+}
+
+// Area and volume forces on the three vertices of triangle (a, b, c):
+// for (v, j, k), dA/dx_v = n_hat x (x_k - x_j) / 2 and 6 dV/dx_v = x_j x x_k.
+template <class T>
+__device__ inline void tri_forces(V3<T> xa, V3<T> xb, V3<T> xc, T ca, T cv, V3<T>& fa, V3<T>& fb,
+                                  V3<T>& fc) {
+  const V3<T> n = cross(xb - xa, xc - xa);
+  const T h = 0.5f * ca * rsqrt_(dot(n, n));
+  fa = h * cross(n, xc - xb) + cv * cross(xb, xc);
+  fb = h * cross(n, xa - xc) + cv * cross(xc, xa);
+  fc = h * cross(n, xb - xa) + cv * cross(xa, xb);
+}
+
+// Bending forces of hinge (i, j, k, l): edge i->j in (i, j, k), j->i in
+// (j, i, l).  theta = atan2((n1 x n2).e, n1.n2) is positive on a convex fold;
+// d theta/dx moves the wings along their face normals and gives the edge
+// vertices the complementary shares, so the four gradients sum to zero.
+template <class T>
+__device__ inline void hinge_forces(V3<T> xi, V3<T> xj, V3<T> xk, V3<T> xl, float theta0, float kb,
+                                    V3<T>& fi, V3<T>& fj, V3<T>& fk, V3<T>& fl) {
+  const V3<T> e = xj - xi;
+  const V3<T> n1 = cross(e, xk - xi);
+  const V3<T> n2 = cross(xi - xj, xl - xj);
+  const T n1s = dot(n1, n1), n2s = dot(n2, n2), el2 = dot(e, e);
+  const T r1 = rsqrt_(n1s), r2 = rsqrt_(n2s), re = rsqrt_(el2);
+  const T theta = atan2_(dot(cross(r1 * n1, r2 * n2), re * e), r1 * r2 * dot(n1, n2));
+  const T m = -kb * nonlin(theta - theta0, kTauBend);
+  const T el = el2 * re;
+  const V3<T> gk = (-el / n1s) * n1;
+  const V3<T> gl = (-el / n2s) * n2;
+  const T ak = dot(xk - xi, e) / el2, al = dot(xl - xi, e) / el2;
+  fk = m * gk;
+  fl = m * gl;
+  fi = m * ((ak - 1.f) * gk + (al - 1.f) * gl);
+  fj = m * ((-ak) * gk + (-al) * gl);
 }
 
 __device__ inline void add_force(long long* acc, int v, f3 f) {
@@ -54,21 +100,12 @@ __device__ inline void add_force(long long* acc, int v, f3 f) {
            f.z * kFixScaleF);
 }
 
-// Forces on one cell with `nthr` cooperating threads (thread `tid`).
-// acc: LDS [nv][3] int64, sp: LDS [nv][3] float, red: LDS [2 * nthr / 64]
-// double.  Writes area/volume (float64) and the per-vertex forces.
-__device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ off,
-                                     const float* __restrict__ k4, const float* trac,
-                                     float* __restrict__ out, double* area, double* volume,
-                                     long long* acc, float* sp, double* red, int tid, int nthr) {
-  for (int i = tid; i < 3 * M.nv; i += nthr) {
-    sp[i] = off[i];
-    acc[i] = 0;
-  }
-  __syncthreads();
-
-  // cell area and volume, float64 accumulation of float32 positions
-  double A = 0.0, V = 0.0;
+// Cell area and volume (float64 sums over triangles, fixed-order reduction
+// over the nthr cooperating threads; red holds 2 * nthr / 64 doubles).
+__device__ inline void area_volume(const Mesh& M, const float* sp, double* red, int tid, int nthr,
+                                   double& A, double& V) {
+  A = 0.0;
+  V = 0.0;
   for (int t = tid; t < M.nt; t += nthr) {
     const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
     const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
@@ -83,6 +120,7 @@ __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ of
     V += __shfl_xor(V, m);
   }
   const int nw = nthr / kWave;
+  __syncthreads();
   if ((tid & (kWave - 1)) == 0) {
     red[tid / kWave] = A;
     red[nw + tid / kWave] = V;
@@ -94,6 +132,22 @@ __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ of
     A += red[w];
     V += red[nw + w];
   }
+}
+
+// Forces on one cell with `nthr` cooperating threads (thread `tid`).
+// acc: LDS [nv][3] int64, sp: LDS [nv][3] float, red: LDS [2 * nthr / 64]
+// double.  Writes area/volume (float64) and the per-vertex forces.
+__device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ off,
+                                     const float* __restrict__ k4, const float* trac,
+                                     float* __restrict__ out, double* area, double* volume,
+                                     long long* acc, float* sp, double* red, int tid, int nthr) {
+  for (int i = tid; i < 3 * M.nv; i += nthr) {
+    sp[i] = off[i];
+    acc[i] = 0;
+  }
+  __syncthreads();
+  double A, V;
+  area_volume(M, sp, red, tid, nthr, A, V);
   if (tid == 0) {
     *area = A;
     *volume = V;
@@ -102,49 +156,30 @@ __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ of
   const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
   const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
 
-  // area and volume: for triangle (v, j, k), dA/dx_v = n_hat x (x_k - x_j) / 2
-  // and 6 dV/dx_v = x_j x x_k (cell-local coordinates)
   for (int t = tid; t < M.nt; t += nthr) {
     const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-    const f3 xa = ld3(sp, ia), xb = ld3(sp, ib), xc = ld3(sp, ic);
-    const f3 n = cross(xb - xa, xc - xa);
-    const float h = 0.5f * ca * rsqrtf(dot(n, n));
-    add_force(acc, ia, h * cross(n, xc - xb) + cv * cross(xb, xc));
-    add_force(acc, ib, h * cross(n, xa - xc) + cv * cross(xc, xa));
-    add_force(acc, ic, h * cross(n, xb - xa) + cv * cross(xa, xb));
+    f3 fa, fb, fc;
+    tri_forces<float>(ld3(sp, ia), ld3(sp, ib), ld3(sp, ic), ca, cv, fa, fb, fc);
+    add_force(acc, ia, fa);
+    add_force(acc, ib, fb);
+    add_force(acc, ic, fc);
   }
-  // links
   for (int e = tid; e < M.ne; e += nthr) {
     const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
-    const f3 d = ld3(sp, j) - ld3(sp, i);
-    const float L = sqrtf(dot(d, d));
-    const float L0 = M.L0[e];
-    const f3 f = (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
+    const f3 f = link_force<float>(ld3(sp, i), ld3(sp, j), M.L0[e], kl);
     add_force(acc, i, f);
     add_force(acc, j, -1.f * f);
   }
-  // bending hinges (i, j, k, l): edge i->j in (i, j, k), j->i in (j, i, l)
   for (int h = tid; h < M.nh; h += nthr) {
     const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
     const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
-    const f3 xi = ld3(sp, i), xj = ld3(sp, j), xk = ld3(sp, k), xl = ld3(sp, l);
-    const f3 e = xj - xi;
-    const f3 n1 = cross(e, xk - xi);
-    const f3 n2 = cross(xi - xj, xl - xj);
-    const float n1s = dot(n1, n1), n2s = dot(n2, n2), el2 = dot(e, e);
-    const float r1 = rsqrtf(n1s), r2 = rsqrtf(n2s), re = rsqrtf(el2);
-    const float theta = atan2f(dot(cross(r1 * n1, r2 * n2), re * e), r1 * r2 * dot(n1, n2));
-    const float m = -kb * nonlin(theta - M.theta0[h], kTauBend);
-    const float el = el2 * re;
-    // d theta / d x: wings move along their face normals, edge vertices take
-    // the complementary shares so that the four gradients sum to zero
-    const f3 gk = (-el / n1s) * n1;
-    const f3 gl = (-el / n2s) * n2;
-    const float ak = dot(xk - xi, e) / el2, al = dot(xl - xi, e) / el2;
-    add_force(acc, k, m * gk);
-    add_force(acc, l, m * gl);
-    add_force(acc, i, m * ((ak - 1.f) * gk + (al - 1.f) * gl));
-    add_force(acc, j, m * ((-ak) * gk + (-al) * gl));
+    f3 fi, fj, fk, fl;
+    hinge_forces<float>(ld3(sp, i), ld3(sp, j), ld3(sp, k), ld3(sp, l), M.theta0[h], kb, fi, fj, fk,
+                        fl);
+    add_force(acc, k, fk);
+    add_force(acc, l, fl);
+    add_force(acc, i, fi);
+    add_force(acc, j, fj);
   }
   __syncthreads();
 

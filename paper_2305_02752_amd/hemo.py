@@ -70,6 +70,11 @@ def _declare(lib):
         "hc_profile": [_P, i32],
         "hc_profile_read": [_P, _P, _P],
         "hc_device_copy": [_P, _P, sz, _P],
+        "hc_set_params": [_P, _P, C.c_float],
+        "hc_adj_query_workspace": [_P, i32, i32, _P],
+        "hc_adj_bind_workspace": [_P, _P, sz, i32, i32],
+        "hc_adj_forward": [_P, _P, _P],
+        "hc_adj_backward": [_P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -262,6 +267,35 @@ class Simulation:
         n = np.zeros(len(KERNELS), dtype=np.int64)
         self._check(self.lib.hc_profile_read(self.ctx, _ptr(ms), _ptr(n)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
+
+    def set_params(self, k=None, tau=None):
+        """Replace per-cell stiffnesses k [C,4] and/or the relaxation time."""
+        kk = None if k is None else np.ascontiguousarray(k, dtype=np.float32).reshape(self.n_cells, 4)
+        t = float(self._desc.tau if tau is None else tau)
+        self._check(self.lib.hc_set_params(self.ctx, None if kk is None else _ptr(kk), t))
+        self._desc.tau = t
+
+    def adj_bind(self, n_steps: int, ckpt_every: int):
+        """Allocate and bind the reverse-mode workspace for runs of n_steps."""
+        nb = C.c_size_t()
+        self._check(self.lib.hc_adj_query_workspace(self.ctx, int(n_steps), int(ckpt_every), C.byref(nb)))
+        with self.torch.cuda.device(self.device):
+            self._adj_ws = self.torch.empty(nb.value + 256, dtype=self.torch.uint8, device=self.device)
+        aligned = (self._adj_ws.data_ptr() + 255) & ~255
+        self._check(self.lib.hc_adj_bind_workspace(self.ctx, C.c_void_p(aligned), nb.value, int(n_steps),
+                                                   int(ckpt_every)))
+        self.adj_workspace_bytes = nb.value
+
+    def adj_forward(self, targets) -> np.ndarray:
+        t = np.ascontiguousarray(targets, dtype=np.float64).reshape(self.n_cells, 2)
+        loss = np.empty(self.n_cells, dtype=np.float64)
+        self._check(self.lib.hc_adj_forward(self.ctx, _ptr(t), _ptr(loss)))
+        return loss
+
+    def adj_backward(self) -> np.ndarray:
+        g = np.empty((self.n_cells, 5), dtype=np.float64)
+        self._check(self.lib.hc_adj_backward(self.ctx, _ptr(g)))
+        return g
 
     def checkpoint_save(self) -> bytes:
         n = C.c_size_t()

@@ -1,0 +1,84 @@
+"""Adjoint form: device reverse sweep vs FP64 central differences of the oracle.
+
+Loss: (D_A - D_A*)^2 + (D_T - D_T*)^2 of one cell after n coupled steps in a
+sheared box with a pole traction.  Parameters p = (k_link, k_bend, k_area,
+k_volume, tau).  Bar: p . dL/dp normwise within 1e-4 of the FP64
+finite-difference gradient.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from workloads import rbc_mesh
+from workloads.configs import K_REF, Lattice, place_cells, small_rotation
+
+from gpu_common import make_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def _box(seed=0, side=20, walls=True):
+    rng = np.random.default_rng(seed)
+    rest64, tri = rbc_mesh()
+    if walls:
+        lat = Lattice(side, side, side, bc=(0, 0, 1), tau=float(rng.uniform(0.8, 1.2)),
+                      wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
+    else:
+        lat = Lattice(side, side, side, tau=float(rng.uniform(0.8, 1.2)))
+    k = K_REF * 10.0 ** rng.uniform(-0.5, 0.5, 4)
+    centre = np.full(3, (side - 1) / 2.0) + rng.uniform(-0.5, 0.5, 3)
+    cells = place_cells(rest64, centre[None], small_rotation(rng, 5.0)[None], k[None],
+                        traction=[[3e-3, 0.0, 0.0]])
+    targets = np.array([16.0 * 1.2, 16.0 * 0.9])
+    return lat, rest64.astype(np.float32), tri, cells, targets
+
+
+def _device_grad(lat, rest, tri, cells, targets, n, ck):
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest, tri=tri, cells=cells), cells)
+    sim.init_equilibrium()
+    sim.adj_bind(n, ck)
+    loss = sim.adj_forward(targets)
+    g = sim.adj_backward()
+    return loss[0], g[0], sim
+
+
+@pytest.mark.parametrize("walls", [True, False])
+def test_adjoint_matches_fd(walls):
+    lat, rest, tri, cells, targets = _box(1 if walls else 2, walls=walls)
+    n = 40
+    loss, g, _ = _device_grad(lat, rest, tri, cells, targets, n, 10)
+    X0 = cells.positions64()[0]
+    k = cells.k[0].astype(np.float64)
+    L_ref, _ = oadj.run_loss(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets)
+    g_fd = oadj.fd_gradient(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets, eps=1e-4)
+    p = np.concatenate([k, [lat.tau]])
+    pg, pf = p * g, p * g_fd
+    comp = np.abs(pg - pf) / np.maximum(np.abs(pf), 1e-30)
+    norm = np.linalg.norm(pg - pf) / np.linalg.norm(pf)
+    print(f"loss {loss:.8f} vs {L_ref:.8f}; p.g {pg}; fd {pf}; comp {comp}; norm {norm:.2e}", flush=True)
+    assert abs(loss - L_ref) <= 1e-5 * abs(L_ref)
+    assert norm <= 1e-4
+
+
+def test_adjoint_checkpoint_interval_is_exact():
+    lat, rest, tri, cells, targets = _box(3)
+    _, g1, _ = _device_grad(lat, rest, tri, cells, targets, 24, 24)
+    _, g2, _ = _device_grad(lat, rest, tri, cells, targets, 24, 5)
+    assert np.array_equal(g1, g2)
+
+
+def test_coupled_step_fn_autograd():
+    import torch
+    from paper_2305_02752_amd.autograd import AdjointBoxes, CoupledStepFn
+    boxes = [_box(10 + b) for b in range(3)]
+    runner = AdjointBoxes([b[0] for b in boxes], boxes[0][1], boxes[0][2], [b[3] for b in boxes],
+                          [b[4] for b in boxes], n_steps=20, ckpt_every=5)
+    p0 = np.array([np.concatenate([b[3].k[0], [b[0].tau]]) for b in boxes])
+    params = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    loss = CoupledStepFn.apply(params, runner)
+    (loss * torch.tensor([1.0, 2.0, -0.5], dtype=torch.float64)).sum().backward()
+    for b in range(3):
+        _, g, _ = _device_grad(boxes[b][0], boxes[b][1], boxes[b][2], boxes[b][3], boxes[b][4], 20, 5)
+        w = [1.0, 2.0, -0.5][b]
+        assert np.allclose(params.grad[b].numpy(), w * g, rtol=1e-12, atol=0)
