@@ -13,8 +13,8 @@ from workloads.configs import K_REF, Lattice, place_cells
 
 def _setup():
     rest64, tri = rbc_mesh()
-    lat = Lattice(16, 16, 16, bc=(0, 0, 1), tau=0.9, wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
-    cells = place_cells(rest64, np.array([[7.6, 7.3, 7.5]]), np.eye(3)[None], K_REF[None],
+    lat = Lattice(20, 20, 20, bc=(0, 0, 1), tau=0.9, wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
+    cells = place_cells(rest64, np.array([[9.6, 9.3, 9.5]]), np.eye(3)[None], K_REF[None],
                         traction=[[3e-3, 0, 0]])
     return lat, rest64.astype(np.float32), tri, cells.positions64()[0], cells.traction[0]
 
@@ -22,9 +22,10 @@ def _setup():
 def test_fd_gradient_converged():
     lat, rest, tri, X0, tr = _setup()
     targets = (19.0, 14.0)
-    g3 = oadj.fd_gradient(lat, rest, tri, X0, K_REF, tr, lat.tau, 12, targets, eps=1e-3)
-    g4 = oadj.fd_gradient(lat, rest, tri, X0, K_REF, tr, lat.tau, 12, targets, eps=1e-4)
+    g3 = oadj.fd_gradient(lat, rest, tri, X0, K_REF, tr, lat.tau, 30, targets, eps=1e-3)
+    g4 = oadj.fd_gradient(lat, rest, tri, X0, K_REF, tr, lat.tau, 30, targets, eps=1e-4)
     p = np.concatenate([K_REF, [lat.tau]])
+    assert np.linalg.norm(p * g4) > 1e-3
     assert np.linalg.norm(p * (g3 - g4)) / np.linalg.norm(p * g4) < 1e-5
 
 
