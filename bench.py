@@ -108,6 +108,97 @@ def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def bench_batched(torch, seed: int = 3, steps: int = 2000, warmup: int = 20):
+    """Batched calibration workload: 256 single-cell boxes (sides U{24..48})
+    advanced together, one persistent launch per run, tiling autotuned."""
+    import tempfile
+
+    from paper_2305_02752_amd import Batch
+    from workloads import batched_calibration
+
+    w = batched_calibration(seed=seed)
+    cells = w.cells
+    bt = Batch(w.lattice, w.rest_pos, w.tri)
+    bt.set_cells(np.concatenate([c.origin for c in cells]), np.concatenate([c.offsets for c in cells]),
+                 np.concatenate([c.k for c in cells]), np.concatenate([c.traction for c in cells]))
+    with tempfile.TemporaryDirectory() as d:
+        choice = bt.autotune(os.path.join(d, "tiling.txt"), trial_steps=10)
+    bt.run(warmup)
+    bt.sync()
+    n0 = bt.launches()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.run(steps)
+    bt.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sites = sum(l.n_sites for l in w.lattice)
+    nv = len(cells) * w.rest_pos.shape[0]
+    return {"workload": w.name, "boxes": len(cells), "sites": sites, "vertices": nv, "steps": steps,
+            "launches": bt.launches() - n0, "ms_per_step": dt / steps * 1e3,
+            "MLUPS": sites * steps / dt / 1e6, "vertex_updates_per_s": nv * steps / dt,
+            "hbm_frac": (BYTES_PER_SITE * sites + BYTES_PER_VERTEX * nv) * steps / dt / 1e9 / PEAK_HBM_GBPS,
+            "tiling": {**choice, **bt.tiling()}}
+
+
+def bench_adjoint(torch, boxes: int = 8, seed: int = 4):
+    """Adjoint workload (48^3 sheared boxes with pole traction, 2000 steps,
+    checkpoint every 100): gradients of the cell-shape loss with respect to
+    (k_link, k_bend, k_area, k_volume, tau) for `boxes` of the 64 boxes, each
+    box on its own stream and host thread.  Reports gradient evaluations per
+    second and the cost of a gradient relative to a plain forward run."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2305_02752_amd import Simulation
+    from workloads import adjoint_boxes
+
+    w = adjoint_boxes(seed=seed)
+    n, ck = w.steps, w.extra["ckpt_every"]
+    sims, streams, starts = [], [], []
+    for b in range(boxes):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            sim = Simulation(w.lattice[b], w.rest_pos, w.tri, max_cells=1)
+            c = w.cells[b]
+            sim.set_cells(c.origin, c.offsets, c.k, c.traction)
+            sim.init_equilibrium()
+            sim.adj_bind(n, ck)
+            starts.append(sim.checkpoint_save())
+        sims.append(sim)
+        streams.append(s)
+
+    def each(fn):
+        with ThreadPoolExecutor(max_workers=boxes) as ex:
+            return list(ex.map(fn, range(boxes)))
+
+    def fwd_plain(b):
+        with torch.cuda.stream(streams[b]):
+            sims[b].checkpoint_restore(starts[b])
+            sims[b].step(n)
+            sims[b].sync()
+
+    def fwd_adj(b):
+        with torch.cuda.stream(streams[b]):
+            sims[b].checkpoint_restore(starts[b])
+            return sims[b].adj_forward(w.extra["targets"][b])[0]
+
+    def bwd(b):
+        with torch.cuda.stream(streams[b]):
+            return sims[b].adj_backward()[0]
+
+    each(fwd_plain)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter(); each(fwd_plain); torch.cuda.synchronize(); t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter(); loss = each(fwd_adj); torch.cuda.synchronize(); t_af = time.perf_counter() - t0
+    t0 = time.perf_counter(); grads = each(bwd); torch.cuda.synchronize(); t_bw = time.perf_counter() - t0
+    g = np.array(grads)
+    return {"workload": w.name, "boxes_timed": boxes, "boxes_in_workload": len(w.cells), "steps": n,
+            "ckpt_every": ck, "grads_per_s": boxes / (t_af + t_bw),
+            "t_forward_s": t_fwd, "t_adjoint_forward_s": t_af, "t_backward_s": t_bw,
+            "t_grad_over_t_forward": (t_af + t_bw) / t_fwd,
+            "finite": bool(np.all(np.isfinite(g)) and np.all(np.isfinite(loss)))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +207,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint forms")
+    ap.add_argument("--adjoint-boxes", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the coupled step has no "
@@ -177,6 +270,20 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_s * 1e3}
 
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    batched = adj = None
+    if not args.no_extra:
+        log("batched calibration form ...")
+        batched = bench_batched(torch)
+        log(f"batched: {batched['ms_per_step']:.3f} ms/step, {batched['MLUPS']:.0f} MLUPS, "
+            f"{batched['launches']} launch(es), tiling {batched['tiling']}")
+        torch.cuda.empty_cache()
+        log("adjoint form ...")
+        adj = bench_adjoint(torch, boxes=args.adjoint_boxes)
+        log(f"adjoint: {adj['grads_per_s']:.2f} gradients/s, t_grad/t_fwd {adj['t_grad_over_t_forward']:.2f}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
@@ -205,6 +312,8 @@ def main():
         "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_calibration": batched,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 
