@@ -176,11 +176,11 @@ hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
  * (index HC_K_*), the summed device time in milliseconds and the number of
  * launches since the last hc_profile call.  Arrays hold HC_NUM_KERNELS. */
 enum {
-  HC_K_MEMBRANE = 0,
-  HC_K_BINNING = 1,
-  HC_K_SPREAD = 2,
-  HC_K_COLLIDE_STREAM = 3,
-  HC_K_INTERP_ADVECT = 4,
+  HC_K_CELL = 0,            /* per-cell: pending vertex move + membrane forces + binning */
+  HC_K_SPREAD = 1,          /* IBM spread onto the force field */
+  HC_K_COLLIDE_STREAM = 2,  /* BGK collide + Guo forcing + push stream */
+  HC_K_INTERP = 3,          /* IBM interpolation, per-tile partial sums */
+  HC_K_ADVECT = 4,          /* vertex move closing the last step of an hc_step call */
   HC_NUM_KERNELS = 5
 };
 hc_status hc_profile(hc_ctx* ctx, int32_t enable);

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhemo.so")
 SOURCES = ["api.hip", "lbm.hip", "ibm.hip", "membrane.hip", "binning.hip", "batch_kernel.hip",
            "batch_api.hip", "mesh_host.hip",
-           "adjoint.hip"]
+           "adjoint.hip", "cell.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -56,6 +56,9 @@ struct hc_ctx {
       *cell_list = nullptr;
   int64_t step = 0;
   bool have_cells = false;
+  // the last step's vertex move is still to be applied (it runs fused into
+  // the next step's per-cell kernel, or in flush() before the state is seen)
+  bool advect_pending = false;
   // optional per-kernel timing with events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -186,26 +189,43 @@ hc_status copy_d2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
   return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "d2d copy");
 }
 
+// One coupled step.  The vertex move that closes the step (interpolated
+// velocity, explicit Euler) is left pending: the next step's per-cell kernel
+// applies it before the membrane forces, or flush() applies it on its own.
 hc_status one_step(hc_ctx* c) {
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
-  HC_TRY(timed(c, HC_K_MEMBRANE, "membrane", [&] { return launch_membrane(C, c->M, c->stream); }));
-  HC_TRY(timed(c, HC_K_BINNING, "binning",
-               [&] { return launch_bin_vertices(C, c->M, c->L, c->B, c->stream); }));
+  const bool adv = c->advect_pending;
+  HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
+    return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, c->stream);
+  }));
   HC_TRY(timed(c, HC_K_SPREAD, "spread",
                [&] { return launch_spread(C, c->M, c->L, c->B, c->F, c->stream); }));
   HC_TRY(timed(c, HC_K_COLLIDE_STREAM, "collide_stream", [&] {
     return launch_collide_stream(c->pops[c->cur], c->pops[c->cur ^ 1], c->F, c->macro, c->L,
                                  c->stream);
   }));
-  HC_TRY(timed(c, HC_K_INTERP_ADVECT, "interp",
-               [&] {
-                 return launch_interp_advect(C, c->M, c->L, c->B, c->macro, c->partial, c->B.flags,
-                                             c->stream);
-               }));
+  HC_TRY(timed(c, HC_K_INTERP, "interp", [&] {
+    return launch_interp_partials(C, c->M, c->L, c->B, c->macro, c->partial, c->stream);
+  }));
+  c->advect_pending = C.n > 0;
   c->cur ^= 1;
   c->step += 1;
   return HC_OK;
+}
+
+// Apply a pending vertex move, so that positions and velocities are current.
+hc_status flush(hc_ctx* c) {
+  if (!c->advect_pending) return HC_OK;
+  c->advect_pending = false;
+  return timed(c, HC_K_ADVECT, "advect", [&] {
+    return launch_advect(c->C, c->M, c->L, c->B, c->partial, c->B.flags, c->stream);
+  });
+}
+
+hc_status run_steps(hc_ctx* c, int n) {
+  for (int i = 0; i < n; ++i) HC_TRY(one_step(c));
+  return flush(c);
 }
 
 struct AdjPlan {
@@ -498,6 +518,7 @@ hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float*
   }
   c->C.n = n;
   c->have_cells = n > 0;
+  c->advect_pending = false;
   c->step = 0;
   return sync(c, "set_cells");
 }
@@ -514,8 +535,7 @@ hc_status hc_init_equilibrium(hc_ctx* c, float rho0, const float u0[3]) {
 hc_status hc_step(hc_ctx* c, int32_t n) {
   HC_TRY(need_ws(c));
   if (n < 0) return fail(c, HC_ERR_ARG, "n_steps < 0");
-  for (int i = 0; i < n; ++i) HC_TRY(one_step(c));
-  return HC_OK;
+  return run_steps(c, n);
 }
 
 hc_status hc_sync(hc_ctx* c) {
@@ -769,6 +789,7 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
       HC_TRY(copy_d2d(c, c->ck_off + k * X, c->C.off, (size_t)X * 4));
     }
     HC_TRY(one_step(c));
+    if ((s + 1) % c->adj_ck == 0 || s + 1 == c->adj_n) HC_TRY(flush(c));
   }
   HC_TRY(check(c, launch_loss_seed(c->C, c->M, c->targets, c->loss, c->lam_X[0], c->stream), "loss"));
   HC_TRY(copy_d2h(c, loss, c->loss, (size_t)c->C.n * 8));

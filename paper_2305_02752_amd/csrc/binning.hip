@@ -10,7 +10,7 @@
 // Lists are filled through per-tile counters (atomic slot reservation), so
 // their content is exact while the order inside a tile is arbitrary; the
 // read-out path sorts each tile segment.
-#include "common.h"
+#include "binning_dev.h"
 
 namespace hc {
 namespace {
@@ -20,107 +20,11 @@ __device__ inline int wrap(int p, int n) {
   return p < 0 ? p + n : p;
 }
 
-// Distinct tiles (<= 3) reached along one axis by K stencil nodes starting at p0.
-__device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
-  int cnt = 0;
-  for (int k = 0; k < K; ++k) {
-    int p = p0 + k;
-    if (wall) {
-      if (p < 0 || p >= n) continue;
-    } else {
-      p = wrap(p, n);
-    }
-    const int t = p / kTile;
-    bool seen = false;
-    for (int q = 0; q < cnt; ++q) seen = seen || out[q] == t;
-    if (!seen && cnt < 3) out[cnt++] = t;
-  }
-  return cnt;
-}
-
-// Tiles reached by the stencil of vertex v, per axis, and its owner tile.
-__device__ inline int vertex_tiles(const Cells& C, const Mesh& M, const Lattice& L, int64_t v,
-                                   int (&T)[3][3], int (&nT)[3]) {
-  const int c = (int)(v / M.nv);
-  const float* o = C.off + v * 3;
-  const int K = L.kernel;
-  const int b = K == 4 ? -1 : 0;
-  const int n[3] = {L.nx, L.ny, L.nz};
-  int own[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int p = C.origin[3 * c + d] + (int)floorf(o[d]);
-    nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
-    own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : wrap(p, n[d])) / kTile;
-  }
-  return (own[2] * L.ty + own[1]) * L.tx + own[0];
-}
-
-__device__ inline int slot_tile(const Lattice& L, const int (&T)[3][3], const int (&nT)[3], int j) {
-  const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
-  return (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
-}
-
-constexpr int kHash = 256;   // distinct tiles one cell may reach
-
-// One work-group per cell.  Every (vertex, reached tile) pair gets a local
-// rank in an LDS hash table keyed by tile; then one global atomic per
-// distinct tile reserves a contiguous block of that tile's list, and the
-// pairs are written at block base + local rank.  Tile lists have a fixed
-// capacity of B.cap entries; an overflow raises flags[1] bit 4.
 __global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
-  __shared__ int keys[kHash], count[kHash], base[kHash];
+  __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
   const int c = blockIdx.x;
-  for (int i = threadIdx.x; i < kHash; i += blockDim.x) {
-    keys[i] = -1;
-    count[i] = 0;
-  }
-  __syncthreads();
-  for (int vl = threadIdx.x; vl < M.nv; vl += blockDim.x) {
-    const int64_t v = (int64_t)c * M.nv + vl;
-    int T[3][3], nT[3];
-    B.owner[v] = vertex_tiles(C, M, L, v, T, nT);
-    int ntouch = nT[0] * nT[1] * nT[2];
-    if (ntouch > L.max_touch) {  // excluded by the per-axis bound set at create
-      atomicOr(&B.flags[1], 2);
-      ntouch = L.max_touch;
-    }
-    B.ntouch[v] = ntouch;
-    for (int j = 0; j < ntouch; ++j) {
-      const int tile = slot_tile(L, T, nT, j);
-      int h = (int)(((unsigned)tile * 2654435761u) >> 24);
-      int probe = 0;
-      for (; probe < kHash; ++probe) {
-        const int prev = atomicCAS(&keys[h], -1, tile);
-        if (prev == -1 || prev == tile) break;
-        h = (h + 1) & (kHash - 1);
-      }
-      if (probe == kHash) {
-        atomicOr(&B.flags[1], 8);
-        B.slot[v * L.max_touch + j] = -1;
-        continue;
-      }
-      B.slot[v * L.max_touch + j] = (h << 16) | atomicAdd(&count[h], 1);
-    }
-  }
-  __syncthreads();
-  for (int h = threadIdx.x; h < kHash; h += blockDim.x) {
-    if (keys[h] < 0) continue;
-    base[h] = atomicAdd(&B.touch_cnt[keys[h]], count[h]);
-    if (base[h] + count[h] > B.cap) atomicOr(&B.flags[1], 4);
-  }
-  __syncthreads();
-  for (int vl = threadIdx.x; vl < M.nv; vl += blockDim.x) {
-    const int64_t v = (int64_t)c * M.nv + vl;
-    const int ntouch = B.ntouch[v];
-    for (int j = 0; j < ntouch; ++j) {
-      const int packed = B.slot[v * L.max_touch + j];
-      if (packed < 0) continue;
-      const int h = packed >> 16;
-      const int pos = base[h] + (packed & 0xffff);
-      if (pos < B.cap) B.touch[(int64_t)keys[h] * B.cap + pos] = (int)(v * 32 + j);
-    }
-  }
+  bin::bin_cell(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, threadIdx.x,
+                blockDim.x);
 }
 
 // Copy the fixed-capacity tile lists into CSR form (read-out path).

@@ -1,0 +1,121 @@
+// Device helpers of the vertex/cell binning to 8^3 tiles, shared by the
+// binning kernels and the fused per-cell kernel.
+#pragma once
+
+#include "common.h"
+
+namespace hc {
+namespace bin {
+
+__device__ inline int bwrap(int p, int n) {
+  p %= n;
+  return p < 0 ? p + n : p;
+}
+
+// Distinct tiles (<= 3) reached along one axis by K stencil nodes starting at p0.
+__device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
+  int cnt = 0;
+  for (int k = 0; k < K; ++k) {
+    int p = p0 + k;
+    if (wall) {
+      if (p < 0 || p >= n) continue;
+    } else {
+      p = bwrap(p, n);
+    }
+    const int t = p / kTile;
+    bool seen = false;
+    for (int q = 0; q < cnt; ++q) seen = seen || out[q] == t;
+    if (!seen && cnt < 3) out[cnt++] = t;
+  }
+  return cnt;
+}
+
+// Tiles reached by the stencil of a vertex of cell c at offset o, per axis,
+// and its owner tile.
+__device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, const float* o,
+                                   int (&T)[3][3], int (&nT)[3]) {
+  const int K = L.kernel;
+  const int b = K == 4 ? -1 : 0;
+  const int n[3] = {L.nx, L.ny, L.nz};
+  int own[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int p = C.origin[3 * c + d] + (int)floorf(o[d]);
+    nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
+    own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : bwrap(p, n[d])) / kTile;
+  }
+  return (own[2] * L.ty + own[1]) * L.tx + own[0];
+}
+
+__device__ inline int slot_tile(const Lattice& L, const int (&T)[3][3], const int (&nT)[3], int j) {
+  const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
+  return (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
+}
+
+constexpr int kHash = 256;   // distinct tiles one cell may reach
+
+// One work-group per cell.  Every (vertex, reached tile) pair gets a local
+// rank in an LDS hash table keyed by tile; then one global atomic per
+// distinct tile reserves a contiguous block of that tile's list, and the
+// pairs are written at block base + local rank.  Tile lists have a fixed
+// capacity of B.cap entries; an overflow raises flags[1] bit 4.
+// pos: the cell's vertex offsets [nv][3] (global or LDS); keys, count and
+// base: LDS arrays of kHash ints.
+__device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B, int c,
+                                const float* pos, int* keys, int* count, int* base, int tid,
+                                int nthr) {
+  for (int i = tid; i < kHash; i += nthr) {
+    keys[i] = -1;
+    count[i] = 0;
+  }
+  __syncthreads();
+  for (int vl = tid; vl < M.nv; vl += nthr) {
+    const int64_t v = (int64_t)c * M.nv + vl;
+    int T[3][3], nT[3];
+    B.owner[v] = vertex_tiles(C, L, c, pos + 3 * vl, T, nT);
+    int ntouch = nT[0] * nT[1] * nT[2];
+    if (ntouch > L.max_touch) {  // excluded by the per-axis bound set at create
+      atomicOr(&B.flags[1], 2);
+      ntouch = L.max_touch;
+    }
+    B.ntouch[v] = ntouch;
+    for (int j = 0; j < ntouch; ++j) {
+      const int tile = slot_tile(L, T, nT, j);
+      int h = (int)(((unsigned)tile * 2654435761u) >> 24);
+      int probe = 0;
+      for (; probe < kHash; ++probe) {
+        const int prev = atomicCAS(&keys[h], -1, tile);
+        if (prev == -1 || prev == tile) break;
+        h = (h + 1) & (kHash - 1);
+      }
+      if (probe == kHash) {
+        atomicOr(&B.flags[1], 8);
+        B.slot[v * L.max_touch + j] = -1;
+        continue;
+      }
+      B.slot[v * L.max_touch + j] = (h << 16) | atomicAdd(&count[h], 1);
+    }
+  }
+  __syncthreads();
+  for (int h = tid; h < kHash; h += nthr) {
+    if (keys[h] < 0) continue;
+    base[h] = atomicAdd(&B.touch_cnt[keys[h]], count[h]);
+    if (base[h] + count[h] > B.cap) atomicOr(&B.flags[1], 4);
+  }
+  __syncthreads();
+  for (int vl = tid; vl < M.nv; vl += nthr) {
+    const int64_t v = (int64_t)c * M.nv + vl;
+    const int ntouch = B.ntouch[v];
+    for (int j = 0; j < ntouch; ++j) {
+      const int packed = B.slot[v * L.max_touch + j];
+      if (packed < 0) continue;
+      const int h = packed >> 16;
+      const int pos = base[h] + (packed & 0xffff);
+      if (pos < B.cap) B.touch[(int64_t)keys[h] * B.cap + pos] = (int)(v * 32 + j);
+    }
+  }
+}
+
+
+}  // namespace bin
+}  // namespace hc

@@ -1,0 +1,54 @@
+// Fused per-cell kernel of the single-lattice step: one work-group per cell
+// (1) closes the previous step's interpolation and moves the vertices
+//     (Sec. 2.6 explicit Euler), when one is pending;
+// (2) computes the membrane forces of the new positions (Sec. 2.3 force sum);
+// (3) bins the cell's vertices to the tiles their IBM stencils reach.
+// All three read the same 642 positions, so the cell is loaded once and its
+// latency-bound steps overlap across the resident work-groups.
+#include "binning_dev.h"
+#include "ibm_dev.h"
+#include "membrane_dev.h"
+
+namespace hc {
+namespace {
+
+constexpr int kCellThreads = 256;
+
+template <int K>
+__global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
+                                                           const float4* __restrict__ partial,
+                                                           int* __restrict__ flags, int advect) {
+  extern __shared__ long long lds64[];
+  __shared__ double red[2 * kCellThreads / kWave];
+  __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
+  long long* acc = lds64;
+  float* sp = reinterpret_cast<float*>(lds64 + 3 * M.nv);
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t b3 = (int64_t)c * M.nv * 3;
+  if (advect) {
+    for (int vl = tid; vl < M.nv; vl += kCellThreads)
+      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl);
+    __syncthreads();
+  }
+  mem::membrane_cell(M, C.off + b3, C.k + 4 * c, C.traction ? C.traction + 3 * c : nullptr,
+                     C.force + b3, C.area + c, C.volume + c, acc, sp, red, tid, kCellThreads);
+  bin::bin_cell(C, M, L, B, c, sp, keys, count, base, tid, kCellThreads);
+}
+
+}  // namespace
+
+hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                            const float4* partial, int* flags, bool advect, hipStream_t s) {
+  hipError_t e = launch_fill_i32(b.touch_cnt, 0, L.ntiles, s);
+  if (e != hipSuccess || c.n == 0) return e;
+  const size_t lds = (size_t)m.nv * 3 * (sizeof(long long) + sizeof(float));
+  if (L.kernel == 4)
+    hipLaunchKernelGGL(k_cell_step<4>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
+                       flags, advect ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_cell_step<2>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
+                       flags, advect ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace hc

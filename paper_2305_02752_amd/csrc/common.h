@@ -128,6 +128,13 @@ hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float4* macro,
                                  const Lattice& L, hipStream_t s);
+hipError_t launch_interp_partials(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                                  const float4* macro, float4* partial, hipStream_t s);
+hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                         const float4* partial, int* flags, hipStream_t s);
+// fused per-cell kernel: [advect of the pending step] + membrane + binning
+hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                            const float4* partial, int* flags, bool advect, hipStream_t s);
 hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                                 const float4* macro, float4* partial, int* flags, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -15,24 +15,13 @@
 // Integer addition is associative, so the result is bitwise independent of
 // the order in which waves and lanes arrive -- no global atomics, no
 // run-to-run drift.
-#include "common.h"
+#include "ibm_dev.h"
 
 namespace hc {
 namespace {
 
-__device__ inline float phi4(float r) {
-  r = fabsf(r);
-  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
-  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
-  return 0.f;
-}
-
-// Weight of stencil node k (0..K-1) for fractional position f in [0, 1).
-template <int K>
-__device__ inline float stencil_w(float f, int k) {
-  if (K == 4) return phi4(f + 1.f - (float)k);
-  return k == 0 ? 1.f - f : f;
-}
+using ibmd::phi4;
+using ibmd::stencil_w;
 
 __device__ inline int wrap(int p, int n) {
   p %= n;
@@ -124,20 +113,41 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
     axis_stencil<K>(C.origin[3 * c + 2], o[2], L.nz, L.bc[2] == 1, z0, lz, wz);
     rotate<K>(lx, wx, rot);
     rotate<K>(ly, wy, rot >> 2);
+    // weights are at most 1, so one test per entry decides whether every
+    // node contribution fits the 32-bit conversion
+    if (fmaxf(fabsf(fx), fmaxf(fabsf(fy), fabsf(fz))) < kFix32Max) {
 #pragma unroll
-    for (int kz = 0; kz < K; ++kz) {
-      if (lz[kz] < 0) continue;
+      for (int kz = 0; kz < K; ++kz) {
+        if (lz[kz] < 0) continue;
 #pragma unroll
-      for (int ky = 0; ky < K; ++ky) {
-        if (ly[ky] < 0) continue;
-        const float wzy = wz[kz] * wy[ky];
-        const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+        for (int ky = 0; ky < K; ++ky) {
+          if (ly[ky] < 0) continue;
+          const float wzy = wz[kz] * wy[ky];
+          const int row = (lz[kz] * kTile + ly[ky]) * kTile;
 #pragma unroll
-        for (int kx = 0; kx < K; ++kx) {
-          if (lx[kx] < 0) continue;
-          const float w = wzy * wx[kx];
-          const int li = row + lx[kx];
-          fix_add3(&acc[0][li], &acc[1][li], &acc[2][li], w * fx, w * fy, w * fz);
+          for (int kx = 0; kx < K; ++kx) {
+            if (lx[kx] < 0) continue;
+            const float w = wzy * wx[kx];
+            const int li = row + lx[kx];
+            atomicAdd((unsigned long long*)&acc[0][li], (unsigned long long)(long long)__float2int_rn(w * fx));
+            atomicAdd((unsigned long long*)&acc[1][li], (unsigned long long)(long long)__float2int_rn(w * fy));
+            atomicAdd((unsigned long long*)&acc[2][li], (unsigned long long)(long long)__float2int_rn(w * fz));
+          }
+        }
+      }
+    } else {
+      for (int kz = 0; kz < K; ++kz) {
+        if (lz[kz] < 0) continue;
+        for (int ky = 0; ky < K; ++ky) {
+          if (ly[ky] < 0) continue;
+          const float wzy = wz[kz] * wy[ky];
+          const int row = (lz[kz] * kTile + ly[ky]) * kTile;
+          for (int kx = 0; kx < K; ++kx) {
+            if (lx[kx] < 0) continue;
+            const float w = wzy * wx[kx];
+            const int li = row + lx[kx];
+            fix_add3_wide(&acc[0][li], &acc[1][li], &acc[2][li], w * fx, w * fy, w * fz);
+          }
         }
       }
     }
@@ -209,55 +219,13 @@ __global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattic
   }
 }
 
-// Interpolation, second half, and explicit Euler advection: one thread per
-// vertex sums its tile partials in slot order (fixed, so the result is
-// reproducible), adds stencil nodes beyond a wall at the wall velocity, and
-// moves the vertex.
 template <int K>
 __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins B,
                                                 const float4* __restrict__ partial,
                                                 int* __restrict__ flags) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
-  float Ux = 0.f, Uy = 0.f, Uz = 0.f;
-  const int nt = B.ntouch[v];
-  for (int j = 0; j < nt; ++j) {
-    const float4 q = partial[v * L.max_touch + j];
-    Ux += q.x;
-    Uy += q.y;
-    Uz += q.z;
-  }
-  float* o = C.off + v * 3;
-  const float ox = o[0], oy = o[1], oz = o[2];
-  if (L.wall_axis >= 0) {
-    // the other two axes' weights sum to one, so a node layer beyond the
-    // wall contributes its axis weight times the wall velocity
-    const int d = L.wall_axis;
-    const int c = (int)(v / M.nv);
-    const float od = d == 0 ? ox : (d == 1 ? oy : oz);
-    const float fl = floorf(od);
-    const int n = d == 0 ? L.nx : (d == 1 ? L.ny : L.nz);
-    const int base = C.origin[3 * c + d] + (int)fl - (K == 4 ? 1 : 0);
-    float wlo = 0.f, whi = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int p = base + k;
-      if (p < 0) wlo += stencil_w<K>(od - fl, k);
-      if (p >= n) whi += stencil_w<K>(od - fl, k);
-    }
-    Ux += wlo * L.ulo[0] + whi * L.uhi[0];
-    Uy += wlo * L.ulo[1] + whi * L.uhi[1];
-    Uz += wlo * L.ulo[2] + whi * L.uhi[2];
-  }
-  const float nx = ox + Ux, ny = oy + Uy, nz = oz + Uz;
-  if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
-  float* vo = C.vel + v * 3;
-  vo[0] = Ux;
-  vo[1] = Uy;
-  vo[2] = Uz;
-  o[0] = nx;
-  o[1] = ny;
-  o[2] = nz;
+  ibmd::advect_vertex<K>(C, M, L, B, partial, flags, v);
 }
 
 }  // namespace
@@ -273,6 +241,30 @@ hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, co
     hipLaunchKernelGGL(k_spread<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
   else
     hipLaunchKernelGGL(k_spread<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_partials(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                                  const float4* macro, float4* partial, hipStream_t s) {
+  if ((int64_t)c.n * m.nv == 0) return hipSuccess;
+  if (L.kernel == 4)
+    hipLaunchKernelGGL(k_interp_partials<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_interp_partials<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
+                       partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                         const float4* partial, int* flags, hipStream_t s) {
+  const int64_t n = (int64_t)c.n * m.nv;
+  if (n == 0) return hipSuccess;
+  const dim3 gv((unsigned)((n + 255) / 256));
+  if (L.kernel == 4)
+    hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
+  else
+    hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
   return hipGetLastError();
 }
 

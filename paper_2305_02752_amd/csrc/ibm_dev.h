@@ -1,0 +1,74 @@
+// Device helpers of the immersed-boundary coupling (Sec. 2.3) shared by the
+// tile kernels and the fused per-cell kernel: Peskin's 4-point function,
+// stencil weights, and the per-vertex close of the interpolation with the
+// explicit Euler move (Sec. 2.6).
+#pragma once
+
+#include "common.h"
+
+namespace hc {
+namespace ibmd {
+
+__device__ inline float phi4(float r) {
+  r = fabsf(r);
+  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
+  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
+  return 0.f;
+}
+
+// Weight of stencil node k (0..K-1) for fractional position f in [0, 1).
+template <int K>
+__device__ inline float stencil_w(float f, int k) {
+  if (K == 4) return phi4(f + 1.f - (float)k);
+  return k == 0 ? 1.f - f : f;
+}
+
+// Vertex velocity = tile partials summed in slot order (fixed, so the result
+// is reproducible) + stencil nodes beyond a wall at the wall velocity; then
+// X += U.  The other two axes' weights sum to one, so a node layer beyond
+// the wall contributes its axis weight times the wall velocity.
+template <int K>
+__device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
+                                     const float4* __restrict__ partial, int* __restrict__ flags,
+                                     int64_t v) {
+  float Ux = 0.f, Uy = 0.f, Uz = 0.f;
+  const int nt = B.ntouch[v];
+  for (int j = 0; j < nt; ++j) {
+    const float4 q = partial[v * L.max_touch + j];
+    Ux += q.x;
+    Uy += q.y;
+    Uz += q.z;
+  }
+  float* o = C.off + v * 3;
+  const float ox = o[0], oy = o[1], oz = o[2];
+  if (L.wall_axis >= 0) {
+    const int d = L.wall_axis;
+    const int c = (int)(v / M.nv);
+    const float od = d == 0 ? ox : (d == 1 ? oy : oz);
+    const float fl = floorf(od);
+    const int n = d == 0 ? L.nx : (d == 1 ? L.ny : L.nz);
+    const int base = C.origin[3 * c + d] + (int)fl - (K == 4 ? 1 : 0);
+    float wlo = 0.f, whi = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int p = base + k;
+      if (p < 0) wlo += stencil_w<K>(od - fl, k);
+      if (p >= n) whi += stencil_w<K>(od - fl, k);
+    }
+    Ux += wlo * L.ulo[0] + whi * L.uhi[0];
+    Uy += wlo * L.ulo[1] + whi * L.uhi[1];
+    Uz += wlo * L.ulo[2] + whi * L.uhi[2];
+  }
+  const float nx = ox + Ux, ny = oy + Uy, nz = oz + Uz;
+  if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
+  float* vo = C.vel + v * 3;
+  vo[0] = Ux;
+  vo[1] = Uy;
+  vo[2] = Uz;
+  o[0] = nx;
+  o[1] = ny;
+  o[2] = nz;
+}
+
+}  // namespace ibmd
+}  // namespace hc

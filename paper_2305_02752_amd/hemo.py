@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhemo.so")
 
 HC_PERIODIC, HC_WALL = 0, 1
 HC_PHI2, HC_PHI4 = 2, 4
-KERNELS = ("membrane", "binning", "spread", "collide_stream", "interp_advect")
+KERNELS = ("cell", "spread", "collide_stream", "interp", "advect")
 STATUS = {0: "HC_OK", 1: "HC_ERR_ARG", 2: "HC_ERR_STATE", 3: "HC_ERR_DEVICE", 4: "HC_ERR_OOM",
           5: "HC_ERR_NONFINITE", 6: "HC_ERR_UNSUPPORTED"}
 
