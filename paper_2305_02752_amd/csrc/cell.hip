@@ -26,12 +26,18 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t b3 = (int64_t)c * M.nv * 3;
   if (advect) {
-    for (int vl = tid; vl < M.nv; vl += kCellThreads)
-      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl);
-    __syncthreads();
+    for (int vl = tid; vl < M.nv; vl += kCellThreads) {
+      float nx[3];
+      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx);
+      sp[3 * vl] = nx[0];
+      sp[3 * vl + 1] = nx[1];
+      sp[3 * vl + 2] = nx[2];
+    }
   }
-  mem::membrane_cell(M, C.off + b3, C.k + 4 * c, C.traction ? C.traction + 3 * c : nullptr,
-                     C.force + b3, C.area + c, C.volume + c, acc, sp, red, tid, kCellThreads);
+  // after a move the new offsets are staged in sp already
+  mem::membrane_cell(M, advect ? nullptr : C.off + b3, C.k + 4 * c,
+                     C.traction ? C.traction + 3 * c : nullptr, C.force + b3, C.area + c,
+                     C.volume + c, acc, sp, red, tid, kCellThreads);
   bin::bin_cell(C, M, L, B, c, sp, keys, count, base, tid, kCellThreads);
 }
 

@@ -225,7 +225,8 @@ __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins
                                                 int* __restrict__ flags) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
-  ibmd::advect_vertex<K>(C, M, L, B, partial, flags, v);
+  float nx[3];
+  ibmd::advect_vertex<K>(C, M, L, B, partial, flags, v, nx);
 }
 
 }  // namespace

@@ -25,12 +25,12 @@ __device__ inline float stencil_w(float f, int k) {
 
 // Vertex velocity = tile partials summed in slot order (fixed, so the result
 // is reproducible) + stencil nodes beyond a wall at the wall velocity; then
-// X += U.  The other two axes' weights sum to one, so a node layer beyond
+// X += U.  The new offset is also returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
 // the wall contributes its axis weight times the wall velocity.
 template <int K>
 __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                      const float4* __restrict__ partial, int* __restrict__ flags,
-                                     int64_t v) {
+                                     int64_t v, float (&nxyz)[3]) {
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
   const int nt = B.ntouch[v];
   for (int j = 0; j < nt; ++j) {
@@ -68,6 +68,9 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
   o[0] = nx;
   o[1] = ny;
   o[2] = nz;
+  nxyz[0] = nx;
+  nxyz[1] = ny;
+  nxyz[2] = nz;
 }
 
 }  // namespace ibmd

@@ -136,13 +136,14 @@ __device__ inline void area_volume(const Mesh& M, const float* sp, double* red, 
 
 // Forces on one cell with `nthr` cooperating threads (thread `tid`).
 // acc: LDS [nv][3] int64, sp: LDS [nv][3] float, red: LDS [2 * nthr / 64]
-// double.  Writes area/volume (float64) and the per-vertex forces.
+// double.  Writes area/volume (float64) and the per-vertex forces.  With
+// off == nullptr the caller has already staged the offsets in sp.
 __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ off,
                                      const float* __restrict__ k4, const float* trac,
                                      float* __restrict__ out, double* area, double* volume,
                                      long long* acc, float* sp, double* red, int tid, int nthr) {
   for (int i = tid; i < 3 * M.nv; i += nthr) {
-    sp[i] = off[i];
+    if (off) sp[i] = off[i];
     acc[i] = 0;
   }
   __syncthreads();
