@@ -129,8 +129,14 @@ hc_status hc_write_populations(hc_ctx* ctx, const float* host, int64_t count);
 
 /* Density [N] and velocity [3][N] of the last step's moments (velocity
  * includes half the force density, Guo forcing); N = nx * ny * nz.
- * Either pointer may be NULL. */
+ * Either pointer may be NULL.  HC_ERR_STATE when the field output is off. */
 hc_status hc_read_macro(hc_ctx* ctx, float* rho, float* u, int64_t n_sites);
+
+/* Whether each step writes its force field and (u, rho) field to device
+ * memory for hc_read_force_field / hc_read_macro (default on).  The step
+ * keeps both on chip, so turning the output off saves 28 bytes per site
+ * per step of HBM writes. */
+hc_status hc_set_field_output(hc_ctx* ctx, int32_t enable);
 
 /* Force density [3][N] (body force + spread membrane forces) of the last step. */
 hc_status hc_read_force_field(hc_ctx* ctx, float* f, int64_t n_sites);
@@ -176,12 +182,10 @@ hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
  * (index HC_K_*), the summed device time in milliseconds and the number of
  * launches since the last hc_profile call.  Arrays hold HC_NUM_KERNELS. */
 enum {
-  HC_K_CELL = 0,            /* per-cell: pending vertex move + membrane forces + binning */
-  HC_K_SPREAD = 1,          /* IBM spread onto the force field */
-  HC_K_COLLIDE_STREAM = 2,  /* BGK collide + Guo forcing + push stream */
-  HC_K_INTERP = 3,          /* IBM interpolation, per-tile partial sums */
-  HC_K_ADVECT = 4,          /* vertex move closing the last step of an hc_step call */
-  HC_NUM_KERNELS = 5
+  HC_K_CELL = 0,     /* per cell: pending vertex move, membrane forces, binning */
+  HC_K_LATTICE = 1,  /* per tile: IBM spread, collide + stream, IBM interpolation */
+  HC_K_ADVECT = 2,   /* vertex move closing the last step of an hc_step call */
+  HC_NUM_KERNELS = 3
 };
 hc_status hc_profile(hc_ctx* ctx, int32_t enable);
 hc_status hc_profile_read(hc_ctx* ctx, double* total_ms, int64_t* launches);

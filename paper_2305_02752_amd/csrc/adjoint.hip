@@ -2,17 +2,21 @@
 // state variable), used to differentiate a cell-shape loss with respect to
 // the membrane stiffnesses and the relaxation time.
 //
-// One forward step n maps (f^n, X^n) to (f^{n+1}, X^{n+1}) through
+// The lattice state is the stored post-collision field h (pull form).  One
+// forward step n maps (h^n, X^n) to (h^{n+1}, X^{n+1}) through
 //   F_v = Fmem(X; k) + T                      (Sec. 2.3 force sum)
 //   F(x) = g + sum_v F_v delta(x - X_v)       (Sec. 2.3 spreading)
+//   f = pull(h^n)                             (streaming, bounce-back)
 //   rho, u = moments(f, F)                    (Sec. 2.2, half force in u)
 //   U_v = sum_x u(x) delta(x - X_v)           (Sec. 2.3 interpolation)
-//   f* = f - omega (f - f_eq) + (1 - omega/2) S(u, F);  f^{n+1} = stream(f*)
+//   h^{n+1} = f - omega (f - f_eq) + (1 - omega/2) S(u, F) + c rho
+//     (c: moving-wall coefficient of populations leaving through a wall)
 //   X^{n+1} = X^n + U                          (Sec. 2.6 Euler)
-// Its transpose, given lam_f^{n+1} and lam_X^{n+1}, is evaluated by:
+// Its transpose, given lam_h^{n+1} and lam_X^{n+1}, is evaluated by:
 //   spread of lam_U = lam_X^{n+1}        -> lam_u(x)        (k_spread, reused)
-//   k_adj_collide: pull lam* from the streamed positions, then the
-//     collision VJP -> lam_f^n, lam_F(x), and d/d omega partial sums;
+//   k_adj_collide: the collision VJP at each node from its own lam_h^{n+1}
+//     -> lam_f, lam_F(x), and d/d omega partial sums; lam_f is then
+//     scattered back to the pull sources (a bijection) as lam_h^n;
 //   k_adj_vertex: lam_{F_v} = sum_x lam_F(x) delta, plus the kernel-gradient
 //     terms sum_x (lam_U.u(x) + F_v.lam_F(x)) grad delta for lam_X;
 //   k_adj_membrane: lam_X += (dF_v/dX) lam_{F_v} by forward-mode duals (the
@@ -55,44 +59,35 @@ __device__ inline int wrap(int p, int n) {
 
 __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ lam1,
                                                      float* __restrict__ lam0,
-                                                     const float* __restrict__ g0,
+                                                     const float* __restrict__ h0,
                                                      const float* __restrict__ F,
                                                      const float* __restrict__ lamu,
                                                      float* __restrict__ lamF,
                                                      double* __restrict__ domega_part, Lattice L) {
   __shared__ double red[4];
-  const int64_t N = L.n;
+  const int64_t N = L.np;   // slots of every (tile-major) lattice field
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double dom = 0.0;
-  if (s < N) {
-    const int x = (int)(s % L.nx);
-    const int64_t r = s / L.nx;
-    const int y = (int)(r % L.ny), z = (int)(r / L.ny);
-    // cotangent of the post-collision values, pulled from where streaming put them
+  int x, y, z;
+  if (s < N && node_of(L, s, x, y, z)) {
+    // cotangent of the post-collision values stored at this node; a value
+    // stored for a bounce-back carries the wall term c rho
     float ls[kQ];
     float lrho = 0.f;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      int xt = x + cx[i], yt = y + cy[i], zt = z + cz[i];
-      int crossed = 0;
-      if (L.wall_axis == 0 && cx[i] != 0) crossed = xt < 0 ? 1 : (xt >= L.nx ? 2 : 0);
-      if (L.wall_axis == 1 && cy[i] != 0) crossed = yt < 0 ? 1 : (yt >= L.ny ? 2 : 0);
-      if (L.wall_axis == 2 && cz[i] != 0) crossed = zt < 0 ? 1 : (zt >= L.nz ? 2 : 0);
-      if (crossed) {
-        ls[i] = lam1[opp[i] * N + s];
-        const float uw = crossed == 1 ? cx[i] * L.ulo[0] + cy[i] * L.ulo[1] + cz[i] * L.ulo[2]
-                                      : cx[i] * L.uhi[0] + cy[i] * L.uhi[1] + cz[i] * L.uhi[2];
-        lrho += -6.f * wq[i] * uw * ls[i];   // moving-wall term depends on rho(x)
-      } else {
-        xt = xt < 0 ? xt + L.nx : (xt >= L.nx ? xt - L.nx : xt);
-        yt = yt < 0 ? yt + L.ny : (yt >= L.ny ? yt - L.ny : yt);
-        zt = zt < 0 ? zt + L.nz : (zt >= L.nz ? zt - L.nz : zt);
-        ls[i] = lam1[i * N + ((int64_t)zt * L.ny + yt) * L.nx + xt];
-      }
+      ls[i] = lam1[i * N + s];
+      lrho += lbm::wall_coeff(L, i, x, y, z) * ls[i];
     }
+    // pre-collision populations, pulled as in the forward step
     float g[kQ];
+    int64_t from[kQ];
+    int qs[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) g[i] = g0[i * N + s];
+    for (int i = 0; i < kQ; ++i) {
+      from[i] = lbm::pull_source(L, i, x, y, z, &qs[i]);
+      g[i] = h0[qs[i] * N + from[i]];
+    }
     const float fx = F[s], fy = F[N + s], fz = F[2 * N + s];
     float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -132,8 +127,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     Bz += lamu[2 * N + s];
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      lam0[i * N + s] = (1.f - om) * ls[i] + A +
-                        (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
+      lam0[qs[i] * N + from[i]] = (1.f - om) * ls[i] + A +
+                                 (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
     lamF[s] = Gx + 0.5f * Bx * inv;
     lamF[N + s] = Gy + 0.5f * By * inv;
     lamF[2 * N + s] = Gz + 0.5f * Bz * inv;
@@ -157,7 +152,7 @@ __global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
   const int c = (int)(v / M.nv);
-  const int64_t N = L.n;
+  const int64_t N = L.np;
   const int n3[3] = {L.nx, L.ny, L.nz};
   int base[3];
   float w[3][4], dw[3][4];
@@ -191,7 +186,7 @@ __global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
         } else if (sd == 2) {
           ux = L.uhi[0]; uy = L.uhi[1]; uz = L.uhi[2];
         } else {
-          const int64_t s = ((int64_t)pz * L.ny + py) * L.nx + px;
+          const int64_t s = site_of(L, px, py, pz);
           const float4 q = macro[s];
           ux = q.x; uy = q.y; uz = q.z;
           lFx = lamF[s]; lFy = lamF[N + s]; lFz = lamF[2 * N + s];
@@ -390,7 +385,7 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
                               const float* lamu, float* lamF, double* domega_part, const Lattice& L,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, lam1, lam0,
+  hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.np + 255) / 256)), dim3(256), 0, s, lam1, lam0,
                      g0, F, lamu, lamF, domega_part, L);
   return hipGetLastError();
 }

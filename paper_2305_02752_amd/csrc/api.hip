@@ -59,6 +59,7 @@ struct hc_ctx {
   // the last step's vertex move is still to be applied (it runs fused into
   // the next step's per-cell kernel, or in flush() before the state is seen)
   bool advect_pending = false;
+  bool fields = true;          // write the force and (u, rho) fields each step
   // optional per-kernel timing with events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -106,7 +107,7 @@ T* at(hc_ctx* c, size_t off) {
 }
 
 void plan(hc_ctx* c, Layout& lay) {
-  const int64_t N = c->L.n;
+  const int64_t N = c->L.np;   // lattice fields are stored tile-major with padding
   const int64_t C = c->max_cells, nv = c->hm.nv;
   const int64_t NT = c->L.ntiles;
   c->o_pops[0] = lay.add(19 * N * 4);
@@ -199,14 +200,9 @@ hc_status one_step(hc_ctx* c) {
   HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
     return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, c->stream);
   }));
-  HC_TRY(timed(c, HC_K_SPREAD, "spread",
-               [&] { return launch_spread(C, c->M, c->L, c->B, c->F, c->stream); }));
-  HC_TRY(timed(c, HC_K_COLLIDE_STREAM, "collide_stream", [&] {
-    return launch_collide_stream(c->pops[c->cur], c->pops[c->cur ^ 1], c->F, c->macro, c->L,
-                                 c->stream);
-  }));
-  HC_TRY(timed(c, HC_K_INTERP, "interp", [&] {
-    return launch_interp_partials(C, c->M, c->L, c->B, c->macro, c->partial, c->stream);
+  HC_TRY(timed(c, HC_K_LATTICE, "lattice pass", [&] {
+    return launch_tile_step(C, c->M, c->L, c->B, c->pops[c->cur], c->pops[c->cur ^ 1], c->F,
+                            c->macro, c->partial, c->fields, c->stream);
   }));
   c->advect_pending = C.n > 0;
   c->cur ^= 1;
@@ -237,7 +233,7 @@ struct AdjPlan {
 AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   AdjPlan p;
   Layout L;
-  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->max_cells * c->hm.nv * 3;
+  const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->max_cells * c->hm.nv * 3;
   const int64_t nck = (n + ck - 1) / ck, C = c->max_cells;
   p.ck_pops = L.add(nck * P * 4);
   p.ck_off = L.add(nck * X * 4);
@@ -264,32 +260,32 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
 }
 
 // One forward step of the recomputed segment, from slot i to slot i + 1,
-// keeping everything the reverse sweep reads.
+// keeping everything the reverse sweep reads.  It runs the same kernels as
+// the forward step (field output on), so a recomputed state equals the
+// forward one bit for bit.
 hc_status adj_forward_into(hc_ctx* c, int i) {
-  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   Cells Ci = c->C;
   Ci.off = c->sg_off + i * X;
   Ci.force = c->sg_Fv + i * X;
   Ci.vel = c->vel_scratch;
   float* Fi = c->sg_F + i * 3 * N;
   float4* Mi = c->sg_macro + i * N;
-  HC_TRY(check(c, launch_membrane(Ci, c->M, c->stream), "membrane"));
-  HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
-  HC_TRY(check(c, launch_spread(Ci, c->M, c->L, c->B, Fi, c->stream), "spread"));
-  HC_TRY(check(c, launch_collide_stream(c->sg_pops + i * P, c->sg_pops + (i + 1) * P, Fi, Mi, c->L,
-                                        c->stream),
-               "collide"));
+  HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, false, c->stream),
+               "cell step"));
+  HC_TRY(check(c, launch_tile_step(Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
+                                   Fi, Mi, c->partial, true, c->stream),
+               "lattice pass"));
   Cells Cn = Ci;
   Cn.off = c->sg_off + (i + 1) * X;
   HC_TRY(copy_d2d(c, Cn.off, Ci.off, (size_t)X * 4));
-  HC_TRY(check(c, launch_interp_advect(Cn, c->M, c->L, c->B, Mi, c->partial, c->B.flags, c->stream),
-               "interp"));
+  HC_TRY(check(c, launch_advect(Cn, c->M, c->L, c->B, c->partial, c->B.flags, c->stream), "advect"));
   return HC_OK;
 }
 
 // Reverse of step i of the segment: (lam_f, lam_X)^{i+1} -> (lam_f, lam_X)^i.
 hc_status adj_reverse_step(hc_ctx* c, int i, int a) {
-  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   Cells Ci = c->C;
   Ci.off = c->sg_off + i * X;
   Ci.force = c->sg_Fv + i * X;
@@ -365,6 +361,7 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   L.ty = (L.ny + kTile - 1) / kTile;
   L.tz = (L.nz + kTile - 1) / kTile;
   L.ntiles = L.tx * L.ty * L.tz;
+  L.np = (int64_t)L.ntiles * kTile * kTile * kTile;
   // a K-node stencil window meets 3 tiles along a periodic axis only when the
   // last tile is at most K-2 nodes wide; otherwise 2 (1 for a 1-tile axis)
   L.max_touch = 1;
@@ -556,41 +553,52 @@ hc_status hc_sync(hc_ctx* c) {
   return HC_OK;
 }
 
+// The idle population buffer (overwritten by the next step) stages the
+// natural-order copies of the read-out and write-in calls.
 hc_status hc_read_populations(hc_ctx* c, float* host, int64_t count) {
   HC_TRY(need_ws(c));
   if (!host || count != 19 * c->L.n) return fail(c, HC_ERR_ARG, "population count mismatch");
-  HC_TRY(copy_d2h(c, host, c->pops[c->cur], (size_t)count * 4));
+  float* tmp = c->pops[c->cur ^ 1];
+  HC_TRY(check(c, launch_to_natural(c->pops[c->cur], tmp, c->L, c->stream), "to natural"));
+  HC_TRY(copy_d2h(c, host, tmp, (size_t)count * 4));
   return sync(c, "read populations");
 }
 
 hc_status hc_write_populations(hc_ctx* c, const float* host, int64_t count) {
   HC_TRY(need_ws(c));
   if (!host || count != 19 * c->L.n) return fail(c, HC_ERR_ARG, "population count mismatch");
-  HC_TRY(copy_h2d(c, c->pops[c->cur], host, (size_t)count * 4));
+  float* tmp = c->pops[c->cur ^ 1];
+  HC_TRY(copy_h2d(c, tmp, host, (size_t)count * 4));
+  HC_TRY(check(c, launch_from_natural(tmp, c->pops[c->cur], c->L, c->stream), "from natural"));
   return sync(c, "write populations");
+}
+
+hc_status hc_set_field_output(hc_ctx* c, int32_t enable) {
+  if (!c) return HC_ERR_ARG;
+  c->fields = enable != 0;
+  return HC_OK;
 }
 
 hc_status hc_read_macro(hc_ctx* c, float* rho, float* u, int64_t n_sites) {
   HC_TRY(need_ws(c));
+  if (!c->fields) return fail(c, HC_ERR_STATE, "field output is switched off");
   if (n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
-  std::vector<float> tmp((size_t)n_sites * 4);
-  HC_TRY(copy_d2h(c, tmp.data(), c->macro, (size_t)n_sites * 16));
-  HC_TRY(sync(c, "read macro"));
-  for (int64_t s = 0; s < n_sites; ++s) {
-    if (u) {
-      u[s] = tmp[4 * s];
-      u[n_sites + s] = tmp[4 * s + 1];
-      u[2 * n_sites + s] = tmp[4 * s + 2];
-    }
-    if (rho) rho[s] = tmp[4 * s + 3];
-  }
-  return HC_OK;
+  float* tmp = c->pops[c->cur ^ 1];   // [4][n]: ux, uy, uz, rho
+  HC_TRY(check(c, launch_field_to_natural(reinterpret_cast<const float*>(c->macro), tmp, 4, c->L,
+                                          c->stream),
+               "to natural"));
+  if (u) HC_TRY(copy_d2h(c, u, tmp, (size_t)n_sites * 12));
+  if (rho) HC_TRY(copy_d2h(c, rho, tmp + 3 * n_sites, (size_t)n_sites * 4));
+  return sync(c, "read macro");
 }
 
 hc_status hc_read_force_field(hc_ctx* c, float* f, int64_t n_sites) {
   HC_TRY(need_ws(c));
+  if (!c->fields) return fail(c, HC_ERR_STATE, "field output is switched off");
   if (!f || n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
-  HC_TRY(copy_d2h(c, f, c->F, (size_t)n_sites * 12));
+  float* tmp = c->pops[c->cur ^ 1];
+  HC_TRY(check(c, launch_field_to_natural(c->F, tmp, 3, c->L, c->stream), "to natural"));
+  HC_TRY(copy_d2h(c, f, tmp, (size_t)n_sites * 12));
   return sync(c, "read force field");
 }
 
@@ -673,7 +681,7 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
 
 hc_status hc_checkpoint_size(const hc_ctx* c, size_t* bytes) {
   if (!c || !bytes) return HC_ERR_ARG;
-  *bytes = 16 + (size_t)19 * c->L.n * 4 + (size_t)c->C.n * 12 + (size_t)c->C.n * c->hm.nv * 12;
+  *bytes = 16 + (size_t)19 * c->L.np * 4 + (size_t)c->C.n * 12 + (size_t)c->C.n * c->hm.nv * 12;
   return HC_OK;
 }
 
@@ -686,8 +694,8 @@ hc_status hc_checkpoint_save(hc_ctx* c, void* host, size_t bytes) {
   int64_t hdr[2] = {c->step, c->C.n};
   std::memcpy(p, hdr, 16);
   p += 16;
-  HC_TRY(copy_d2h(c, p, c->pops[c->cur], (size_t)19 * c->L.n * 4));
-  p += (size_t)19 * c->L.n * 4;
+  HC_TRY(copy_d2h(c, p, c->pops[c->cur], (size_t)19 * c->L.np * 4));
+  p += (size_t)19 * c->L.np * 4;
   HC_TRY(copy_d2h(c, p, c->C.origin, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
   HC_TRY(copy_d2h(c, p, c->C.off, (size_t)c->C.n * c->hm.nv * 12));
@@ -704,8 +712,8 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   std::memcpy(hdr, p, 16);
   if (hdr[1] != c->C.n) return fail(c, HC_ERR_ARG, "checkpoint cell count differs");
   p += 16;
-  HC_TRY(copy_h2d(c, c->pops[c->cur], p, (size_t)19 * c->L.n * 4));
-  p += (size_t)19 * c->L.n * 4;
+  HC_TRY(copy_h2d(c, c->pops[c->cur], p, (size_t)19 * c->L.np * 4));
+  p += (size_t)19 * c->L.np * 4;
   HC_TRY(copy_h2d(c, c->C.origin, p, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
   HC_TRY(copy_h2d(c, c->C.off, p, (size_t)c->C.n * c->hm.nv * 12));
@@ -780,7 +788,7 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
   HC_TRY(need_ws(c));
   if (!c->adj_ws) return fail(c, HC_ERR_STATE, "no adjoint workspace bound");
   if (!c->have_cells || !targets || !loss) return fail(c, HC_ERR_STATE, "adjoint: no cells or targets");
-  const int64_t P = 19 * c->L.n, X = (int64_t)c->C.n * c->hm.nv * 3;
+  const int64_t P = 19 * c->L.np, X = (int64_t)c->C.n * c->hm.nv * 3;
   HC_TRY(copy_h2d(c, c->targets, targets, (size_t)c->C.n * 16));
   for (int s = 0; s < c->adj_n; ++s) {
     if (s % c->adj_ck == 0) {
@@ -801,7 +809,7 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
 hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   HC_TRY(need_ws(c));
   if (!c->adj_ready || !grad) return fail(c, HC_ERR_STATE, "hc_adj_forward must run first");
-  const int64_t N = c->L.n, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
+  const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   const int nblk = (int)((N + 255) / 256);
   HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));

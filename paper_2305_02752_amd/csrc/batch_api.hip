@@ -385,12 +385,9 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   HB_TRY(bcheck(b, launch_fill_i32(reinterpret_cast<int*>(V.uacc), 0,
                                    (int64_t)b->nbox * m.nv * 6, b->stream),
                 "clear"));
-  for (auto& B : b->box) {
-    Lattice L{};
-    L.n = B.n;
-    HB_TRY(bcheck(b, launch_init_equilibrium(V.pops0 + B.pop_off, 1.f, 0.f, 0.f, 0.f, L, b->stream),
+  for (auto& B : b->box)
+    HB_TRY(bcheck(b, launch_init_uniform(V.pops0 + B.pop_off, 1.f, 0.f, 0.f, 0.f, B.n, b->stream),
                   "init"));
-  }
   if (!b->cap_stream) HB_TRY(bcheck(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "stream"));
   HB_TRY(apply_tiling(b, b->ty, b->tz, b->block));
   return bsync(b);

@@ -56,9 +56,30 @@ struct Lattice {
   float ulo[3], uhi[3];     // wall velocities (wall axis only)
   int kernel;               // 4 or 2
   int64_t n;                // nx * ny * nz
+  int64_t np;               // ntiles * 512: site slots of every lattice field
   int tx, ty, tz, ntiles;   // tile grid
   int max_touch;            // touch-list slots per vertex (product over axes)
 };
+
+// Site order of every lattice field on the device (populations, force,
+// velocity and their cotangents): 8^3 tiles in (tz, ty, tx) order, the 512
+// sites of a tile in (z, y, x) order.  A work-group that owns a tile reads
+// and writes each population as one contiguous 2 KiB block.  Sides that are
+// not multiples of 8 leave padding slots, which are never read.
+static_assert(kTile == 8, "site_of assumes 8^3 tiles");
+__host__ __device__ inline int64_t site_of(const Lattice& L, int x, int y, int z) {
+  const int t = ((z >> 3) * L.ty + (y >> 3)) * L.tx + (x >> 3);
+  return (int64_t)t * 512 + (((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
+}
+
+// Node of slot h, or false for a padding slot.
+__host__ __device__ inline bool node_of(const Lattice& L, int64_t h, int& x, int& y, int& z) {
+  const int t = (int)(h >> 9), i = (int)(h & 511);
+  x = (t % L.tx) * kTile + (i & 7);
+  y = ((t / L.tx) % L.ty) * kTile + ((i >> 3) & 7);
+  z = (t / (L.tx * L.ty)) * kTile + (i >> 6);
+  return x < L.nx && y < L.ny && z < L.nz;
+}
 
 // Mesh tables shared by every cell (built on the host from the rest shape).
 struct Mesh {
@@ -108,8 +129,6 @@ hipError_t launch_touch_csr(const Lattice& L, const Bins& b, int* cnt_tmp, int* 
 hipError_t launch_sort_segments(const int* ptr, int* list, int* tmp, int nseg, hipStream_t s);
 hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
-hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                         float* F, hipStream_t s);
 // spread an arbitrary per-vertex vector field (vec [n*nv][3]) plus body * g
 hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                              const float* vec, float body, float* F, hipStream_t s);
@@ -126,19 +145,31 @@ hipError_t launch_loss_seed(const Cells& c, const Mesh& m, const double* targets
                             float* lamX, hipStream_t s);
 hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
-hipError_t launch_collide_stream(const float* gin, float* gout, const float* F, float4* macro,
-                                 const Lattice& L, hipStream_t s);
-hipError_t launch_interp_partials(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                                  const float4* macro, float4* partial, hipStream_t s);
+// interpolation close (tile partials summed per vertex) + explicit Euler move
 hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                          const float4* partial, int* flags, hipStream_t s);
+// fused lattice pass: spread + collide/stream + interpolation partials;
+// with fields set it also writes the force field F and (u, rho) to macro
+hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                            const float* gin, float* gout, float* F, float4* macro, float4* partial,
+                            bool fields, hipStream_t s);
 // fused per-cell kernel: [advect of the pending step] + membrane + binning
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, hipStream_t s);
-hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                                const float4* macro, float4* partial, int* flags, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// stored (pull-form) state of a uniform equilibrium on the tile-major lattice
 hipError_t launch_init_equilibrium(float* g, float rho0, float ux, float uy, float uz,
                                    const Lattice& L, hipStream_t s);
+// uniform equilibrium on n sites in any order (fully periodic boxes)
+hipError_t launch_init_uniform(float* g, float rho0, float ux, float uy, float uz, int64_t n,
+                               hipStream_t s);
+// natural <-> device site order: to_natural writes g[19][n] (pre-collision
+// populations, x fastest) from the stored state h; from_natural the inverse;
+// field_to_natural copies `comps` float components of a [comps][np] field
+// (or, with comps == 4, a float4 [np] field into [4][n])
+hipError_t launch_to_natural(const float* h, float* g, const Lattice& L, hipStream_t s);
+hipError_t launch_from_natural(const float* g, float* h, const Lattice& L, hipStream_t s);
+hipError_t launch_field_to_natural(const float* f, float* out, int comps, const Lattice& L,
+                                   hipStream_t s);
 
 }  // namespace hc

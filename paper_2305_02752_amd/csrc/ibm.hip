@@ -16,6 +16,7 @@
 // the order in which waves and lanes arrive -- no global atomics, no
 // run-to-run drift.
 #include "ibm_dev.h"
+#include "lbm_dev.h"
 
 namespace hc {
 namespace {
@@ -79,24 +80,14 @@ __device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, in
   z0 = (t / (L.tx * L.ty)) * kTile;
 }
 
-// One work-group per tile; one thread per (vertex, tile) entry of the tile's
-// list: the thread evaluates its 3 x K axis weights once and adds the
-// contributions of the stencil nodes inside the tile to the LDS accumulator.
+// Spread phase of one tile: one thread per (vertex, tile) entry of the
+// tile's list; the thread evaluates its 3 x K axis weights once and adds the
+// contributions of the stencil nodes inside the tile to the LDS accumulator
+// acc[3][512] (zeroed by the caller, synchronised after).
 template <int K>
-__global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
-                                                const float* __restrict__ vec, float body,
-                                                float* __restrict__ F) {
-  __shared__ long long acc[3][kTile * kTile * kTile];
-  const int t = blockIdx.x;
-  int x0, y0, z0;
-  tile_origin(L, t, x0, y0, z0);
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
-    acc[0][i] = 0;
-    acc[1][i] = 0;
-    acc[2][i] = 0;
-  }
-  __syncthreads();
-
+__device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
+                                   const float* __restrict__ vec, int t, int x0, int y0, int z0,
+                                   long long (*acc)[kTile * kTile * kTile]) {
   const int64_t e0 = (int64_t)t * B.cap;
   const int64_t e1 = e0 + min(B.touch_cnt[t], B.cap);
   const int rot = threadIdx.x;
@@ -152,38 +143,16 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
       }
     }
   }
-  __syncthreads();
-
-  const int64_t N = L.n;
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
-    const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
-    if (x >= L.nx || y >= L.ny || z >= L.nz) continue;
-    const int64_t s = ((int64_t)z * L.ny + y) * L.nx + x;
-    F[s] = body * L.g[0] + (float)((double)acc[0][i] * kFixInv);
-    F[N + s] = body * L.g[1] + (float)((double)acc[1][i] * kFixInv);
-    F[2 * N + s] = body * L.g[2] + (float)((double)acc[2][i] * kFixInv);
-  }
 }
 
-// Interpolation, first half: one work-group per tile stages the tile's
-// velocities in LDS; each (vertex, tile) entry sums w * u over its stencil
-// nodes inside the tile and stores the partial sum in the vertex's slot.
+// Interpolation phase of one tile: one thread per (vertex, tile) entry sums
+// w * u over its stencil nodes inside the tile (velocities staged in su) and
+// stores the partial sum in the vertex's slot.
 template <int K>
-__global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattice L, Bins B,
-                                                         const float4* __restrict__ macro,
-                                                         float4* __restrict__ partial) {
-  __shared__ float4 su[kTile * kTile * kTile];
-  const int t = blockIdx.x;
+__device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
+                                   const float4* su, int t, int x0, int y0, int z0,
+                                   float4* __restrict__ partial) {
   const int cnt = min(B.touch_cnt[t], B.cap);
-  if (cnt == 0) return;
-  int x0, y0, z0;
-  tile_origin(L, t, x0, y0, z0);
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
-    const int x = x0 + i % kTile, y = y0 + (i / kTile) % kTile, z = z0 + i / (kTile * kTile);
-    su[i] = (x < L.nx && y < L.ny && z < L.nz) ? macro[((int64_t)z * L.ny + y) * L.nx + x]
-                                                : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  __syncthreads();
   const int64_t e0 = (int64_t)t * B.cap, e1 = e0 + cnt;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int code = B.touch[e];
@@ -219,6 +188,112 @@ __global__ __launch_bounds__(256) void k_interp_partials(Cells C, Mesh M, Lattic
   }
 }
 
+// Spreading of a vertex field alone (the reverse sweep spreads cotangents
+// with it): writes body * g + the spread field, tile-major (padding slots
+// receive body * g).
+template <int K>
+__global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
+                                                const float* __restrict__ vec, float body,
+                                                float* __restrict__ F) {
+  __shared__ long long acc[3][kTile * kTile * kTile];
+  const int t = blockIdx.x;
+  int x0, y0, z0;
+  tile_origin(L, t, x0, y0, z0);
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
+    acc[0][i] = 0;
+    acc[1][i] = 0;
+    acc[2][i] = 0;
+  }
+  __syncthreads();
+  spread_tile<K>(C, M, L, B, vec, t, x0, y0, z0, acc);
+  __syncthreads();
+
+  const int64_t NP = L.np, h0 = (int64_t)t * 512;
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
+    F[h0 + i] = body * L.g[0] + (float)((double)acc[0][i] * kFixInv);
+    F[NP + h0 + i] = body * L.g[1] + (float)((double)acc[1][i] * kFixInv);
+    F[2 * NP + h0 + i] = body * L.g[2] + (float)((double)acc[2][i] * kFixInv);
+  }
+}
+
+// Which tile block b works on.  Work-groups go to the 8 XCDs round-robin by
+// block id; each XCD gets one contiguous range of tiles, walked in order, so
+// the neighbours a tile pulls boundary populations from were mostly just
+// processed on the same XCD and sit in its L2.  -1 for padding blocks.
+__device__ inline int tile_of_block(const Lattice& L, int b) {
+  const int per = (L.ntiles + 7) >> 3;
+  const int t = (b & 7) * per + (b >> 3);
+  return t < L.ntiles ? t : -1;
+}
+
+__host__ __device__ inline int tile_grid(const Lattice& L) { return ((L.ntiles + 7) >> 3) * 8; }
+
+// The fused lattice pass of one step, one work-group per tile:
+//  1. spread the vertex forces of every entry reaching the tile into LDS;
+//  2. pull-stream + collide the tile's nodes (force = body force + spread
+//     field) and store their post-collision populations, keeping (u, rho)
+//     in LDS (and writing the force and (u, rho) fields out when fields is
+//     non-zero);
+//  3. interpolate u to the tile's entries into their partial-sum slots.
+// The force and velocity fields never leave the chip.
+template <int K>
+__global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, Bins B,
+                                                   const float* __restrict__ gin,
+                                                   float* __restrict__ gout,
+                                                   float* __restrict__ F,
+                                                   float4* __restrict__ macro,
+                                                   float4* __restrict__ partial, int fields) {
+  __shared__ long long acc[3][kTile * kTile * kTile];
+  __shared__ float4 su[kTile * kTile * kTile];
+  const int t = tile_of_block(L, blockIdx.x);
+  if (t < 0) return;
+  int x0, y0, z0;
+  tile_origin(L, t, x0, y0, z0);
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
+    acc[0][i] = 0;
+    acc[1][i] = 0;
+    acc[2][i] = 0;
+  }
+  __syncthreads();
+  if (C.n > 0) spread_tile<K>(C, M, L, B, C.force, t, x0, y0, z0, acc);
+  __syncthreads();
+
+  const int64_t NP = L.np, h0 = (int64_t)t * 512;
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
+    const int x = x0 + (i & 7), y = y0 + ((i >> 3) & 7), z = z0 + (i >> 6);
+    if (x >= L.nx || y >= L.ny || z >= L.nz) {
+      su[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    float g[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      int qs;
+      const int64_t src = lbm::pull_source(L, q, x, y, z, &qs);
+      g[q] = gin[qs * NP + src];
+    }
+    const float fx = L.g[0] + (float)((double)acc[0][i] * kFixInv);
+    const float fy = L.g[1] + (float)((double)acc[1][i] * kFixInv);
+    const float fz = L.g[2] + (float)((double)acc[2][i] * kFixInv);
+    float rho, ux, uy, uz;
+    lbm::collide(g, fx, fy, fz, L.omega, rho, ux, uy, uz);
+    const float4 m = make_float4(ux, uy, uz, rho);
+    su[i] = m;
+    const int64_t h = h0 + i;
+    if (fields) {
+      macro[h] = m;
+      F[h] = fx;
+      F[NP + h] = fy;
+      F[2 * NP + h] = fz;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) gout[q * NP + h] = g[q] + lbm::wall_coeff(L, q, x, y, z) * rho;
+  }
+  if (C.n == 0) return;
+  __syncthreads();
+  interp_tile<K>(C, M, L, B, su, t, x0, y0, z0, partial);
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins B,
                                                 const float4* __restrict__ partial,
@@ -231,11 +306,6 @@ __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins
 
 }  // namespace
 
-hipError_t launch_spread(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b, float* F,
-                         hipStream_t s) {
-  return launch_spread_vec(c, m, L, b, c.force, 1.f, F, s);
-}
-
 hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                              const float* vec, float body, float* F, hipStream_t s) {
   if (L.kernel == 4)
@@ -245,15 +315,17 @@ hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, co
   return hipGetLastError();
 }
 
-hipError_t launch_interp_partials(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                                  const float4* macro, float4* partial, hipStream_t s) {
-  if ((int64_t)c.n * m.nv == 0) return hipSuccess;
+hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
+                            const float* gin, float* gout, float* F, float4* macro, float4* partial,
+                            bool fields, hipStream_t s) {
+  const dim3 grid((unsigned)tile_grid(L));
+  const int fl = fields ? 1 : 0;
   if (L.kernel == 4)
-    hipLaunchKernelGGL(k_interp_partials<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
-                       partial);
+    hipLaunchKernelGGL(k_tile_step<4>, grid, dim3(256), 0, s, c, m, L, b, gin, gout, F, macro,
+                       partial, fl);
   else
-    hipLaunchKernelGGL(k_interp_partials<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
-                       partial);
+    hipLaunchKernelGGL(k_tile_step<2>, grid, dim3(256), 0, s, c, m, L, b, gin, gout, F, macro,
+                       partial, fl);
   return hipGetLastError();
 }
 
@@ -266,23 +338,6 @@ hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const 
     hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
   else
     hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_interp_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                                const float4* macro, float4* partial, int* flags, hipStream_t s) {
-  const int64_t n = (int64_t)c.n * m.nv;
-  if (n == 0) return hipSuccess;
-  const dim3 gv((unsigned)((n + 255) / 256));
-  if (L.kernel == 4) {
-    hipLaunchKernelGGL(k_interp_partials<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
-                       partial);
-    hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
-  } else {
-    hipLaunchKernelGGL(k_interp_partials<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, macro,
-                       partial);
-    hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
-  }
   return hipGetLastError();
 }
 

@@ -82,5 +82,52 @@ __device__ inline int stream_target(int i, int x, int y, int z, int nx, int ny, 
   return i;
 }
 
+// Pull form of streaming on the tile-major lattice.  The stored state h
+// holds post-collision values; population q at node x before the next
+// collision is h_q(x - e_q), or, when x - e_q lies beyond the wall, the
+// opposite population stored at x itself (half-way bounce-back, whose
+// moving-wall term was added when it was stored).  Returns the slot in h;
+// *qs the population index.
+__host__ __device__ inline int64_t pull_source(const Lattice& L, int q, int x, int y, int z,
+                                               int* qs) {
+  constexpr int ex[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  constexpr int ey[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  constexpr int ez[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  constexpr int eo[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  int xs = x - ex[q], ys = y - ey[q], zs = z - ez[q];
+  const int wa = L.wall_axis;
+  if ((wa == 0 && (xs < 0 || xs >= L.nx)) || (wa == 1 && (ys < 0 || ys >= L.ny)) ||
+      (wa == 2 && (zs < 0 || zs >= L.nz))) {
+    *qs = eo[q];
+    return site_of(L, x, y, z);
+  }
+  xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
+  ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
+  zs = zs < 0 ? zs + L.nz : (zs >= L.nz ? zs - L.nz : zs);
+  *qs = q;
+  return site_of(L, xs, ys, zs);
+}
+
+// Which wall population q leaving node (x, y, z) crosses: 0 none, 1 the
+// lower, 2 the upper one (x + e_q beyond the wall axis' range).
+__device__ inline int wall_crossed(const Lattice& L, int q, int x, int y, int z) {
+  const int wa = L.wall_axis;
+  if (wa < 0) return 0;
+  const int e = wa == 0 ? cx[q] : (wa == 1 ? cy[q] : cz[q]);
+  const int p = (wa == 0 ? x : (wa == 1 ? y : z)) + e;
+  const int n = wa == 0 ? L.nx : (wa == 1 ? L.ny : L.nz);
+  return p < 0 ? 1 : (p >= n ? 2 : 0);
+}
+
+// Moving-wall coefficient of population q leaving node (x, y, z): when it
+// crosses a wall, the value stored for the bounce-back is post + c rho with
+// c = -6 w_q (e_q . u_wall) (Ladd); otherwise c = 0.
+__device__ inline float wall_coeff(const Lattice& L, int q, int x, int y, int z) {
+  const int side = wall_crossed(L, q, x, y, z);
+  if (side == 0) return 0.f;
+  const float* uw = side == 1 ? L.ulo : L.uhi;
+  return -6.f * wq[q] * (cx[q] * uw[0] + cy[q] * uw[1] + cz[q] * uw[2]);
+}
+
 }  // namespace lbm
 }  // namespace hc

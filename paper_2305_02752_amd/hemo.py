@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhemo.so")
 
 HC_PERIODIC, HC_WALL = 0, 1
 HC_PHI2, HC_PHI4 = 2, 4
-KERNELS = ("cell", "spread", "collide_stream", "interp", "advect")
+KERNELS = ("cell", "lattice", "advect")
 STATUS = {0: "HC_OK", 1: "HC_ERR_ARG", 2: "HC_ERR_STATE", 3: "HC_ERR_DEVICE", 4: "HC_ERR_OOM",
           5: "HC_ERR_NONFINITE", 6: "HC_ERR_UNSUPPORTED"}
 
@@ -56,6 +56,7 @@ def _declare(lib):
         "hc_read_populations": [_P, _P, i64],
         "hc_write_populations": [_P, _P, i64],
         "hc_read_macro": [_P, _P, _P, i64],
+        "hc_set_field_output": [_P, i32],
         "hc_read_force_field": [_P, _P, i64],
         "hc_read_vertices": [_P, _P, _P, _P, i64],
         "hc_write_vertices": [_P, _P, _P, i64],
@@ -210,6 +211,11 @@ class Simulation:
     def write_populations(self, g):
         g = np.ascontiguousarray(g, dtype=np.float32)
         self._check(self.lib.hc_write_populations(self.ctx, _ptr(g), g.size))
+
+    def set_field_output(self, enable: bool):
+        """Whether each step writes its force and (u, rho) fields out (for
+        read_force_field / read_macro); the step itself keeps them on chip."""
+        self._check(self.lib.hc_set_field_output(self.ctx, 1 if enable else 0))
 
     def read_macro(self):
         rho = np.empty((self.nz, self.ny, self.nx), dtype=np.float32)
