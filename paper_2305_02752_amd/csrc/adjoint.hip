@@ -224,17 +224,40 @@ __device__ inline double dotf(mem::f3 f, const float* lam, int v) {
   return (double)f.x * lam[3 * v] + (double)f.y * lam[3 * v + 1] + (double)f.z * lam[3 * v + 2];
 }
 
-// One wave per cell.  LDS: positions, tangents (= lam_{F_v}), int64
-// accumulator of the Jacobian-vector product.
-__global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const float* __restrict__ lamFv,
-                                                     float* __restrict__ lamX, double* __restrict__ dk) {
+// Sum of 4 doubles over the kAdjThreads threads of a work-group: within each
+// wave by shuffles, then across waves in a fixed order (reproducible).
+constexpr int kAdjThreads = 256;
+__device__ inline void block_sum4(double (&v)[4], double* red) {
+  for (int m = kWave / 2; m > 0; m >>= 1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] += __shfl_xor(v[j], m);
+  const int w = threadIdx.x / kWave, nw = kAdjThreads / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[j * nw + w] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j] = 0.0;
+    for (int q = 0; q < nw; ++q) v[j] += red[j * nw + q];
+  }
+}
+
+// One work-group of kAdjThreads per cell.  LDS: positions, tangents
+// (= lam_{F_v}), int64 accumulator of the Jacobian-vector product.
+__global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
+                                                              const float* __restrict__ lamFv,
+                                                              float* __restrict__ lamX,
+                                                              double* __restrict__ dk) {
   extern __shared__ long long lds64[];
+  __shared__ double red[4 * kAdjThreads / kWave];
   long long* acc = lds64;
   float* sp = reinterpret_cast<float*>(lds64 + 3 * M.nv);
   float* st = sp + 3 * M.nv;
   const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t b3 = (int64_t)c * M.nv * 3;
-  for (int i = tid; i < 3 * M.nv; i += kWave) {
+  for (int i = tid; i < 3 * M.nv; i += kAdjThreads) {
     sp[i] = C.off[b3 + i];
     st[i] = lamFv[b3 + i];
     acc[i] = 0;
@@ -242,7 +265,7 @@ __global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const floa
   __syncthreads();
   // area and volume with their directional derivatives (float64)
   double A = 0, V = 0, dA = 0, dV = 0;
-  for (int t = tid; t < M.nt; t += kWave) {
+  for (int t = tid; t < M.nt; t += kAdjThreads) {
     const int a = M.tri[3 * t], b = M.tri[3 * t + 1], e = M.tri[3 * t + 2];
     double x[3][3], dx[3][3];
     for (int d = 0; d < 3; ++d) {
@@ -271,18 +294,18 @@ __global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const floa
     V += trip(x[0], x[1], x[2]) / 6.0;
     dV += (trip(dx[0], x[1], x[2]) + trip(x[0], dx[1], x[2]) + trip(x[0], x[1], dx[2])) / 6.0;
   }
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    A += __shfl_xor(A, m);
-    V += __shfl_xor(V, m);
-    dA += __shfl_xor(dA, m);
-    dV += __shfl_xor(dV, m);
-  }
+  double av[4] = {A, V, dA, dV};
+  block_sum4(av, red);
+  A = av[0];
+  V = av[1];
+  dA = av[2];
+  dV = av[3];
   const float kl = C.k[4 * c], kb = C.k[4 * c + 1], ka = C.k[4 * c + 2], kv = C.k[4 * c + 3];
   const float a_rel = (float)((A - M.A0) / M.A0), v_rel = (float)((V - M.V0) / M.V0);
   const Dual ca = {-ka * a_rel, -ka * (float)(dA / M.A0)};
   const Dual cv = {-kv * v_rel / 6.f, -kv * (float)(dV / M.V0) / 6.f};
   double sl = 0, sb = 0, sa = 0, sv = 0;   // sum_v lam_{F_v} . F_v^(term) / k_term
-  for (int t = tid; t < M.nt; t += kWave) {
+  for (int t = tid; t < M.nt; t += kAdjThreads) {
     const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
     V3<Dual> fa, fb, fc;
     mem::tri_forces<Dual>(ldd(sp, st, ia), ldd(sp, st, ib), ldd(sp, st, ic), ca, cv, fa, fb, fc);
@@ -296,14 +319,14 @@ __global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const floa
                            pb, pc);
     sv += dotf(pa, st, ia) + dotf(pb, st, ib) + dotf(pc, st, ic);
   }
-  for (int e = tid; e < M.ne; e += kWave) {
+  for (int e = tid; e < M.ne; e += kAdjThreads) {
     const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
     const V3<Dual> f = mem::link_force<Dual>(ldd(sp, st, i), ldd(sp, st, j), M.L0[e], kl);
     add_tangent(acc, i, f);
     add_tangent(acc, j, -1.f * f);
     sl += (dotv(f, st, i) - dotv(f, st, j)) / kl;
   }
-  for (int h = tid; h < M.nh; h += kWave) {
+  for (int h = tid; h < M.nh; h += kAdjThreads) {
     const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
     const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
     V3<Dual> fi, fj, fk, fl;
@@ -315,12 +338,12 @@ __global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const floa
     add_tangent(acc, l, fl);
     sb += (dotv(fi, st, i) + dotv(fj, st, j) + dotv(fk, st, k) + dotv(fl, st, l)) / kb;
   }
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    sl += __shfl_xor(sl, m);
-    sb += __shfl_xor(sb, m);
-    sa += __shfl_xor(sa, m);
-    sv += __shfl_xor(sv, m);
-  }
+  double sk[4] = {sl, sb, sa, sv};
+  block_sum4(sk, red);
+  sl = sk[0];
+  sb = sk[1];
+  sa = sk[2];
+  sv = sk[3];
   if (tid == 0) {
     dk[4 * c] += sl;
     dk[4 * c + 1] += sb;
@@ -328,7 +351,7 @@ __global__ __launch_bounds__(64) void k_adj_membrane(Cells C, Mesh M, const floa
     dk[4 * c + 3] += sv;
   }
   __syncthreads();
-  for (int i = tid; i < 3 * M.nv; i += kWave) lamX[b3 + i] += (float)((double)acc[i] * kFixInv);
+  for (int i = tid; i < 3 * M.nv; i += kAdjThreads) lamX[b3 + i] += (float)((double)acc[i] * kFixInv);
 }
 
 // Loss (D_A - D_A*)^2 + (D_T - D_T*)^2 of every cell from its extents along
@@ -404,7 +427,7 @@ hipError_t launch_adj_membrane(const Cells& c, const Mesh& m, const float* lamFv
                                hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * 3 * (8 + 4 + 4);
-  hipLaunchKernelGGL(k_adj_membrane, dim3(c.n), dim3(kWave), lds, s, c, m, lamFv, lamX, dk);
+  hipLaunchKernelGGL(k_adj_membrane, dim3(c.n), dim3(kAdjThreads), lds, s, c, m, lamFv, lamX, dk);
   return hipGetLastError();
 }
 

@@ -198,7 +198,7 @@ hc_status one_step(hc_ctx* c) {
   C.n = c->have_cells ? c->C.n : 0;
   const bool adv = c->advect_pending;
   HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
-    return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, c->stream);
+    return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, c->stream);
   }));
   HC_TRY(timed(c, HC_K_LATTICE, "lattice pass", [&] {
     return launch_tile_step(C, c->M, c->L, c->B, c->pops[c->cur], c->pops[c->cur ^ 1], c->F,
@@ -259,10 +259,11 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   return p;
 }
 
-// One forward step of the recomputed segment, from slot i to slot i + 1,
-// keeping everything the reverse sweep reads.  It runs the same kernels as
-// the forward step (field output on), so a recomputed state equals the
-// forward one bit for bit.
+// One forward step of the recomputed segment at slot i, keeping everything
+// the reverse sweep reads.  It runs the forward step's kernels (field output
+// on), so a recomputed state equals the forward one bit for bit.  The move
+// that produces slot i's positions from slot i - 1 runs inside slot i's
+// per-cell kernel, as in the forward step.
 hc_status adj_forward_into(hc_ctx* c, int i) {
   const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   Cells Ci = c->C;
@@ -271,15 +272,13 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   Ci.vel = c->vel_scratch;
   float* Fi = c->sg_F + i * 3 * N;
   float4* Mi = c->sg_macro + i * N;
-  HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, false, c->stream),
+  const float* prev = i > 0 ? c->sg_off + (i - 1) * X : nullptr;
+  HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev,
+                                   c->stream),
                "cell step"));
   HC_TRY(check(c, launch_tile_step(Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
                                    Fi, Mi, c->partial, true, c->stream),
                "lattice pass"));
-  Cells Cn = Ci;
-  Cn.off = c->sg_off + (i + 1) * X;
-  HC_TRY(copy_d2d(c, Cn.off, Ci.off, (size_t)X * 4));
-  HC_TRY(check(c, launch_advect(Cn, c->M, c->L, c->B, c->partial, c->B.flags, c->stream), "advect"));
   return HC_OK;
 }
 
@@ -494,6 +493,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   HC_TRY(copy_h2d(c, (void*)M.theta0, m.theta0.data(), m.theta0.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
   HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
+  HC_TRY(check(c, launch_fill_i32(B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   HC_TRY(check(c, launch_init_equilibrium(c->pops[0], 1.f, 0.f, 0.f, 0.f, c->L, c->stream), "init"));
   return sync(c, "bind");
 }
@@ -516,6 +516,7 @@ hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float*
   c->C.n = n;
   c->have_cells = n > 0;
   c->advect_pending = false;
+  HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
   return sync(c, "set_cells");
 }
@@ -649,9 +650,12 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
   HC_TRY(need_ws(c));
   if (!touch_ptr || !cell_ptr) return fail(c, HC_ERR_ARG, "null pointer array");
   const int NT = c->L.ntiles;
+  HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, NT, c->stream), "clear tile lists"));
   HC_TRY(check(c, launch_bin_vertices(c->C, c->M, c->L, c->B, c->stream), "binning"));
   HC_TRY(check(c, launch_touch_csr(c->L, c->B, c->cell_cnt, c->touch_ptr, c->touch_csr, c->stream),
                "tile lists"));
+  // the lists are copied out: leave zero counts for the next step's binning
+  HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, NT, c->stream), "clear tile lists"));
   HC_TRY(check(c, launch_sort_segments(c->touch_ptr, c->touch_csr, c->B.slot, NT, c->stream),
                "sort"));
   HC_TRY(check(c, launch_bin_cells(c->C, c->M, c->L, c->cell_cnt, c->cell_ptr, c->cell_rank,

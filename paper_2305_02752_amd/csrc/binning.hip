@@ -208,10 +208,12 @@ hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s
   return hipGetLastError();
 }
 
+// The tile-list counts must be zero on entry: every kernel that consumes
+// the lists (the lattice pass, the vector spread) zeroes its tile's count
+// when done, and the API zeroes them at bind time and after a read-out.
 hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                                hipStream_t s) {
-  hipError_t e = launch_fill_i32(b.touch_cnt, 0, L.ntiles, s);
-  if (e != hipSuccess || c.n == 0) return e;
+  if (c.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bin_vertices, dim3(c.n), dim3(256), 0, s, c, m, L, b);
   return hipGetLastError();
 }

@@ -17,7 +17,8 @@ constexpr int kCellThreads = 256;
 template <int K>
 __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
                                                            const float4* __restrict__ partial,
-                                                           int* __restrict__ flags, int advect) {
+                                                           int* __restrict__ flags, int advect,
+                                                           const float* __restrict__ src) {
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   if (advect) {
     for (int vl = tid; vl < M.nv; vl += kCellThreads) {
       float nx[3];
-      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx);
+      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src);
       sp[3 * vl] = nx[0];
       sp[3 * vl + 1] = nx[1];
       sp[3 * vl + 2] = nx[2];
@@ -43,17 +44,18 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
 
 }  // namespace
 
+// Tile-list counts must be zero on entry (see launch_bin_vertices).
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                            const float4* partial, int* flags, bool advect, hipStream_t s) {
-  hipError_t e = launch_fill_i32(b.touch_cnt, 0, L.ntiles, s);
-  if (e != hipSuccess || c.n == 0) return e;
+                            const float4* partial, int* flags, bool advect, const float* src,
+                            hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * 3 * (sizeof(long long) + sizeof(float));
   if (L.kernel == 4)
     hipLaunchKernelGGL(k_cell_step<4>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0);
+                       flags, advect ? 1 : 0, src);
   else
     hipLaunchKernelGGL(k_cell_step<2>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0);
+                       flags, advect ? 1 : 0, src);
   return hipGetLastError();
 }
 

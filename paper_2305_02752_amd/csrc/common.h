@@ -154,8 +154,10 @@ hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             const float* gin, float* gout, float* F, float4* macro, float4* partial,
                             bool fields, hipStream_t s);
 // fused per-cell kernel: [advect of the pending step] + membrane + binning
+// (src: offsets to move from, or null to move in place)
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                            const float4* partial, int* flags, bool advect, hipStream_t s);
+                            const float4* partial, int* flags, bool advect, const float* src,
+                            hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // stored (pull-form) state of a uniform equilibrium on the tile-major lattice
 hipError_t launch_init_equilibrium(float* g, float rho0, float ux, float uy, float uz,

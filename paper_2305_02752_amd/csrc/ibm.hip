@@ -207,6 +207,7 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
   __syncthreads();
   spread_tile<K>(C, M, L, B, vec, t, x0, y0, z0, acc);
   __syncthreads();
+  if (threadIdx.x == 0) B.touch_cnt[t] = 0;   // consumed: zero for the next binning
 
   const int64_t NP = L.np, h0 = (int64_t)t * 512;
   for (int i = threadIdx.x; i < kTile * kTile * kTile; i += blockDim.x) {
@@ -292,6 +293,8 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
   if (C.n == 0) return;
   __syncthreads();
   interp_tile<K>(C, M, L, B, su, t, x0, y0, z0, partial);
+  __syncthreads();   // every thread has read the count: leave it zero for the next binning
+  if (threadIdx.x == 0) B.touch_cnt[t] = 0;
 }
 
 template <int K>

@@ -25,12 +25,13 @@ __device__ inline float stencil_w(float f, int k) {
 
 // Vertex velocity = tile partials summed in slot order (fixed, so the result
 // is reproducible) + stencil nodes beyond a wall at the wall velocity; then
-// X += U.  The new offset is also returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
+// X += U, reading X from src when given (else in place) and writing C.off.
+// The new offset is also returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
 // the wall contributes its axis weight times the wall velocity.
 template <int K>
 __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                      const float4* __restrict__ partial, int* __restrict__ flags,
-                                     int64_t v, float (&nxyz)[3]) {
+                                     int64_t v, float (&nxyz)[3], const float* src = nullptr) {
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
   const int nt = B.ntouch[v];
   for (int j = 0; j < nt; ++j) {
@@ -40,7 +41,8 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
     Uz += q.z;
   }
   float* o = C.off + v * 3;
-  const float ox = o[0], oy = o[1], oz = o[2];
+  const float* oi = (src ? src : C.off) + v * 3;
+  const float ox = oi[0], oy = oi[1], oz = oi[2];
   if (L.wall_axis >= 0) {
     const int d = L.wall_axis;
     const int c = (int)(v / M.nv);
