@@ -48,18 +48,15 @@ def make_model(lat, rest_pos, tri, k, traction=None) -> Model:
                  traction=None if traction is None else np.asarray(traction, dtype=np.float64))
 
 
-def step(m: Model, f: np.ndarray, X: np.ndarray):
-    """Advance populations f [19, nz, ny, nx] and positions X [C, V, 3] by one step.
-
-    Returns (f_new, X_new, info) where info holds the intermediate fields.
-    """
+def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray):
+    """Steps 2-5 with given vertex forces Fv [C, V, 3]: returns the streamed
+    populations, the interpolated vertex velocity U and the intermediate
+    fields."""
     nx, ny, nz = m.dims
     C = X.shape[0]
     if C:
-        Fv = membrane.forces(X, m.k, m.topo, m.rest, m.traction)
         F = ibm.spread(X.reshape(-1, 3), Fv.reshape(-1, 3), m.dims, m.bc, m.kernel)
     else:
-        Fv = np.zeros_like(X)
         F = np.zeros((3, nz, ny, nx))
     for d in range(3):
         F[d] += m.body_force[d]
@@ -71,7 +68,17 @@ def step(m: Model, f: np.ndarray, X: np.ndarray):
         U = np.zeros_like(X)
     post = lattice.collide(f, rho, u, F, m.tau)
     f_new = lattice.stream(post, rho, m.bc, m.wall_u_lo, m.wall_u_hi)
-    return f_new, X + U, {"Fv": Fv, "F": F, "rho": rho, "u": u, "U": U}
+    return f_new, U, {"Fv": Fv, "F": F, "rho": rho, "u": u, "U": U}
+
+
+def step(m: Model, f: np.ndarray, X: np.ndarray):
+    """Advance populations f [19, nz, ny, nx] and positions X [C, V, 3] by one step.
+
+    Returns (f_new, X_new, info) where info holds the intermediate fields.
+    """
+    Fv = membrane.forces(X, m.k, m.topo, m.rest, m.traction) if X.shape[0] else np.zeros_like(X)
+    f_new, U, info = fluid_step(m, f, X, Fv)
+    return f_new, X + U, info
 
 
 def run(m: Model, f, X, n: int):
