@@ -171,10 +171,26 @@ hc_status hc_read_bins(hc_ctx* ctx, int32_t* owner, int32_t* touch_ptr, int32_t*
                        int64_t cap_touch, int32_t* cell_ptr, int32_t* cells, int64_t cap_cells);
 hc_status hc_num_tiles(const hc_ctx* ctx, int32_t* n_tiles);
 
-/* Checkpoint (Sec. 2.6: pause, save, continue): populations, cells, step. */
+/* Checkpoint (Sec. 2.6: pause, save, continue): the step counter and
+ * integration settings, the stored lattice state (the library's own
+ * layout), cell origins and offsets, the last vertex velocities and the
+ * held vertex forces -- everything a resumed run needs to continue bit for
+ * bit, also in the middle of a force-refresh interval.  The buffer is
+ * opaque to the caller; restore checks the cell count. */
 hc_status hc_checkpoint_size(const hc_ctx* ctx, size_t* bytes);
 hc_status hc_checkpoint_save(hc_ctx* ctx, void* host, size_t bytes);
 hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
+
+/* Cell integration with separated time scales (Sec. 2.6: cells move by
+ * Euler or Adams-Bashforth, and the constitutive model is evaluated less
+ * often than the fluid is advanced).  force_every >= 1: the membrane forces
+ * (with the pole traction) are recomputed at every force_every-th step,
+ * counted from hc_set_cells, and held in between.  scheme: HC_EULER
+ * (X += U) or HC_AB2 (X += 3/2 U^n - 1/2 U^{n-1}; the first move after
+ * hc_set_cells or hc_write_vertices is an Euler move).  Defaults: 1,
+ * HC_EULER.  The adjoint calls require the defaults. */
+enum { HC_EULER = 0, HC_AB2 = 1 };
+hc_status hc_set_integration(hc_ctx* ctx, int32_t force_every, int32_t scheme);
 
 /* Per-kernel timing.  hc_profile(ctx, 1) clears the record and brackets
  * every subsequent launch of the step with events on the context stream;

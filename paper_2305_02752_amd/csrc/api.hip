@@ -60,6 +60,11 @@ struct hc_ctx {
   // the next step's per-cell kernel, or in flush() before the state is seen)
   bool advect_pending = false;
   bool fields = true;          // write the force and (u, rho) fields each step
+  // cell integration (Sec. 2.6): membrane forces every force_every steps,
+  // Euler or Adams-Bashforth moves; have_prev: C.vel holds the previous U
+  int force_every = 1;
+  int scheme = HC_EULER;
+  bool have_prev = false;
   // optional per-kernel timing with events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -191,15 +196,21 @@ hc_status copy_d2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 // One coupled step.  The vertex move that closes the step (interpolated
-// velocity, explicit Euler) is left pending: the next step's per-cell kernel
-// applies it before the membrane forces, or flush() applies it on its own.
+// velocity, Euler or Adams-Bashforth) is left pending: the next step's
+// per-cell kernel applies it before the membrane forces, or flush() applies
+// it on its own.  The membrane forces are recomputed every force_every
+// steps and held in between.
 hc_status one_step(hc_ctx* c) {
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
   const bool adv = c->advect_pending;
+  const bool ab2 = adv && c->scheme == HC_AB2 && c->have_prev;
+  const bool refresh = c->step % c->force_every == 0;
   HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
-    return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, c->stream);
+    return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, refresh, ab2,
+                            c->stream);
   }));
+  if (adv) c->have_prev = true;
   HC_TRY(timed(c, HC_K_LATTICE, "lattice pass", [&] {
     return launch_tile_step(C, c->M, c->L, c->B, c->pops[c->cur], c->pops[c->cur ^ 1], c->F,
                             c->macro, c->partial, c->fields, c->stream);
@@ -214,8 +225,10 @@ hc_status one_step(hc_ctx* c) {
 hc_status flush(hc_ctx* c) {
   if (!c->advect_pending) return HC_OK;
   c->advect_pending = false;
+  const bool ab2 = c->scheme == HC_AB2 && c->have_prev;
+  c->have_prev = true;
   return timed(c, HC_K_ADVECT, "advect", [&] {
-    return launch_advect(c->C, c->M, c->L, c->B, c->partial, c->B.flags, c->stream);
+    return launch_advect(c->C, c->M, c->L, c->B, c->partial, c->B.flags, ab2, c->stream);
   });
 }
 
@@ -273,8 +286,8 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   float* Fi = c->sg_F + i * 3 * N;
   float4* Mi = c->sg_macro + i * N;
   const float* prev = i > 0 ? c->sg_off + (i - 1) * X : nullptr;
-  HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev,
-                                   c->stream),
+  HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev, true,
+                                   false, c->stream),
                "cell step"));
   HC_TRY(check(c, launch_tile_step(Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
                                    Fi, Mi, c->partial, true, c->stream),
@@ -516,6 +529,7 @@ hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float*
   c->C.n = n;
   c->have_cells = n > 0;
   c->advect_pending = false;
+  c->have_prev = false;
   HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
   return sync(c, "set_cells");
@@ -627,6 +641,7 @@ hc_status hc_write_vertices(hc_ctx* c, const int32_t* origin, const float* offse
   if (n_cells != c->C.n || !origin || !offsets) return fail(c, HC_ERR_ARG, "cell count mismatch");
   HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n_cells * 12));
   HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n_cells * c->hm.nv * 12));
+  c->have_prev = false;   // new positions: an Adams-Bashforth run restarts with Euler
   return sync(c, "write vertices");
 }
 
@@ -683,9 +698,15 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
   return HC_OK;
 }
 
+// Checkpoint layout: header {step, cells, have_prev, force_every, scheme,
+// 0} (int64 x 2, int32 x 4), then the stored populations, origins, offsets,
+// vertex velocities and held vertex forces.
+constexpr size_t kCkHeader = 32;
+
 hc_status hc_checkpoint_size(const hc_ctx* c, size_t* bytes) {
   if (!c || !bytes) return HC_ERR_ARG;
-  *bytes = 16 + (size_t)19 * c->L.np * 4 + (size_t)c->C.n * 12 + (size_t)c->C.n * c->hm.nv * 12;
+  const size_t X = (size_t)c->C.n * c->hm.nv * 12;
+  *bytes = kCkHeader + (size_t)19 * c->L.np * 4 + (size_t)c->C.n * 12 + 3 * X;
   return HC_OK;
 }
 
@@ -694,15 +715,23 @@ hc_status hc_checkpoint_save(hc_ctx* c, void* host, size_t bytes) {
   size_t need;
   hc_checkpoint_size(c, &need);
   if (!host || bytes < need) return fail(c, HC_ERR_ARG, "checkpoint buffer too small");
+  HC_TRY(flush(c));
   char* p = static_cast<char*>(host);
-  int64_t hdr[2] = {c->step, c->C.n};
-  std::memcpy(p, hdr, 16);
-  p += 16;
+  const int64_t h64[2] = {c->step, c->C.n};
+  const int32_t h32[4] = {c->have_prev ? 1 : 0, c->force_every, c->scheme, 0};
+  std::memcpy(p, h64, 16);
+  std::memcpy(p + 16, h32, 16);
+  p += kCkHeader;
+  const size_t X = (size_t)c->C.n * c->hm.nv * 12;
   HC_TRY(copy_d2h(c, p, c->pops[c->cur], (size_t)19 * c->L.np * 4));
   p += (size_t)19 * c->L.np * 4;
   HC_TRY(copy_d2h(c, p, c->C.origin, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
-  HC_TRY(copy_d2h(c, p, c->C.off, (size_t)c->C.n * c->hm.nv * 12));
+  HC_TRY(copy_d2h(c, p, c->C.off, X));
+  p += X;
+  HC_TRY(copy_d2h(c, p, c->C.vel, X));
+  p += X;
+  HC_TRY(copy_d2h(c, p, c->C.force, X));
   return sync(c, "checkpoint save");
 }
 
@@ -712,17 +741,40 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   hc_checkpoint_size(c, &need);
   if (!host || bytes < need) return fail(c, HC_ERR_ARG, "checkpoint buffer too small");
   const char* p = static_cast<const char*>(host);
-  int64_t hdr[2];
-  std::memcpy(hdr, p, 16);
-  if (hdr[1] != c->C.n) return fail(c, HC_ERR_ARG, "checkpoint cell count differs");
-  p += 16;
+  int64_t h64[2];
+  int32_t h32[4];
+  std::memcpy(h64, p, 16);
+  std::memcpy(h32, p + 16, 16);
+  if (h64[1] != c->C.n) return fail(c, HC_ERR_ARG, "checkpoint cell count differs");
+  if (h32[1] < 1 || (h32[2] != HC_EULER && h32[2] != HC_AB2))
+    return fail(c, HC_ERR_ARG, "checkpoint header is not valid");
+  p += kCkHeader;
+  const size_t X = (size_t)c->C.n * c->hm.nv * 12;
   HC_TRY(copy_h2d(c, c->pops[c->cur], p, (size_t)19 * c->L.np * 4));
   p += (size_t)19 * c->L.np * 4;
   HC_TRY(copy_h2d(c, c->C.origin, p, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
-  HC_TRY(copy_h2d(c, c->C.off, p, (size_t)c->C.n * c->hm.nv * 12));
-  c->step = hdr[0];
+  HC_TRY(copy_h2d(c, c->C.off, p, X));
+  p += X;
+  HC_TRY(copy_h2d(c, c->C.vel, p, X));
+  p += X;
+  HC_TRY(copy_h2d(c, c->C.force, p, X));
+  c->step = h64[0];
+  c->have_prev = h32[0] != 0;
+  c->force_every = h32[1];
+  c->scheme = h32[2];
+  c->advect_pending = false;
   return sync(c, "checkpoint restore");
+}
+
+hc_status hc_set_integration(hc_ctx* c, int32_t force_every, int32_t scheme) {
+  if (!c) return HC_ERR_ARG;
+  if (force_every < 1) return fail(c, HC_ERR_ARG, "force_every must be >= 1");
+  if (scheme != HC_EULER && scheme != HC_AB2) return fail(c, HC_ERR_ARG, "scheme must be HC_EULER or HC_AB2");
+  HC_TRY(flush(c));
+  c->force_every = force_every;
+  c->scheme = scheme;
+  return HC_OK;
 }
 
 hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
@@ -756,6 +808,8 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(c, HC_ERR_ARG, "workspace not 256-aligned");
   if (c->L.kernel != HC_PHI4)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
+  if (c->force_every != 1 || c->scheme != HC_EULER)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int ck = std::min(ckpt_every, n_steps);
   const AdjPlan p = adj_plan(c, n_steps, ck);
   if (bytes < p.total) return fail(c, HC_ERR_OOM, "adjoint workspace too small");
@@ -792,6 +846,8 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
   HC_TRY(need_ws(c));
   if (!c->adj_ws) return fail(c, HC_ERR_STATE, "no adjoint workspace bound");
   if (!c->have_cells || !targets || !loss) return fail(c, HC_ERR_STATE, "adjoint: no cells or targets");
+  if (c->force_every != 1 || c->scheme != HC_EULER)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int64_t P = 19 * c->L.np, X = (int64_t)c->C.n * c->hm.nv * 3;
   HC_TRY(copy_h2d(c, c->targets, targets, (size_t)c->C.n * 16));
   for (int s = 0; s < c->adj_n; ++s) {

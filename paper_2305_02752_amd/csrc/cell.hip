@@ -1,7 +1,9 @@
 // Fused per-cell kernel of the single-lattice step: one work-group per cell
 // (1) closes the previous step's interpolation and moves the vertices
 //     (Sec. 2.6 explicit Euler), when one is pending;
-// (2) computes the membrane forces of the new positions (Sec. 2.3 force sum);
+// (2) computes the membrane forces of the new positions (Sec. 2.3 force
+//     sum) when they are due (refresh); between refreshes the forces of
+//     the last one are held (Sec. 2.6 time-scale separation);
 // (3) bins the cell's vertices to the tiles their IBM stencils reach.
 // All three read the same 642 positions, so the cell is loaded once and its
 // latency-bound steps overlap across the resident work-groups.
@@ -18,7 +20,8 @@ template <int K>
 __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
                                                            const float4* __restrict__ partial,
                                                            int* __restrict__ flags, int advect,
-                                                           const float* __restrict__ src) {
+                                                           const float* __restrict__ src,
+                                                           int refresh, int ab2) {
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
@@ -29,16 +32,21 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   if (advect) {
     for (int vl = tid; vl < M.nv; vl += kCellThreads) {
       float nx[3];
-      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src);
+      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src, ab2 != 0);
       sp[3 * vl] = nx[0];
       sp[3 * vl + 1] = nx[1];
       sp[3 * vl + 2] = nx[2];
     }
+  } else {
+    for (int i = tid; i < 3 * M.nv; i += kCellThreads) sp[i] = C.off[b3 + i];
   }
-  // after a move the new offsets are staged in sp already
-  mem::membrane_cell(M, advect ? nullptr : C.off + b3, C.k + 4 * c,
-                     C.traction ? C.traction + 3 * c : nullptr, C.force + b3, C.area + c,
-                     C.volume + c, acc, sp, red, tid, kCellThreads);
+  if (refresh) {
+    // offsets staged in sp (the call synchronises before reading them)
+    mem::membrane_cell(M, nullptr, C.k + 4 * c, C.traction ? C.traction + 3 * c : nullptr,
+                       C.force + b3, C.area + c, C.volume + c, acc, sp, red, tid, kCellThreads);
+  } else {
+    __syncthreads();   // forces held from the last refresh; sp complete for the binning
+  }
   bin::bin_cell(C, M, L, B, c, sp, keys, count, base, tid, kCellThreads);
 }
 
@@ -47,15 +55,15 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
 // Tile-list counts must be zero on entry (see launch_bin_vertices).
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, const float* src,
-                            hipStream_t s) {
+                            bool refresh, bool ab2, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * 3 * (sizeof(long long) + sizeof(float));
   if (L.kernel == 4)
     hipLaunchKernelGGL(k_cell_step<4>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0, src);
+                       flags, advect ? 1 : 0, src, refresh ? 1 : 0, ab2 ? 1 : 0);
   else
     hipLaunchKernelGGL(k_cell_step<2>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0, src);
+                       flags, advect ? 1 : 0, src, refresh ? 1 : 0, ab2 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -145,19 +145,20 @@ hipError_t launch_loss_seed(const Cells& c, const Mesh& m, const double* targets
                             float* lamX, hipStream_t s);
 hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
-// interpolation close (tile partials summed per vertex) + explicit Euler move
+// interpolation close (tile partials summed per vertex) + Euler or AB2 move
 hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                         const float4* partial, int* flags, hipStream_t s);
+                         const float4* partial, int* flags, bool ab2, hipStream_t s);
 // fused lattice pass: spread + collide/stream + interpolation partials;
 // with fields set it also writes the force field F and (u, rho) to macro
 hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float* gin, float* gout, float* F, float4* macro, float4* partial,
                             bool fields, hipStream_t s);
 // fused per-cell kernel: [advect of the pending step] + membrane + binning
-// (src: offsets to move from, or null to move in place)
+// (src: offsets to move from, or null to move in place; refresh: compute
+// the membrane forces, else hold the stored ones; ab2: Adams-Bashforth move)
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, const float* src,
-                            hipStream_t s);
+                            bool refresh, bool ab2, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // stored (pull-form) state of a uniform equilibrium on the tile-major lattice
 hipError_t launch_init_equilibrium(float* g, float rho0, float ux, float uy, float uz,

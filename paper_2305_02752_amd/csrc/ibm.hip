@@ -300,11 +300,11 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
 template <int K>
 __global__ __launch_bounds__(256) void k_advect(Cells C, Mesh M, Lattice L, Bins B,
                                                 const float4* __restrict__ partial,
-                                                int* __restrict__ flags) {
+                                                int* __restrict__ flags, int ab2) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
   float nx[3];
-  ibmd::advect_vertex<K>(C, M, L, B, partial, flags, v, nx);
+  ibmd::advect_vertex<K>(C, M, L, B, partial, flags, v, nx, nullptr, ab2 != 0);
 }
 
 }  // namespace
@@ -333,14 +333,15 @@ hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, con
 }
 
 hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
-                         const float4* partial, int* flags, hipStream_t s) {
+                         const float4* partial, int* flags, bool ab2, hipStream_t s) {
   const int64_t n = (int64_t)c.n * m.nv;
   if (n == 0) return hipSuccess;
   const dim3 gv((unsigned)((n + 255) / 256));
+  const int a2 = ab2 ? 1 : 0;
   if (L.kernel == 4)
-    hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
+    hipLaunchKernelGGL(k_advect<4>, gv, dim3(256), 0, s, c, m, L, b, partial, flags, a2);
   else
-    hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags);
+    hipLaunchKernelGGL(k_advect<2>, gv, dim3(256), 0, s, c, m, L, b, partial, flags, a2);
   return hipGetLastError();
 }
 

@@ -25,13 +25,16 @@ __device__ inline float stencil_w(float f, int k) {
 
 // Vertex velocity = tile partials summed in slot order (fixed, so the result
 // is reproducible) + stencil nodes beyond a wall at the wall velocity; then
-// X += U, reading X from src when given (else in place) and writing C.off.
-// The new offset is also returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
+// X += U (Euler) or X += 3/2 U - 1/2 U_prev (second-order Adams-Bashforth,
+// U_prev = the velocity stored by the previous move), reading X from src
+// when given (else in place) and writing C.off.  The new offset is also
+// returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
 // the wall contributes its axis weight times the wall velocity.
 template <int K>
 __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                      const float4* __restrict__ partial, int* __restrict__ flags,
-                                     int64_t v, float (&nxyz)[3], const float* src = nullptr) {
+                                     int64_t v, float (&nxyz)[3], const float* src = nullptr,
+                                     bool ab2 = false) {
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
   const int nt = B.ntouch[v];
   for (int j = 0; j < nt; ++j) {
@@ -61,9 +64,15 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
     Uy += wlo * L.ulo[1] + whi * L.uhi[1];
     Uz += wlo * L.ulo[2] + whi * L.uhi[2];
   }
-  const float nx = ox + Ux, ny = oy + Uy, nz = oz + Uz;
-  if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
   float* vo = C.vel + v * 3;
+  float dx = Ux, dy = Uy, dz = Uz;
+  if (ab2) {
+    dx = 1.5f * Ux - 0.5f * vo[0];
+    dy = 1.5f * Uy - 0.5f * vo[1];
+    dz = 1.5f * Uz - 0.5f * vo[2];
+  }
+  const float nx = ox + dx, ny = oy + dy, nz = oz + dz;
+  if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
   vo[0] = Ux;
   vo[1] = Uy;
   vo[2] = Uz;

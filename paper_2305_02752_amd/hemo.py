@@ -57,6 +57,7 @@ def _declare(lib):
         "hc_write_populations": [_P, _P, i64],
         "hc_read_macro": [_P, _P, _P, i64],
         "hc_set_field_output": [_P, i32],
+        "hc_set_integration": [_P, i32, i32],
         "hc_read_force_field": [_P, _P, i64],
         "hc_read_vertices": [_P, _P, _P, _P, i64],
         "hc_write_vertices": [_P, _P, _P, i64],
@@ -211,6 +212,12 @@ class Simulation:
     def write_populations(self, g):
         g = np.ascontiguousarray(g, dtype=np.float32)
         self._check(self.lib.hc_write_populations(self.ctx, _ptr(g), g.size))
+
+    def set_integration(self, force_every: int = 1, scheme: str = "euler"):
+        """Membrane forces every `force_every` steps (held in between) and
+        Euler or second-order Adams-Bashforth ("ab2") vertex moves."""
+        code = {"euler": 0, "ab2": 1}[scheme]
+        self._check(self.lib.hc_set_integration(self.ctx, int(force_every), code))
 
     def set_field_output(self, enable: bool):
         """Whether each step writes its force and (u, rho) fields out (for
