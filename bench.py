@@ -114,6 +114,25 @@ def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int = 10):
+    """The same suspension with separated cell time scales: membrane forces
+    every `force_every` steps (held in between), Adams-Bashforth moves."""
+    sim.set_integration(force_every, "ab2")
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.set_integration(1, "euler")
+    return {"force_every": force_every, "scheme": "ab2", "steps": steps,
+            "ms_per_step": dt / steps * 1e3, "MLUPS": n_sites * steps / dt / 1e6,
+            "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
+
+
 def bench_batched(torch, seed: int = 3, steps: int = 2000, warmup: int = 20):
     """Batched calibration workload: 256 single-cell boxes (sides U{24..48})
     advanced together, one persistent launch per run, tiling autotuned."""
@@ -277,6 +296,11 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_s * 1e3}
 
+    tss = None
+    if not args.no_extra:
+        tss = bench_separated(sim, n_sites, args.warmup, args.steps)
+        log(f"separated time scales (forces every {tss['force_every']}, {tss['scheme']}): "
+            f"{tss['ms_per_step']:.3f} ms/step, {tss['MLUPS']:.0f} MLUPS")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -319,6 +343,7 @@ def main():
         "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "separated_time_scales": tss,
         "batched_calibration": batched,
         "adjoint": adj,
     }

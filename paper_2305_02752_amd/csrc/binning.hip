@@ -21,10 +21,13 @@ __device__ inline int wrap(int p, int n) {
 }
 
 __global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
+  extern __shared__ unsigned short slots[];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
   const int c = blockIdx.x;
-  bin::bin_cell(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, threadIdx.x,
-                blockDim.x);
+  unsigned short* srank = slots;
+  unsigned char* shash = reinterpret_cast<unsigned char*>(slots + (size_t)M.nv * L.max_touch);
+  bin::bin_cell(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, srank, shash,
+                threadIdx.x, blockDim.x);
 }
 
 // Copy the fixed-capacity tile lists into CSR form (read-out path).
@@ -214,7 +217,8 @@ hipError_t launch_scan(const int* cnt, int* ptr, int* sums, int n, hipStream_t s
 hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                                hipStream_t s) {
   if (c.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin_vertices, dim3(c.n), dim3(256), 0, s, c, m, L, b);
+  const size_t lds = (size_t)m.nv * bin::slot_lds_per_vertex(L.max_touch);
+  hipLaunchKernelGGL(k_bin_vertices, dim3(c.n), dim3(256), lds, s, c, m, L, b);
   return hipGetLastError();
 }
 

@@ -54,16 +54,20 @@ __device__ inline int slot_tile(const Lattice& L, const int (&T)[3][3], const in
 
 constexpr int kHash = 256;   // distinct tiles one cell may reach
 
+// LDS bytes per vertex that bin_cell needs for its slot records.
+__host__ __device__ inline int slot_lds_per_vertex(int max_touch) { return 3 * max_touch; }
+
 // One work-group per cell.  Every (vertex, reached tile) pair gets a local
 // rank in an LDS hash table keyed by tile; then one global atomic per
 // distinct tile reserves a contiguous block of that tile's list, and the
 // pairs are written at block base + local rank.  Tile lists have a fixed
 // capacity of B.cap entries; an overflow raises flags[1] bit 4.
 // pos: the cell's vertex offsets [nv][3] (global or LDS); keys, count and
-// base: LDS arrays of kHash ints.
+// base: LDS arrays of kHash ints; srank / shash: LDS [nv * max_touch]
+// records of each pair's rank and hash slot (rank 0xffff: no slot).
 __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B, int c,
-                                const float* pos, int* keys, int* count, int* base, int tid,
-                                int nthr) {
+                                const float* pos, int* keys, int* count, int* base,
+                                unsigned short* srank, unsigned char* shash, int tid, int nthr) {
   for (int i = tid; i < kHash; i += nthr) {
     keys[i] = -1;
     count[i] = 0;
@@ -84,16 +88,23 @@ __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L,
       int h = (int)(((unsigned)tile * 2654435761u) >> 24);
       int probe = 0;
       for (; probe < kHash; ++probe) {
-        const int prev = atomicCAS(&keys[h], -1, tile);
-        if (prev == -1 || prev == tile) break;
+        // nearly every lookup finds a key already present: read before CAS
+        const int cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+        if (cur == tile) break;
+        if (cur == -1) {
+          const int prev = atomicCAS(&keys[h], -1, tile);
+          if (prev == -1 || prev == tile) break;
+        }
         h = (h + 1) & (kHash - 1);
       }
+      const int s = vl * L.max_touch + j;
       if (probe == kHash) {
         atomicOr(&B.flags[1], 8);
-        B.slot[v * L.max_touch + j] = -1;
+        srank[s] = 0xffff;
         continue;
       }
-      B.slot[v * L.max_touch + j] = (h << 16) | atomicAdd(&count[h], 1);
+      srank[s] = (unsigned short)atomicAdd(&count[h], 1);
+      shash[s] = (unsigned char)h;
     }
   }
   __syncthreads();
@@ -107,15 +118,14 @@ __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L,
     const int64_t v = (int64_t)c * M.nv + vl;
     const int ntouch = B.ntouch[v];
     for (int j = 0; j < ntouch; ++j) {
-      const int packed = B.slot[v * L.max_touch + j];
-      if (packed < 0) continue;
-      const int h = packed >> 16;
-      const int pos = base[h] + (packed & 0xffff);
-      if (pos < B.cap) B.touch[(int64_t)keys[h] * B.cap + pos] = (int)(v * 32 + j);
+      const int s = vl * L.max_touch + j;
+      if (srank[s] == 0xffff) continue;
+      const int h = shash[s];
+      const int p = base[h] + srank[s];
+      if (p < B.cap) B.touch[(int64_t)keys[h] * B.cap + p] = (int)(v * 32 + j);
     }
   }
 }
-
 
 }  // namespace bin
 }  // namespace hc

@@ -7,6 +7,8 @@
 // (3) bins the cell's vertices to the tiles their IBM stencils reach.
 // All three read the same 642 positions, so the cell is loaded once and its
 // latency-bound steps overlap across the resident work-groups.
+#include <algorithm>
+
 #include "binning_dev.h"
 #include "ibm_dev.h"
 #include "membrane_dev.h"
@@ -25,8 +27,12 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
+  // LDS: [membrane accumulator, later the binning's slot records][offsets]
+  const int region = max(24, bin::slot_lds_per_vertex(L.max_touch)) * M.nv;   // bytes
   long long* acc = lds64;
-  float* sp = reinterpret_cast<float*>(lds64 + 3 * M.nv);
+  unsigned short* srank = reinterpret_cast<unsigned short*>(lds64);
+  unsigned char* shash = reinterpret_cast<unsigned char*>(srank + (size_t)M.nv * L.max_touch);
+  float* sp = reinterpret_cast<float*>(reinterpret_cast<char*>(lds64) + ((region + 7) & ~7));
   const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t b3 = (int64_t)c * M.nv * 3;
   if (advect) {
@@ -47,7 +53,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   } else {
     __syncthreads();   // forces held from the last refresh; sp complete for the binning
   }
-  bin::bin_cell(C, M, L, B, c, sp, keys, count, base, tid, kCellThreads);
+  __syncthreads();   // the accumulator is free: its space takes the slot records
+  bin::bin_cell(C, M, L, B, c, sp, keys, count, base, srank, shash, tid, kCellThreads);
 }
 
 }  // namespace
@@ -57,7 +64,8 @@ hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             const float4* partial, int* flags, bool advect, const float* src,
                             bool refresh, bool ab2, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
-  const size_t lds = (size_t)m.nv * 3 * (sizeof(long long) + sizeof(float));
+  const int region = std::max(24, bin::slot_lds_per_vertex(L.max_touch)) * m.nv;
+  const size_t lds = (size_t)((region + 7) & ~7) + (size_t)m.nv * 3 * sizeof(float);
   if (L.kernel == 4)
     hipLaunchKernelGGL(k_cell_step<4>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
                        flags, advect ? 1 : 0, src, refresh ? 1 : 0, ab2 ? 1 : 0);
