@@ -133,6 +133,34 @@ def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int
             "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
 
 
+def bench_small(torch):
+    """The single-cell shear box (32^3, 500 steps) and the dense channel
+    (128x64x64, 220 cells, 1000 steps): whole runs, timed per step."""
+    from paper_2305_02752_amd import Simulation
+    from workloads import dense_channel, single_rbc_shear
+
+    out = {}
+    for w in (single_rbc_shear(), dense_channel()):
+        sim = Simulation(w.lattice, w.rest_pos, w.tri, max_cells=w.cells.n)
+        sim.set_cells(w.cells.origin, w.cells.offsets, w.cells.k, w.cells.traction)
+        sim.init_equilibrium()
+        sim.set_field_output(False)
+        sim.step(20)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(w.steps)
+        sim.sync()
+        dt = time.perf_counter() - t0
+        n = w.lattice.nx * w.lattice.ny * w.lattice.nz
+        nv = w.cells.n * w.rest_pos.shape[0]
+        out[w.name] = {"steps": w.steps, "us_per_step": dt / w.steps * 1e6,
+                       "MLUPS": n * w.steps / dt / 1e6, "vertex_updates_per_s": nv * w.steps / dt,
+                       "launches_per_step": 2}
+        sim.close()
+    return out
+
+
 def bench_batched(torch, seed: int = 3, steps: int = 2000, warmup: int = 20):
     """Batched calibration workload: 256 single-cell boxes (sides U{24..48})
     advanced together, one persistent launch per run, tiling autotuned."""
@@ -315,6 +343,13 @@ def main():
         adj = bench_adjoint(torch, boxes=args.adjoint_boxes)
         log(f"adjoint: {adj['grads_per_s']:.2f} gradients/s, t_grad/t_fwd {adj['t_grad_over_t_forward']:.2f}")
 
+    small = None
+    if not args.no_extra:
+        log("single-cell shear and dense channel ...")
+        small = bench_small(torch)
+        for k, v in small.items():
+            log(f"  {k}: {v['us_per_step']:.1f} us/step, {v['MLUPS']:.0f} MLUPS")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
@@ -344,6 +379,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "separated_time_scales": tss,
+        "small_workloads": small,
         "batched_calibration": batched,
         "adjoint": adj,
     }
