@@ -46,7 +46,7 @@ def advance(m: step.Model, f, X, st: CellState, force_every: int = 1, scheme: st
     if st.steps % force_every == 0 or Fv is None:
         Fv = (membrane.forces(X, m.k, m.topo, m.rest, m.traction) if X.shape[0]
               else np.zeros_like(X))
-    f_new, U, info = step.fluid_step(m, f, X, Fv)
+    f_new, U, info = step.fluid_step(m, f, X, Fv, st.steps)
     if scheme == "ab2" and st.U_prev is not None:
         X_new = X + 1.5 * U - 0.5 * st.U_prev
     else:

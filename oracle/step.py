@@ -19,7 +19,7 @@ import dataclasses
 
 import numpy as np
 
-from . import ibm, lattice, membrane
+from . import ibm, lattice, lees_edwards, membrane
 
 
 @dataclasses.dataclass
@@ -35,9 +35,10 @@ class Model:
     rest: membrane.RestState
     k: np.ndarray          # [C, 4]
     traction: np.ndarray | None
+    le_u: float = 0.0      # Lees-Edwards image velocity along x (gradient axis z); 0: off
 
 
-def make_model(lat, rest_pos, tri, k, traction=None) -> Model:
+def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0) -> Model:
     topo = membrane.Topology(tri, rest_pos.shape[0])
     rest = membrane.RestState(np.asarray(rest_pos, dtype=np.float64), topo)
     return Model(dims=(lat.nx, lat.ny, lat.nz), bc=tuple(lat.bc), tau=float(lat.tau),
@@ -45,43 +46,55 @@ def make_model(lat, rest_pos, tri, k, traction=None) -> Model:
                  wall_u_lo=tuple(lat.wall_u_lo), wall_u_hi=tuple(lat.wall_u_hi),
                  kernel=int(lat.ibm_kernel), topo=topo, rest=rest,
                  k=np.asarray(k, dtype=np.float64),
-                 traction=None if traction is None else np.asarray(traction, dtype=np.float64))
+                 traction=None if traction is None else np.asarray(traction, dtype=np.float64),
+                 le_u=float(le_u))
 
 
-def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray):
+def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 0):
     """Steps 2-5 with given vertex forces Fv [C, V, 3]: returns the streamed
     populations, the interpolated vertex velocity U and the intermediate
-    fields."""
+    fields.  t: the step index (fixes the Lees-Edwards image shift)."""
     nx, ny, nz = m.dims
     C = X.shape[0]
-    if C:
+    le = m.le_u != 0.0
+    delta = lees_edwards.image_shift(m.le_u, t, nx) if le else 0.0
+    if C and le:
+        F = lees_edwards.spread(X.reshape(-1, 3), Fv.reshape(-1, 3), m.dims, delta, m.kernel)
+    elif C:
         F = ibm.spread(X.reshape(-1, 3), Fv.reshape(-1, 3), m.dims, m.bc, m.kernel)
     else:
         F = np.zeros((3, nz, ny, nx))
     for d in range(3):
         F[d] += m.body_force[d]
     rho, u = lattice.moments(f, F)
-    if C:
+    if C and le:
+        U = lees_edwards.interpolate(u, X.reshape(-1, 3), m.dims, m.le_u, delta,
+                                     m.kernel).reshape(X.shape)
+    elif C:
         U = ibm.interpolate(u, X.reshape(-1, 3), m.dims, m.bc, m.wall_u_lo, m.wall_u_hi,
                             m.kernel).reshape(X.shape)
     else:
         U = np.zeros_like(X)
     post = lattice.collide(f, rho, u, F, m.tau)
-    f_new = lattice.stream(post, rho, m.bc, m.wall_u_lo, m.wall_u_hi)
+    if le:
+        f_new = lees_edwards.stream(post, m.le_u, delta)
+    else:
+        f_new = lattice.stream(post, rho, m.bc, m.wall_u_lo, m.wall_u_hi)
     return f_new, U, {"Fv": Fv, "F": F, "rho": rho, "u": u, "U": U}
 
 
-def step(m: Model, f: np.ndarray, X: np.ndarray):
-    """Advance populations f [19, nz, ny, nx] and positions X [C, V, 3] by one step.
+def step(m: Model, f: np.ndarray, X: np.ndarray, t: int = 0):
+    """Advance populations f [19, nz, ny, nx] and positions X [C, V, 3] by one
+    step (t: its index, counted from 0).
 
     Returns (f_new, X_new, info) where info holds the intermediate fields.
     """
     Fv = membrane.forces(X, m.k, m.topo, m.rest, m.traction) if X.shape[0] else np.zeros_like(X)
-    f_new, U, info = fluid_step(m, f, X, Fv)
+    f_new, U, info = fluid_step(m, f, X, Fv, t)
     return f_new, X + U, info
 
 
-def run(m: Model, f, X, n: int):
-    for _ in range(n):
-        f, X, _ = step(m, f, X)
+def run(m: Model, f, X, n: int, t0: int = 0):
+    for i in range(n):
+        f, X, _ = step(m, f, X, t0 + i)
     return f, X
