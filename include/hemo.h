@@ -70,7 +70,17 @@ typedef struct hc_ctx hc_ctx;
  *  wall_u_lo/hi velocity of the lower / upper wall of the wall axis
  *               (moving walls impose shear, Sec. 2.5); must be tangential.
  *  ibm_kernel   HC_PHI4 (Peskin 4-point, default) or HC_PHI2 (linear hat,
- *               the "linear interpolation" of Sec. 2.3).                     */
+ *               the "linear interpolation" of Sec. 2.3).
+ *  lees_edwards_u  0, or the velocity U of Lees-Edwards sheared periodic
+ *               images (Sec. 2.5: boundary-free uniform shear): z is the
+ *               gradient axis, x the flow axis; the image above the box is
+ *               displaced by +U t along x and moves with +U, the one below
+ *               by -U t and -U.  Populations crossing the z boundary are
+ *               interpolated along the displaced image row and changed by
+ *               the Galilean equilibrium term; IBM stencil nodes in an image
+ *               use the vertex's displaced image.  Requires every axis
+ *               periodic and nx, nz multiples of 8; not available to the
+ *               batched form or the adjoint.                                 */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t bc[3];
@@ -79,6 +89,7 @@ typedef struct {
   float wall_u_lo[3];
   float wall_u_hi[3];
   int32_t ibm_kernel;
+  float lees_edwards_u;
 } hc_lattice_desc;
 
 /* Cell surface mesh shared by all cells (Sec. 2.3: triangulated membrane).

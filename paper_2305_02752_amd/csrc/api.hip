@@ -195,12 +195,26 @@ hc_status copy_d2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
   return check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "d2d copy");
 }
 
+// Lees-Edwards image displacements U t mod nx (in double: t grows) for the
+// step about to run (IBM stencils) and for the step before it, whose
+// streaming the next pull completes.
+void le_update(hc_ctx* c) {
+  if (!c->L.le) return;
+  auto shift = [&](int64_t t) {
+    const double n = c->L.nx;
+    return (float)std::fmod(std::fmod((double)c->L.le_u * (double)t, n) + n, n);
+  };
+  c->L.le_delta = shift(c->step);
+  c->L.le_pull_delta = shift(c->step - 1);
+}
+
 // One coupled step.  The vertex move that closes the step (interpolated
 // velocity, Euler or Adams-Bashforth) is left pending: the next step's
 // per-cell kernel applies it before the membrane forces, or flush() applies
 // it on its own.  The membrane forces are recomputed every force_every
 // steps and held in between.
 hc_status one_step(hc_ctx* c) {
+  le_update(c);
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
   const bool adv = c->advect_pending;
@@ -218,6 +232,7 @@ hc_status one_step(hc_ctx* c) {
   c->advect_pending = C.n > 0;
   c->cur ^= 1;
   c->step += 1;
+  c->L.le_raw = 0;   // the new state holds post-collision values
   return HC_OK;
 }
 
@@ -346,6 +361,11 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     }
   }
   if (walls > 1) return fail(nullptr, HC_ERR_UNSUPPORTED, "at most one wall axis");
+  const bool le = lat->lees_edwards_u != 0.f;
+  if (le && (walls > 0 || lat->nx % kTile != 0 || lat->nz % kTile != 0))
+    return fail(nullptr, HC_ERR_UNSUPPORTED,
+                "Lees-Edwards images need every axis periodic and nx, nz multiples of 8");
+  if (!std::isfinite(lat->lees_edwards_u)) return fail(nullptr, HC_ERR_ARG, "lees_edwards_u not finite");
   if (wall_axis >= 0 && (lat->wall_u_lo[wall_axis] != 0.f || lat->wall_u_hi[wall_axis] != 0.f))
     return fail(nullptr, HC_ERR_ARG, "wall velocities must be tangential");
   hc_ctx* c = new hc_ctx();
@@ -368,6 +388,11 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   L.tau = lat->tau;
   L.omega = 1.0f / lat->tau;
   L.kernel = lat->ibm_kernel;
+  L.le = le ? 1 : 0;
+  L.le_u = lat->lees_edwards_u;
+  L.le_delta = 0.f;
+  L.le_pull_delta = 0.f;
+  L.le_raw = 1;
   L.n = (int64_t)L.nx * L.ny * L.nz;
   L.tx = (L.nx + kTile - 1) / kTile;
   L.ty = (L.ny + kTile - 1) / kTile;
@@ -382,7 +407,10 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     const int last = sides[d] - (sides[d] - 1) / kTile * kTile;
     int per_axis = sides[d] <= kTile ? 1 : 2;
     if (L.bc[d] == HC_PERIODIC && sides[d] > kTile && last <= L.kernel - 2) per_axis = 3;
-    L.max_touch *= std::min(per_axis, (sides[d] + kTile - 1) / kTile);
+    int reach = std::min(per_axis, (sides[d] + kTile - 1) / kTile);
+    // with sheared images a stencil spans the x tiles of two displaced copies
+    if (le && d == 0) reach = std::min(2 * reach, (sides[d] + kTile - 1) / kTile);
+    L.max_touch *= reach;
   }
   c->max_cells = max_cells;
   // tile-list capacity: 4 entries per tile node (about 4x the densest
@@ -541,6 +569,7 @@ hc_status hc_init_equilibrium(hc_ctx* c, float rho0, const float u0[3]) {
   const float* u = u0 ? u0 : z;
   HC_TRY(check(c, launch_init_equilibrium(c->pops[c->cur], rho0, u[0], u[1], u[2], c->L, c->stream),
                "init"));
+  c->L.le_raw = 1;
   return HC_OK;
 }
 
@@ -574,6 +603,7 @@ hc_status hc_read_populations(hc_ctx* c, float* host, int64_t count) {
   HC_TRY(need_ws(c));
   if (!host || count != 19 * c->L.n) return fail(c, HC_ERR_ARG, "population count mismatch");
   float* tmp = c->pops[c->cur ^ 1];
+  le_update(c);
   HC_TRY(check(c, launch_to_natural(c->pops[c->cur], tmp, c->L, c->stream), "to natural"));
   HC_TRY(copy_d2h(c, host, tmp, (size_t)count * 4));
   return sync(c, "read populations");
@@ -585,6 +615,7 @@ hc_status hc_write_populations(hc_ctx* c, const float* host, int64_t count) {
   float* tmp = c->pops[c->cur ^ 1];
   HC_TRY(copy_h2d(c, tmp, host, (size_t)count * 4));
   HC_TRY(check(c, launch_from_natural(tmp, c->pops[c->cur], c->L, c->stream), "from natural"));
+  c->L.le_raw = 1;
   return sync(c, "write populations");
 }
 
@@ -699,7 +730,7 @@ hc_status hc_read_bins(hc_ctx* c, int32_t* owner, int32_t* touch_ptr, int32_t* t
 }
 
 // Checkpoint layout: header {step, cells, have_prev, force_every, scheme,
-// 0} (int64 x 2, int32 x 4), then the stored populations, origins, offsets,
+// raw state flag} (int64 x 2, int32 x 4), then the stored populations, origins, offsets,
 // vertex velocities and held vertex forces.
 constexpr size_t kCkHeader = 32;
 
@@ -718,7 +749,7 @@ hc_status hc_checkpoint_save(hc_ctx* c, void* host, size_t bytes) {
   HC_TRY(flush(c));
   char* p = static_cast<char*>(host);
   const int64_t h64[2] = {c->step, c->C.n};
-  const int32_t h32[4] = {c->have_prev ? 1 : 0, c->force_every, c->scheme, 0};
+  const int32_t h32[4] = {c->have_prev ? 1 : 0, c->force_every, c->scheme, c->L.le_raw};
   std::memcpy(p, h64, 16);
   std::memcpy(p + 16, h32, 16);
   p += kCkHeader;
@@ -763,6 +794,7 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   c->have_prev = h32[0] != 0;
   c->force_every = h32[1];
   c->scheme = h32[2];
+  c->L.le_raw = h32[3];
   c->advect_pending = false;
   return sync(c, "checkpoint restore");
 }
@@ -808,6 +840,7 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(c, HC_ERR_ARG, "workspace not 256-aligned");
   if (c->L.kernel != HC_PHI4)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
+  if (c->L.le) return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover Lees-Edwards images");
   if (c->force_every != 1 || c->scheme != HC_EULER)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int ck = std::min(ckpt_every, n_steps);

@@ -283,6 +283,7 @@ hc_status hc_batch_create(int32_t n_boxes, const hc_lattice_desc* boxes, const h
     if (walls > 1) why = "at most one wall axis per box";
     if (wall_axis >= 0 && (d.wall_u_lo[wall_axis] != 0.f || d.wall_u_hi[wall_axis] != 0.f))
       why = "wall velocities must be tangential";
+    if (d.lees_edwards_u != 0.f) why = "Lees-Edwards images are not available to the batched form";
     if (!why.empty()) {
       delete b;
       return bfail(nullptr, HC_ERR_ARG, "box " + std::to_string(i) + ": " + why);

@@ -12,9 +12,10 @@ __device__ inline int bwrap(int p, int n) {
   return p < 0 ? p + n : p;
 }
 
-// Distinct tiles (<= 3) reached along one axis by K stencil nodes starting at p0.
-__device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
-  int cnt = 0;
+// Distinct tiles reached along one axis by K stencil nodes starting at p0,
+// appended to out[cnt, cap) (already listed tiles are skipped).
+__device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out, int cnt = 0,
+                                 int cap = 3) {
   for (int k = 0; k < K; ++k) {
     int p = p0 + k;
     if (wall) {
@@ -25,15 +26,17 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out) {
     const int t = p / kTile;
     bool seen = false;
     for (int q = 0; q < cnt; ++q) seen = seen || out[q] == t;
-    if (!seen && cnt < 3) out[cnt++] = t;
+    if (!seen && cnt < cap) out[cnt++] = t;
   }
   return cnt;
 }
 
 // Tiles reached by the stencil of a vertex of cell c at offset o, per axis,
-// and its owner tile.
+// and its owner tile.  With sheared periodic images the x tiles are those
+// of the vertex's displaced copies in every image its z stencil reaches
+// (two at most), so up to 4 along x.
 __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, const float* o,
-                                   int (&T)[3][3], int (&nT)[3]) {
+                                   int (&T)[3][4], int (&nT)[3]) {
   const int K = L.kernel;
   const int b = K == 4 ? -1 : 0;
   const int n[3] = {L.nx, L.ny, L.nz};
@@ -44,10 +47,19 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
     nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
     own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : bwrap(p, n[d])) / kTile;
   }
+  if (L.le) {
+    const int pz = C.origin[3 * c + 2] + (int)floorf(o[2]);
+    const int ma = floor_div(pz + b, L.nz), mb = floor_div(pz + b + K - 1, L.nz);
+    const float xa = o[0] - (float)ma * L.le_delta, xb = o[0] - (float)mb * L.le_delta;
+    nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xa) + b, K, L.nx, 0, T[0], 0, 4);
+    if (mb != ma) nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xb) + b, K, L.nx, 0, T[0], nT[0], 4);
+    const float xo = o[0] - (float)floor_div(pz, L.nz) * L.le_delta;
+    own[0] = bwrap(C.origin[3 * c] + (int)floorf(xo), L.nx) / kTile;
+  }
   return (own[2] * L.ty + own[1]) * L.tx + own[0];
 }
 
-__device__ inline int slot_tile(const Lattice& L, const int (&T)[3][3], const int (&nT)[3], int j) {
+__device__ inline int slot_tile(const Lattice& L, const int (&T)[3][4], const int (&nT)[3], int j) {
   const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
   return (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
 }
@@ -75,7 +87,7 @@ __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L,
   __syncthreads();
   for (int vl = tid; vl < M.nv; vl += nthr) {
     const int64_t v = (int64_t)c * M.nv + vl;
-    int T[3][3], nT[3];
+    int T[3][4], nT[3];
     B.owner[v] = vertex_tiles(C, L, c, pos + 3 * vl, T, nT);
     int ntouch = nT[0] * nT[1] * nT[2];
     if (ntouch > L.max_touch) {  // excluded by the per-axis bound set at create

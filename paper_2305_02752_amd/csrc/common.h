@@ -55,6 +55,12 @@ struct Lattice {
   float g[3];               // body force density
   float ulo[3], uhi[3];     // wall velocities (wall axis only)
   int kernel;               // 4 or 2
+  int le;                   // Lees-Edwards images across z (flow along x)
+  float le_u;               // image velocity U
+  float le_delta;           // displacement U t mod nx at this step (IBM stencils)
+  float le_pull_delta;      // displacement of the previous step, whose streaming the pull completes
+  int le_raw;               // the stored state is a plain permutation of the pre-collision
+                            // populations (fresh from a write or init): pull periodically
   int64_t n;                // nx * ny * nz
   int64_t np;               // ntiles * 512: site slots of every lattice field
   int tx, ty, tz, ntiles;   // tile grid
@@ -71,6 +77,9 @@ __host__ __device__ inline int64_t site_of(const Lattice& L, int x, int y, int z
   const int t = ((z >> 3) * L.ty + (y >> 3)) * L.tx + (x >> 3);
   return (int64_t)t * 512 + (((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
 }
+
+// floor(a / b) for b > 0.
+__host__ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // Node of slot h, or false for a padding slot.
 __host__ __device__ inline bool node_of(const Lattice& L, int64_t h, int& x, int& y, int& z) {

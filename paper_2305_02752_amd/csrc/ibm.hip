@@ -48,6 +48,23 @@ __device__ inline void axis_stencil(int origin, float x, int n, int wall, int t0
   }
 }
 
+// Sheared periodic images (Lees-Edwards, z gradient / x flow): the image
+// index of each z stencil position (floor of its unwrapped index / nz), and
+// the x stencils of the vertex as seen from the first and last of them
+// (x - m Delta).  Consecutive positions cross at most one boundary, so two
+// x stencils cover all K.
+template <int K>
+struct LeStencil {
+  int m[K];
+  int ma, mb;
+  int lxa[K], lxb[K];
+  float wxa[K], wxb[K];
+};
+
+template <int K>
+__device__ inline void le_stencil(const Lattice& L, int ox, float x, int oz, float zoff, int t0,
+                                  LeStencil<K>& S);
+
 // Rotate a K-entry stencil by r so that lanes holding nearby vertices visit
 // different nodes at the same time (fewer LDS same-address conflicts).
 template <int K>
@@ -74,6 +91,18 @@ __device__ inline void rotate(int (&l)[K], float (&w)[K], int r) {
   }
 }
 
+template <int K>
+__device__ inline void le_stencil(const Lattice& L, int ox, float x, int oz, float zoff, int t0,
+                                  LeStencil<K>& S) {
+  const int bz = oz + (int)floorf(zoff) - (K == 4 ? 1 : 0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) S.m[k] = floor_div(bz + k, L.nz);
+  S.ma = S.m[0];
+  S.mb = S.m[K - 1];
+  axis_stencil<K>(ox, x - (float)S.ma * L.le_delta, L.nx, 0, t0, S.lxa, S.wxa);
+  axis_stencil<K>(ox, x - (float)S.mb * L.le_delta, L.nx, 0, t0, S.lxb, S.wxb);
+}
+
 __device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, int& z0) {
   x0 = (t % L.tx) * kTile;
   y0 = ((t / L.tx) % L.ty) * kTile;
@@ -84,7 +113,7 @@ __device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, in
 // tile's list; the thread evaluates its 3 x K axis weights once and adds the
 // contributions of the stencil nodes inside the tile to the LDS accumulator
 // acc[3][512] (zeroed by the caller, synchronised after).
-template <int K>
+template <int K, bool LE = false>
 __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                    const float* __restrict__ vec, int t, int x0, int y0, int z0,
                                    long long (*acc)[kTile * kTile * kTile]) {
@@ -99,17 +128,35 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
     const float fx = fv[0] * kFixScaleF, fy = fv[1] * kFixScaleF, fz = fv[2] * kFixScaleF;
     int lx[K], ly[K], lz[K];
     float wx[K], wy[K], wz[K];
-    axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
+    LeStencil<K> S;
+    if (LE) {
+      le_stencil<K>(L, C.origin[3 * c + 0], o[0], C.origin[3 * c + 2], o[2], x0, S);
+      rotate<K>(S.lxa, S.wxa, rot);
+      rotate<K>(S.lxb, S.wxb, rot);
+    } else {
+      axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
+      rotate<K>(lx, wx, rot);
+    }
     axis_stencil<K>(C.origin[3 * c + 1], o[1], L.ny, L.bc[1] == 1, y0, ly, wy);
     axis_stencil<K>(C.origin[3 * c + 2], o[2], L.nz, L.bc[2] == 1, z0, lz, wz);
-    rotate<K>(lx, wx, rot);
     rotate<K>(ly, wy, rot >> 2);
+    // the x stencil of the image z position kz lies in (sheared images only)
+    auto pick_x = [&](int kz) {
+      if (!LE) return;
+      const bool a = S.m[kz] == S.ma;
+#pragma unroll
+      for (int kx = 0; kx < K; ++kx) {
+        lx[kx] = a ? S.lxa[kx] : S.lxb[kx];
+        wx[kx] = a ? S.wxa[kx] : S.wxb[kx];
+      }
+    };
     // weights are at most 1, so one test per entry decides whether every
     // node contribution fits the 32-bit conversion
     if (fmaxf(fabsf(fx), fmaxf(fabsf(fy), fabsf(fz))) < kFix32Max) {
 #pragma unroll
       for (int kz = 0; kz < K; ++kz) {
         if (lz[kz] < 0) continue;
+        pick_x(kz);
 #pragma unroll
         for (int ky = 0; ky < K; ++ky) {
           if (ly[ky] < 0) continue;
@@ -129,6 +176,7 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
     } else {
       for (int kz = 0; kz < K; ++kz) {
         if (lz[kz] < 0) continue;
+        pick_x(kz);
         for (int ky = 0; ky < K; ++ky) {
           if (ly[ky] < 0) continue;
           const float wzy = wz[kz] * wy[ky];
@@ -148,7 +196,7 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
 // Interpolation phase of one tile: one thread per (vertex, tile) entry sums
 // w * u over its stencil nodes inside the tile (velocities staged in su) and
 // stores the partial sum in the vertex's slot.
-template <int K>
+template <int K, bool LE = false>
 __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                    const float4* su, int t, int x0, int y0, int z0,
                                    float4* __restrict__ partial) {
@@ -161,13 +209,27 @@ __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice&
     const float* o = C.off + (int64_t)v * 3;
     int lx[K], ly[K], lz[K];
     float wx[K], wy[K], wz[K];
-    axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
+    LeStencil<K> S;
+    if (LE)
+      le_stencil<K>(L, C.origin[3 * c + 0], o[0], C.origin[3 * c + 2], o[2], x0, S);
+    else
+      axis_stencil<K>(C.origin[3 * c + 0], o[0], L.nx, L.bc[0] == 1, x0, lx, wx);
     axis_stencil<K>(C.origin[3 * c + 1], o[1], L.ny, L.bc[1] == 1, y0, ly, wy);
     axis_stencil<K>(C.origin[3 * c + 2], o[2], L.nz, L.bc[2] == 1, z0, lz, wz);
     float ux = 0.f, uy = 0.f, uz = 0.f;
 #pragma unroll
     for (int kz = 0; kz < K; ++kz) {
       if (lz[kz] < 0) continue;
+      float shift = 0.f;   // velocity of the image this z position lies in
+      if (LE) {
+        const bool a = S.m[kz] == S.ma;
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+          lx[kx] = a ? S.lxa[kx] : S.lxb[kx];
+          wx[kx] = a ? S.wxa[kx] : S.wxb[kx];
+        }
+        shift = (float)S.m[kz] * L.le_u;
+      }
 #pragma unroll
       for (int ky = 0; ky < K; ++ky) {
         if (ly[ky] < 0) continue;
@@ -178,7 +240,7 @@ __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice&
           if (lx[kx] < 0) continue;
           const float w = wzy * wx[kx];
           const float4 q = su[row + lx[kx]];
-          ux += w * q.x;
+          ux += w * (LE ? q.x + shift : q.x);
           uy += w * q.y;
           uz += w * q.z;
         }
@@ -237,7 +299,7 @@ __host__ __device__ inline int tile_grid(const Lattice& L) { return ((L.ntiles +
 //     non-zero);
 //  3. interpolate u to the tile's entries into their partial-sum slots.
 // The force and velocity fields never leave the chip.
-template <int K>
+template <int K, bool LE>
 __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, Bins B,
                                                    const float* __restrict__ gin,
                                                    float* __restrict__ gout,
@@ -256,7 +318,7 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
     acc[2][i] = 0;
   }
   __syncthreads();
-  if (C.n > 0) spread_tile<K>(C, M, L, B, C.force, t, x0, y0, z0, acc);
+  if (C.n > 0) spread_tile<K, LE>(C, M, L, B, C.force, t, x0, y0, z0, acc);
   __syncthreads();
 
   const int64_t NP = L.np, h0 = (int64_t)t * 512;
@@ -269,9 +331,13 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
     float g[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      int qs;
-      const int64_t src = lbm::pull_source(L, q, x, y, z, &qs);
-      g[q] = gin[qs * NP + src];
+      if (LE && !L.le_raw && ((lbm::cz[q] > 0 && z == 0) || (lbm::cz[q] < 0 && z == L.nz - 1))) {
+        g[q] = lbm::le_pull(L, gin, q, x, y);
+      } else {
+        int qs;
+        const int64_t src = lbm::pull_source(L, q, x, y, z, &qs);
+        g[q] = gin[qs * NP + src];
+      }
     }
     const float fx = L.g[0] + (float)((double)acc[0][i] * kFixInv);
     const float fy = L.g[1] + (float)((double)acc[1][i] * kFixInv);
@@ -292,7 +358,7 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
   }
   if (C.n == 0) return;
   __syncthreads();
-  interp_tile<K>(C, M, L, B, su, t, x0, y0, z0, partial);
+  interp_tile<K, LE>(C, M, L, B, su, t, x0, y0, z0, partial);
   __syncthreads();   // every thread has read the count: leave it zero for the next binning
   if (threadIdx.x == 0) B.touch_cnt[t] = 0;
 }
@@ -323,12 +389,18 @@ hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             bool fields, hipStream_t s) {
   const dim3 grid((unsigned)tile_grid(L));
   const int fl = fields ? 1 : 0;
-  if (L.kernel == 4)
-    hipLaunchKernelGGL(k_tile_step<4>, grid, dim3(256), 0, s, c, m, L, b, gin, gout, F, macro,
-                       partial, fl);
+  if (L.kernel == 4 && L.le)
+    hipLaunchKernelGGL((k_tile_step<4, true>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
+                       macro, partial, fl);
+  else if (L.kernel == 4)
+    hipLaunchKernelGGL((k_tile_step<4, false>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
+                       macro, partial, fl);
+  else if (L.le)
+    hipLaunchKernelGGL((k_tile_step<2, true>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
+                       macro, partial, fl);
   else
-    hipLaunchKernelGGL(k_tile_step<2>, grid, dim3(256), 0, s, c, m, L, b, gin, gout, F, macro,
-                       partial, fl);
+    hipLaunchKernelGGL((k_tile_step<2, false>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
+                       macro, partial, fl);
   return hipGetLastError();
 }
 

@@ -53,14 +53,19 @@ __global__ void k_to_natural(const float* __restrict__ h, float* __restrict__ g,
   const int x = (int)(s % L.nx), y = (int)((s / L.nx) % L.ny), z = (int)(s / ((int64_t)L.nx * L.ny));
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
+    if (L.le && !L.le_raw && ((cz[q] > 0 && z == 0) || (cz[q] < 0 && z == L.nz - 1))) {
+      g[q * L.n + s] = lbm::le_pull(L, h, q, x, y);   // crossing the sheared boundary
+      continue;
+    }
     int qs;
     const int64_t src = lbm::pull_source(L, q, x, y, z, &qs);
     g[q * L.n + s] = h[qs * L.np + src];
   }
 }
 
-// Inverse of k_to_natural: every stored slot is the pull source of exactly
-// one (population, node) pair, so the scatter writes each slot once.
+// Inverse of k_to_natural for a plain state (periodic or walled pull): every
+// stored slot is the pull source of exactly one (population, node) pair, so
+// the scatter writes each slot once.  The result is a raw state.
 __global__ void k_from_natural(const float* __restrict__ g, float* __restrict__ h, Lattice L) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= L.n) return;

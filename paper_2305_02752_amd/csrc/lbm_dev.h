@@ -129,5 +129,48 @@ __device__ inline float wall_coeff(const Lattice& L, int q, int x, int y, int z)
   return -6.f * wq[q] * (cx[q] * uw[0] + cy[q] * uw[1] + cz[q] * uw[2]);
 }
 
+// Population q arriving at boundary node (x, y, z) across the z boundary of
+// a Lees-Edwards lattice, completing the streaming of the previous step (so
+// with that step's displacement): from the image below (e_z > 0, node on z = 0) or
+// above (e_z < 0, node on z = nz - 1), whose boundary row is displaced by
+// -Delta or +Delta along x and moves with -U or +U.  The source point
+// x - e_x +- Delta falls between two nodes: all 19 stored populations of
+// both are interpolated linearly, and the transferred population gets the
+// Galilean change f_eq(rho, u -+ U) - f_eq(rho, u) with the density and
+// velocity of the interpolated set.  (Shifted populations: the weights
+// cancel from both the interpolation and the velocity.)
+__device__ inline float le_pull(const Lattice& L, const float* __restrict__ h, int q, int x, int y) {
+  const int64_t NP = L.np;
+  const int ez = cz[q];
+  const int zs = ez > 0 ? L.nz - 1 : 0;
+  const float sign = ez > 0 ? -1.f : 1.f;
+  int ys = y - cy[q];
+  ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
+  const float pos = (float)(x - cx[q]) - sign * L.le_pull_delta;
+  const float fl = floorf(pos);
+  const float s = pos - fl;
+  int x0 = (int)fl % L.nx;
+  x0 = x0 < 0 ? x0 + L.nx : x0;
+  const int x1 = x0 + 1 == L.nx ? 0 : x0 + 1;
+  const int64_t a = site_of(L, x0, ys, zs), b = site_of(L, x1, ys, zs);
+  float hq = 0.f, drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int j = 0; j < kQ; ++j) {
+    const float v = (1.f - s) * h[j * NP + a] + s * h[j * NP + b];
+    drho += v;
+    jx += cx[j] * v;
+    jy += cy[j] * v;
+    jz += cz[j] * v;
+    if (j == q) hq = v;
+  }
+  const float rho = 1.f + drho, inv = 1.f / rho;
+  const float ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const float vx = ux + sign * L.le_u;
+  const float eu = cx[q] * ux + cy[q] * uy + cz[q] * uz;
+  const float ev = cx[q] * vx + cy[q] * uy + cz[q] * uz;
+  const float uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + uy * uy + uz * uz;
+  return hq + wq[q] * rho * (3.f * (ev - eu) + 4.5f * (ev * ev - eu * eu) - 1.5f * (vv - uu));
+}
+
 }  // namespace lbm
 }  // namespace hc

@@ -30,7 +30,8 @@ class HemoError(RuntimeError):
 class LatticeDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc", C.c_int32 * 3),
                 ("tau", C.c_float), ("body_force", C.c_float * 3), ("wall_u_lo", C.c_float * 3),
-                ("wall_u_hi", C.c_float * 3), ("ibm_kernel", C.c_int32)]
+                ("wall_u_hi", C.c_float * 3), ("ibm_kernel", C.c_int32),
+                ("lees_edwards_u", C.c_float)]
 
 
 class MeshDesc(C.Structure):
@@ -115,6 +116,7 @@ def lattice_desc(lat) -> LatticeDesc:
         d.wall_u_hi[i] = float(lat.wall_u_hi[i])
     d.tau = float(lat.tau)
     d.ibm_kernel = int(lat.ibm_kernel)
+    d.lees_edwards_u = float(getattr(lat, "lees_edwards_u", 0.0))
     return d
 
 

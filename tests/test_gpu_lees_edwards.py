@@ -1,0 +1,133 @@
+"""Lees-Edwards sheared periodic images on the device against the FP64 oracle
+(Sec. 2.5 reading, oracle/lees_edwards.py).
+
+* fluid only: populations after several steps with a growing image shift;
+* coupled: one step (populations, force field, vertex velocity) and twelve
+  steps (populations, positions) with a cell straddling the z boundary;
+* a fluid-only box relaxes to the uniform shear the images impose;
+* unsupported combinations are refused.
+"""
+import numpy as np
+import pytest
+
+from oracle import lattice, lees_edwards as le, step
+from workloads import jitter_cells, random_shifted_populations, rbc_mesh
+from workloads.configs import K_REF, Lattice, place_cells, small_rotation
+
+from gpu_common import relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5
+
+
+def _sim(lat, cells=None, max_cells=None):
+    from paper_2305_02752_amd import Simulation
+    rest, tri = rbc_mesh()
+    sim = Simulation(lat, rest.astype(np.float32), tri,
+                     max_cells=max_cells if max_cells is not None else (cells.n if cells else 0))
+    if cells is not None:
+        sim.set_cells(cells.origin, cells.offsets, cells.k, cells.traction)
+    return sim
+
+
+def test_fluid_only_parity():
+    U = 0.03
+    lat = Lattice(16, 12, 24, tau=0.9, lees_edwards_u=U)
+    g0 = random_shifted_populations(np.random.default_rng(41), lat, 1e-3)
+    sim = _sim(lat)
+    sim.write_populations(g0)
+    n = 6
+    sim.step(n)
+    sim.sync()
+    f = lattice.unshift(g0)
+    F = np.zeros((3,) + lat.shape)
+    for t in range(n):
+        rho, u = lattice.moments(f, F)
+        post = lattice.collide(f, rho, u, F, lat.tau)
+        f = le.stream(post, U, le.image_shift(U, t, lat.nx))
+    e = relerr(sim.read_populations(), lattice.shifted(f))
+    print("fluid-only", e, flush=True)
+    assert e <= n * TOL_STEP
+
+
+def _straddling_cell(lat, seed):
+    rest64, tri = rbc_mesh()
+    rng = np.random.default_rng(seed)
+    centre = np.array([lat.nx * 0.4, lat.ny * 0.5, lat.nz - 1.2]) + rng.uniform(-0.3, 0.3, 3)
+    cells = place_cells(rest64, centre[None], small_rotation(rng, 10.0)[None],
+                        (K_REF * 10.0 ** rng.uniform(-0.3, 0.3, 4))[None], traction=[[2e-3, 0, 0]])
+    return rest64, tri, jitter_cells(rng, cells, 0.05)
+
+
+def _oracle(lat, rest64, tri, cells, U):
+    return step.make_model(lat, rest64, tri, cells.k.astype(np.float64), cells.traction.astype(np.float64),
+                           le_u=U)
+
+
+@pytest.mark.parametrize("U", [0.02, -0.035])
+def test_coupled_one_step_parity(U):
+    lat = Lattice(24, 20, 24, tau=1.0, lees_edwards_u=U)
+    rest64, tri, cells = _straddling_cell(lat, 42)
+    g0 = random_shifted_populations(np.random.default_rng(43), lat, 1e-3)
+    sim = _sim(lat, cells)
+    sim.write_populations(g0)
+    sim.step(3)                      # the third step runs with image shift 2U
+    sim.sync()
+    m = _oracle(lat, rest64, tri, cells, U)
+    f, X = lattice.unshift(g0), cells.positions64()
+    for t in range(2):
+        f, X, _ = step.step(m, f, X, t)
+    f3, X3, info = step.step(m, f, X, 2)
+    e_g = relerr(sim.read_populations(), lattice.shifted(f3))
+    e_u = relerr(sim.read_vertex_velocity(), info["U"])
+    print("coupled 3 steps", e_g, e_u, flush=True)
+    assert e_g <= 3 * TOL_STEP and e_u <= 3 * TOL_STEP
+
+
+def test_coupled_multistep_positions():
+    U = 0.03
+    lat = Lattice(24, 20, 24, tau=1.0, lees_edwards_u=U)
+    rest64, tri, cells = _straddling_cell(lat, 44)
+    sim = _sim(lat, cells)
+    sim.init_equilibrium()
+    n = 12
+    sim.step(n)
+    sim.sync()
+    m = _oracle(lat, rest64, tri, cells, U)
+    X0 = cells.positions64()
+    f, X = step.run(m, lattice.init_equilibrium(lat.shape), X0, n)
+    o, off, _ = sim.read_vertices()
+    Xg = o[:, None, :] + off.astype(np.float64)
+    bound = n * 6e-8 * np.abs(off).max() + 1e-4 * np.abs(X - X0).max()
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    print("12 steps", e_g, np.abs(Xg - X).max(), bound, flush=True)
+    assert e_g <= 1e-4 and np.abs(Xg - X).max() <= bound
+
+
+def test_relaxes_to_uniform_shear():
+    U = 0.02
+    lat = Lattice(8, 8, 16, tau=1.0, lees_edwards_u=U)
+    sim = _sim(lat)
+    sim.init_equilibrium()
+    sim.step(4000)
+    sim.sync()
+    rho, u = sim.read_macro()
+    z = np.arange(lat.nz)
+    exact = U * (z - (lat.nz - 1) / 2.0) / lat.nz
+    prof = u[0].mean(axis=(1, 2))
+    print("profile error", np.abs(prof - exact).max() / U, flush=True)
+    assert np.abs(prof - exact).max() <= 1e-4 * U
+
+
+def test_refused_combinations():
+    from paper_2305_02752_amd import HemoError
+    with pytest.raises(HemoError):
+        _sim(Lattice(16, 16, 16, bc=(0, 1, 0), lees_edwards_u=0.01))
+    with pytest.raises(HemoError):
+        _sim(Lattice(20, 16, 16, lees_edwards_u=0.01))
+    lat = Lattice(24, 20, 24, lees_edwards_u=0.01)
+    _, _, cells = _straddling_cell(lat, 45)
+    sim = _sim(lat, cells)
+    with pytest.raises(HemoError):
+        sim.adj_bind(10, 5)

@@ -40,6 +40,7 @@ class Lattice:
     wall_u_lo: tuple = (0.0, 0.0, 0.0)
     wall_u_hi: tuple = (0.0, 0.0, 0.0)
     ibm_kernel: int = 4          # 4: Peskin 4-point, 2: linear hat
+    lees_edwards_u: float = 0.0  # sheared periodic images along x across z (0: off)
 
     @property
     def shape(self):
