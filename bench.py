@@ -133,6 +133,32 @@ def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int
             "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
 
 
+def bench_lees_edwards(torch, w, warmup: int, steps: int, u_le: float = 0.02):
+    """The large suspension as a boundary-free shear: the same lattice and
+    cells with Lees-Edwards images (gradient z, flow x, image velocity u_le)
+    instead of the body force."""
+    import dataclasses
+
+    from paper_2305_02752_amd import Simulation
+    lat = dataclasses.replace(w.lattice, body_force=(0.0, 0.0, 0.0), lees_edwards_u=u_le)
+    sim = Simulation(lat, w.rest_pos, w.tri, max_cells=w.cells.n)
+    sim.set_cells(w.cells.origin, w.cells.offsets, w.cells.k, None)
+    sim.init_equilibrium()
+    sim.set_field_output(False)
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.close()
+    n = lat.nx * lat.ny * lat.nz
+    return {"u_le": u_le, "steps": steps, "ms_per_step": dt / steps * 1e3, "MLUPS": n * steps / dt / 1e6,
+            "kernel_ms": {k: ms / max(c, 1) for k, (ms, c) in prof.items()}}
+
+
 def bench_small(torch):
     """The single-cell shear box (32^3, 500 steps) and the dense channel
     (128x64x64, 220 cells, 1000 steps): whole runs, timed per step."""
@@ -343,8 +369,12 @@ def main():
         adj = bench_adjoint(torch, boxes=args.adjoint_boxes)
         log(f"adjoint: {adj['grads_per_s']:.2f} gradients/s, t_grad/t_fwd {adj['t_grad_over_t_forward']:.2f}")
 
-    small = None
+    small = lees = None
     if not args.no_extra:
+        log("Lees-Edwards shear of the same suspension ...")
+        lees = bench_lees_edwards(torch, w, args.warmup, args.steps)
+        torch.cuda.empty_cache()
+        log(f"  {lees['ms_per_step']:.3f} ms/step, {lees['MLUPS']:.0f} MLUPS")
         log("single-cell shear and dense channel ...")
         small = bench_small(torch)
         for k, v in small.items():
@@ -380,6 +410,7 @@ def main():
         "cpu_baseline": cpu,
         "separated_time_scales": tss,
         "small_workloads": small,
+        "lees_edwards_shear": lees,
         "batched_calibration": batched,
         "adjoint": adj,
     }
