@@ -27,6 +27,7 @@
 #include "common.h"
 #include "lbm_dev.h"
 #include "membrane_dev.h"
+#include "stencil.h"
 
 namespace hc {
 namespace {
@@ -36,26 +37,6 @@ using lbm::cy;
 using lbm::cz;
 using lbm::opp;
 using lbm::wq;
-
-__device__ inline float phi4(float r) {
-  r = fabsf(r);
-  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
-  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
-  return 0.f;
-}
-
-// d phi4 / dr.
-__device__ inline float dphi4(float r) {
-  const float a = fabsf(r), s = r < 0.f ? -1.f : 1.f;
-  if (a <= 1.f) return s * 0.25f * (-1.f + (1.f - 2.f * a) / sqrtf(1.f + 4.f * a - 4.f * a * a));
-  if (a < 2.f) return s * 0.25f * (-1.f - (3.f - 2.f * a) / sqrtf(-7.f + 12.f * a - 4.f * a * a));
-  return 0.f;
-}
-
-__device__ inline int wrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
-}
 
 __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ lam1,
                                                      float* __restrict__ lam0,

@@ -23,27 +23,10 @@
 #include "batch.h"
 #include "lbm_dev.h"
 #include "membrane_dev.h"
+#include "stencil.h"
 
 namespace hc {
 namespace {
-
-__device__ inline int wrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
-}
-
-__device__ inline float phi4(float r) {
-  r = fabsf(r);
-  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
-  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
-  return 0.f;
-}
-
-template <int K>
-__device__ inline float stencil_w(float f, int k) {
-  if (K == 4) return phi4(f + 1.f - (float)k);
-  return k == 0 ? 1.f - f : f;
-}
 
 // Does the node range [lo, hi] (unwrapped) meet [a, a + h) on an axis of n nodes?
 __device__ inline bool range_meets(int lo, int hi, int a, int h, int n, bool wall) {

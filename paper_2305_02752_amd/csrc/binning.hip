@@ -15,11 +15,6 @@
 namespace hc {
 namespace {
 
-__device__ inline int wrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
-}
-
 __global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
   extern __shared__ unsigned short slots[];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];

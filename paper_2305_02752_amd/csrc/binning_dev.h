@@ -2,15 +2,10 @@
 // binning kernels and the fused per-cell kernel.
 #pragma once
 
-#include "common.h"
+#include "stencil.h"
 
 namespace hc {
 namespace bin {
-
-__device__ inline int bwrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
-}
 
 // Distinct tiles reached along one axis by K stencil nodes starting at p0,
 // appended to out[cnt, cap) (already listed tiles are skipped).
@@ -21,7 +16,7 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out, int c
     if (wall) {
       if (p < 0 || p >= n) continue;
     } else {
-      p = bwrap(p, n);
+      p = wrap(p, n);
     }
     const int t = p / kTile;
     bool seen = false;
@@ -45,7 +40,7 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
   for (int d = 0; d < 3; ++d) {
     const int p = C.origin[3 * c + d] + (int)floorf(o[d]);
     nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
-    own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : bwrap(p, n[d])) / kTile;
+    own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : wrap(p, n[d])) / kTile;
   }
   if (L.le) {
     const int pz = C.origin[3 * c + 2] + (int)floorf(o[2]);
@@ -54,7 +49,7 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
     nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xa) + b, K, L.nx, 0, T[0], 0, 4);
     if (mb != ma) nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xb) + b, K, L.nx, 0, T[0], nT[0], 4);
     const float xo = o[0] - (float)floor_div(pz, L.nz) * L.le_delta;
-    own[0] = bwrap(C.origin[3 * c] + (int)floorf(xo), L.nx) / kTile;
+    own[0] = wrap(C.origin[3 * c] + (int)floorf(xo), L.nx) / kTile;
   }
   return (own[2] * L.ty + own[1]) * L.tx + own[0];
 }

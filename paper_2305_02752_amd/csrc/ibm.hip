@@ -21,14 +21,6 @@
 namespace hc {
 namespace {
 
-using ibmd::phi4;
-using ibmd::stencil_w;
-
-__device__ inline int wrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
-}
-
 // Per-axis stencil of one vertex relative to a tile starting at t0: local
 // node index inside the tile (-1 outside the tile or beyond a wall) and
 // weight; the first node is floor(X) - 1 (K = 4) or floor(X) (K = 2).

@@ -5,23 +5,10 @@
 #pragma once
 
 #include "common.h"
+#include "stencil.h"
 
 namespace hc {
 namespace ibmd {
-
-__device__ inline float phi4(float r) {
-  r = fabsf(r);
-  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
-  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
-  return 0.f;
-}
-
-// Weight of stencil node k (0..K-1) for fractional position f in [0, 1).
-template <int K>
-__device__ inline float stencil_w(float f, int k) {
-  if (K == 4) return phi4(f + 1.f - (float)k);
-  return k == 0 ? 1.f - f : f;
-}
 
 // Vertex velocity = tile partials summed in slot order (fixed, so the result
 // is reproducible) + stencil nodes beyond a wall at the wall velocity; then
@@ -57,8 +44,8 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int p = base + k;
-      if (p < 0) wlo += stencil_w<K>(od - fl, k);
-      if (p >= n) whi += stencil_w<K>(od - fl, k);
+      if (p < 0) wlo += hc::stencil_w<K>(od - fl, k);
+      if (p >= n) whi += hc::stencil_w<K>(od - fl, k);
     }
     Ux += wlo * L.ulo[0] + whi * L.uhi[0];
     Uy += wlo * L.ulo[1] + whi * L.uhi[1];

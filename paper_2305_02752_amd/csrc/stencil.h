@@ -1,0 +1,39 @@
+// The immersed-boundary stencil shared by every kernel that spreads or
+// interpolates (Sec. 2.3): Peskin's 4-point function, its derivative (for
+// the reverse sweep), the weight of stencil position k, and periodic index
+// wrapping.  Stencil nodes of a vertex at x are floor(x) - 1 .. floor(x) + 2
+// (4-point) or floor(x), floor(x) + 1 (the 2-point linear hat).
+#pragma once
+
+#include "common.h"
+
+namespace hc {
+
+__host__ __device__ inline int wrap(int p, int n) {
+  p %= n;
+  return p < 0 ? p + n : p;
+}
+
+__device__ inline float phi4(float r) {
+  r = fabsf(r);
+  if (r <= 1.f) return 0.125f * (3.f - 2.f * r + sqrtf(1.f + 4.f * r - 4.f * r * r));
+  if (r < 2.f) return 0.125f * (5.f - 2.f * r - sqrtf(-7.f + 12.f * r - 4.f * r * r));
+  return 0.f;
+}
+
+// d phi4 / dr.
+__device__ inline float dphi4(float r) {
+  const float a = fabsf(r), s = r < 0.f ? -1.f : 1.f;
+  if (a <= 1.f) return s * 0.25f * (-1.f + (1.f - 2.f * a) / sqrtf(1.f + 4.f * a - 4.f * a * a));
+  if (a < 2.f) return s * 0.25f * (-1.f - (3.f - 2.f * a) / sqrtf(-7.f + 12.f * a - 4.f * a * a));
+  return 0.f;
+}
+
+// Weight of stencil position k (0..K-1) for fractional position f in [0, 1).
+template <int K>
+__device__ inline float stencil_w(float f, int k) {
+  if (K == 4) return phi4(f + 1.f - (float)k);
+  return k == 0 ? 1.f - f : f;
+}
+
+}  // namespace hc
