@@ -19,7 +19,7 @@ import dataclasses
 
 import numpy as np
 
-from . import ibm, lattice, lees_edwards, membrane
+from . import ibm, interior, lattice, lees_edwards, membrane
 
 
 @dataclasses.dataclass
@@ -36,9 +36,11 @@ class Model:
     k: np.ndarray          # [C, 4]
     traction: np.ndarray | None
     le_u: float = 0.0      # Lees-Edwards image velocity along x (gradient axis z); 0: off
+    interior_ratio: float = 1.0   # viscosity ratio inside the cells (1: off)
 
 
-def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0) -> Model:
+def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0,
+               interior_ratio: float = 1.0) -> Model:
     topo = membrane.Topology(tri, rest_pos.shape[0])
     rest = membrane.RestState(np.asarray(rest_pos, dtype=np.float64), topo)
     return Model(dims=(lat.nx, lat.ny, lat.nz), bc=tuple(lat.bc), tau=float(lat.tau),
@@ -47,7 +49,7 @@ def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0) -> Model
                  kernel=int(lat.ibm_kernel), topo=topo, rest=rest,
                  k=np.asarray(k, dtype=np.float64),
                  traction=None if traction is None else np.asarray(traction, dtype=np.float64),
-                 le_u=float(le_u))
+                 le_u=float(le_u), interior_ratio=float(interior_ratio))
 
 
 def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 0):
@@ -75,7 +77,11 @@ def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 
                             m.kernel).reshape(X.shape)
     else:
         U = np.zeros_like(X)
-    post = lattice.collide(f, rho, u, F, m.tau)
+    tau = m.tau
+    if C and m.interior_ratio != 1.0:
+        tau = interior.site_tau(interior.inside_sites(X, m.topo.tri, m.dims, m.bc), m.tau,
+                                m.interior_ratio)
+    post = lattice.collide(f, rho, u, F, tau)
     if le:
         f_new = lees_edwards.stream(post, m.le_u, delta)
     else:

@@ -1,0 +1,69 @@
+"""Pins of the interior-site oracle (ray parity) and of per-site relaxation.
+
+* sphere: sites well inside the inscribed sphere of an icosphere mesh are
+  inside, sites outside its circumscribed sphere are outside;
+* the parity does not depend on the ray direction: casting along x instead
+  of z (coordinates permuted) marks the same sites for a generic placement;
+* translating a cell across a periodic boundary by whole nodes translates
+  its mask;
+* per-site relaxation is local: with one relaxation time everywhere it is
+  the scalar collision, and each site relaxes with its own time.
+"""
+import numpy as np
+
+from oracle import interior, lattice
+from workloads import rbc_mesh
+from workloads.mesh import sphere_mesh
+
+
+def test_sphere_inside_outside():
+    R = 7.0
+    V, tri = sphere_mesh(3, R)
+    c = np.array([12.31, 11.77, 10.52])
+    mask = interior.inside_sites((V + c)[None], tri, (24, 24, 22), (0, 0, 0))
+    z, y, x = np.meshgrid(np.arange(22), np.arange(24), np.arange(24), indexing="ij")
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    r_in = R * 0.99     # faces of a level-3 icosphere lie within 1% of R
+    assert mask[r < r_in - 1e-6].all()
+    assert not mask[r > R + 1e-6].any()
+
+
+def test_parity_independent_of_ray_direction():
+    rest, tri = rbc_mesh()
+    rng = np.random.default_rng(5)
+    th = rng.uniform(0, 2 * np.pi)
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    Ry = np.array([[np.cos(0.7), 0, np.sin(0.7)], [0, 1.0, 0], [-np.sin(0.7), 0, np.cos(0.7)]])
+    X = rest @ (Rz @ Ry).T + np.array([16.137, 15.791, 14.263])
+    dims = (32, 32, 30)
+    mz = interior.inside_sites(X[None], tri, dims, (0, 0, 0))
+    # cast along x: swap the x and z coordinates (orientation flips, parity does not)
+    Xs = X[:, [2, 1, 0]]
+    mx = interior.inside_sites(Xs[None], tri, (dims[2], dims[1], dims[0]), (0, 0, 0))
+    assert mz.sum() > 500
+    assert np.array_equal(mz, np.transpose(mx, (2, 1, 0)))
+
+
+def test_periodic_translation():
+    rest, tri = rbc_mesh()
+    X = rest + np.array([10.21, 9.87, 8.43])
+    dims = (20, 20, 18)
+    m0 = interior.inside_sites(X[None], tri, dims, (0, 0, 0))
+    shift = np.array([13, -7, 11])
+    m1 = interior.inside_sites((X + shift)[None], tri, dims, (0, 0, 0))
+    assert np.array_equal(np.roll(m0, (shift[2], shift[1], shift[0]), axis=(0, 1, 2)), m1)
+
+
+def test_per_site_relaxation_is_local():
+    rng = np.random.default_rng(6)
+    f = lattice.init_equilibrium((6, 5, 4)) + 1e-3 * rng.standard_normal((19, 6, 5, 4))
+    F = 1e-5 * rng.standard_normal((3, 6, 5, 4))
+    rho, u = lattice.moments(f, F)
+    ref = lattice.collide(f, rho, u, F, 0.8)
+    assert np.allclose(lattice.collide(f, rho, u, F, np.full((6, 5, 4), 0.8)), ref, rtol=0, atol=1e-16)
+    tau = np.where(rng.uniform(size=(6, 5, 4)) < 0.5, 0.8, 2.5)
+    post = lattice.collide(f, rho, u, F, tau)
+    ref2 = lattice.collide(f, rho, u, F, 2.5)
+    sel = tau == 2.5
+    assert np.allclose(post[:, sel], ref2[:, sel], rtol=0, atol=1e-16)
+    assert np.allclose(post[:, ~sel], ref[:, ~sel], rtol=0, atol=1e-16)
