@@ -55,22 +55,29 @@ def crossings(V: np.ndarray, tri: np.ndarray, x: np.ndarray, y: np.ndarray):
     return [np.sort(z[j][inside[j]]) for j in range(x.shape[0])]
 
 
-def inside_sites(X: np.ndarray, tri: np.ndarray, dims, bc) -> np.ndarray:
-    """Boolean [nz, ny, nx]: the sites inside any cell (X [C, nv, 3])."""
+def inside_sites(X: np.ndarray, tri: np.ndarray, dims, bc, origin=None) -> np.ndarray:
+    """Boolean [nz, ny, nx]: the sites inside any cell.  X [C, nv, 3] holds
+    positions (float64 arithmetic), or, with integer origins [C, 3], each
+    cell's vertex offsets from its origin: then the crossings are found in
+    those local coordinates in X's own precision, which lets a float32
+    caller reproduce the decisions of a float32 implementation exactly."""
     nx, ny, nz = dims
     n = (nx, ny, nz)
     mask = np.zeros((nz, ny, nx), dtype=bool)
     tri = np.asarray(tri, dtype=np.int64)
-    for V in np.asarray(X, dtype=np.float64):
+    X = np.asarray(X)
+    dt = X.dtype if origin is not None else np.float64
+    for c, V in enumerate(X.astype(dt)):
+        o = np.zeros(3, np.int64) if origin is None else np.asarray(origin[c], dtype=np.int64)
         lo = np.ceil(V.min(axis=0)).astype(np.int64)
         hi = np.floor(V.max(axis=0)).astype(np.int64)
         gx, gy = np.meshgrid(np.arange(lo[0], hi[0] + 1), np.arange(lo[1], hi[1] + 1), indexing="ij")
         gx, gy = gx.ravel(), gy.ravel()
-        zs = crossings(V, tri, gx.astype(np.float64), gy.astype(np.float64))
+        zs = crossings(V, tri, gx.astype(dt), gy.astype(dt))
         for ix, iy, z in zip(gx, gy, zs):
             for k in range(0, len(z) - 1, 2):
-                iz = np.arange(np.floor(z[k]) + 1, np.ceil(z[k + 1])).astype(np.int64)
-                idx = [np.int64(ix), np.int64(iy), iz]
+                iz = np.arange(np.floor(z[k]) + 1, np.ceil(z[k + 1])).astype(np.int64) + o[2]
+                idx = [np.int64(ix) + o[0], np.int64(iy) + o[1], iz]
                 ok = np.ones(iz.shape, dtype=bool)
                 for d in range(3):
                     if bc[d] == WALL:

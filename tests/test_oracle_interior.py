@@ -67,3 +67,21 @@ def test_per_site_relaxation_is_local():
     sel = tau == 2.5
     assert np.allclose(post[:, sel], ref2[:, sel], rtol=0, atol=1e-16)
     assert np.allclose(post[:, ~sel], ref[:, ~sel], rtol=0, atol=1e-16)
+
+
+def test_local_float32_mode_matches_positions():
+    """Offsets from integer origins in float32 mark what the float64
+    positions mark (generic placements: no crossing within rounding of a
+    node), including cells that wrap across periodic sides."""
+    rest, tri = rbc_mesh()
+    rng = np.random.default_rng(8)
+    dims = (40, 36, 34)
+    origin = np.array([[3, 30, 5], [20, 17, 30], [37, 2, 17]])
+    off = np.stack([rest @ np.linalg.qr(rng.standard_normal((3, 3)))[0].T + rng.uniform(0, 1, 3)
+                    for _ in range(3)])
+    off32 = off.astype(np.float32)
+    X = origin[:, None, :] + off32.astype(np.float64)
+    m64 = interior.inside_sites(X, tri, dims, (0, 0, 0))
+    m32 = interior.inside_sites(off32, tri, dims, (0, 0, 0), origin=origin)
+    assert m64.sum() > 1500
+    assert np.array_equal(m64, m32)
