@@ -133,6 +133,26 @@ def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int
             "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
 
 
+def bench_interior(sim, n_sites: int, warmup: int, steps: int, ratio: float = 5.0):
+    """The same suspension with the cytosol `ratio` times as viscous as the
+    plasma: the sites inside the cells are marked every step and relax with
+    the interior relaxation time."""
+    sim.set_interior_viscosity(ratio)
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.set_interior_viscosity(1.0)
+    return {"ratio": ratio, "steps": steps, "ms_per_step": dt / steps * 1e3,
+            "MLUPS": n_sites * steps / dt / 1e6,
+            "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
+
+
 def bench_lees_edwards(torch, w, warmup: int, steps: int, u_le: float = 0.02):
     """The large suspension as a boundary-free shear: the same lattice and
     cells with Lees-Edwards images (gradient z, flow x, image velocity u_le)
@@ -350,11 +370,14 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_s * 1e3}
 
-    tss = None
+    tss = interior = None
     if not args.no_extra:
         tss = bench_separated(sim, n_sites, args.warmup, args.steps)
         log(f"separated time scales (forces every {tss['force_every']}, {tss['scheme']}): "
             f"{tss['ms_per_step']:.3f} ms/step, {tss['MLUPS']:.0f} MLUPS")
+        interior = bench_interior(sim, n_sites, args.warmup, args.steps)
+        log(f"interior viscosity ratio {interior['ratio']}: {interior['ms_per_step']:.3f} ms/step, "
+            f"marking {interior['kernel_ms']['interior']:.3f} ms")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -409,6 +432,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "separated_time_scales": tss,
+        "interior_viscosity": interior,
         "small_workloads": small,
         "lees_edwards_shear": lees,
         "batched_calibration": batched,

@@ -203,6 +203,39 @@ hc_status hc_checkpoint_restore(hc_ctx* ctx, const void* host, size_t bytes);
 enum { HC_EULER = 0, HC_AB2 = 1 };
 hc_status hc_set_integration(hc_ctx* ctx, int32_t force_every, int32_t scheme);
 
+/* Interior viscosity (Sec. 1: the cytosol is more viscous than plasma;
+ * Sec. 3.4: stiffened cells raise the internal viscosity ratio).  Sites
+ * inside a cell relax with tau_in = 1/2 + ratio (tau - 1/2); the others
+ * with tau.  A site is inside by ray parity along z: the vertical line
+ * through it crosses the membrane at z_1 < z_2 < ..., and the site lies
+ * strictly between z_(2k-1) and z_(2k); a point on a projected triangle
+ * edge is counted by exactly one of the two triangles sharing the edge.
+ * The marks are recomputed every step from the positions the step spreads
+ * from.  ratio > 0; 1 (the default) switches the marking off.  Limits per
+ * cell: a bounding box of at most 1024 (x, y) node columns and 8 membrane
+ * crossings per column (hc_sync reports HC_ERR_UNSUPPORTED beyond).  Not
+ * combined with Lees-Edwards images or the adjoint calls
+ * (HC_ERR_UNSUPPORTED). */
+hc_status hc_set_interior_viscosity(hc_ctx* ctx, float ratio);
+
+/* One interior viscosity ratio per current cell, ratio [n_cells] (mixtures
+ * of healthy and stiffened cells, Sec. 3.4), at most 8 distinct values
+ * (HC_ERR_UNSUPPORTED beyond).  A site inside several cells (overlap) takes
+ * the largest of their ratios.  Replaces the single ratio until the next
+ * hc_set_cells or hc_set_interior_viscosity call, either of which returns
+ * to the single ratio of the last hc_set_interior_viscosity (1 if none).
+ * Same refusals as hc_set_interior_viscosity; n_cells must equal the
+ * current cell count. */
+hc_status hc_set_cell_viscosity(hc_ctx* ctx, const float* ratio, int64_t n_cells);
+
+/* The inside marks of the current positions (after applying a pending
+ * vertex move), uint8 [N] in natural site order (x fastest): bit k is set
+ * when a cell of viscosity class k contains the site (classes are the
+ * distinct ratios in increasing order; a single ratio is class 0), 0
+ * outside every cell.  Synchronous; reports marking overflows as hc_sync
+ * does. */
+hc_status hc_read_interior(hc_ctx* ctx, uint8_t* inside, int64_t n_sites);
+
 /* Per-kernel timing.  hc_profile(ctx, 1) clears the record and brackets
  * every subsequent launch of the step with events on the context stream;
  * hc_profile_read waits for the stream and returns, per kernel family
@@ -212,7 +245,8 @@ enum {
   HC_K_CELL = 0,     /* per cell: pending vertex move, membrane forces, binning */
   HC_K_LATTICE = 1,  /* per tile: IBM spread, collide + stream, IBM interpolation */
   HC_K_ADVECT = 2,   /* vertex move closing the last step of an hc_step call */
-  HC_NUM_KERNELS = 3
+  HC_K_INTERIOR = 3, /* per cell: marking of the sites inside it (interior viscosity) */
+  HC_NUM_KERNELS = 4
 };
 hc_status hc_profile(hc_ctx* ctx, int32_t enable);
 hc_status hc_profile_read(hc_ctx* ctx, double* total_ms, int64_t* launches);

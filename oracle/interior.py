@@ -89,6 +89,25 @@ def inside_sites(X: np.ndarray, tri: np.ndarray, dims, bc, origin=None) -> np.nd
     return mask
 
 
+def ratio_field(X: np.ndarray, tri: np.ndarray, dims, bc, ratios, origin=None) -> np.ndarray:
+    """Viscosity ratio per site [nz, ny, nx] with one ratio per cell
+    (mixtures of healthy and stiffened cells, Sec. 3.4): the ratio of the
+    cell containing the site, the largest one where cells overlap, and 0
+    where no cell does.  X, origin: as for inside_sites."""
+    nx, ny, nz = dims
+    r = np.zeros((nz, ny, nx))
+    for c in range(np.asarray(X).shape[0]):
+        m = inside_sites(np.asarray(X)[c:c + 1], tri, dims, bc,
+                         None if origin is None else np.asarray(origin)[c:c + 1])
+        r[m] = np.maximum(r[m], float(ratios[c]))
+    return r
+
+
+def tau_field(r: np.ndarray, tau: float) -> np.ndarray:
+    """Per-site relaxation time from a ratio field (0: plasma)."""
+    return np.where(r > 0, 0.5 + r * (tau - 0.5), tau)
+
+
 def site_tau(mask: np.ndarray, tau: float, ratio: float) -> np.ndarray:
     """Per-site relaxation time: tau inside cells scaled to ratio times the viscosity."""
     return np.where(mask, 0.5 + ratio * (tau - 0.5), tau)

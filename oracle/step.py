@@ -36,11 +36,11 @@ class Model:
     k: np.ndarray          # [C, 4]
     traction: np.ndarray | None
     le_u: float = 0.0      # Lees-Edwards image velocity along x (gradient axis z); 0: off
-    interior_ratio: float = 1.0   # viscosity ratio inside the cells (1: off)
+    interior_ratio: float | np.ndarray = 1.0   # viscosity ratio inside the cells, one or per cell (1: off)
 
 
 def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0,
-               interior_ratio: float = 1.0) -> Model:
+               interior_ratio=1.0) -> Model:
     topo = membrane.Topology(tri, rest_pos.shape[0])
     rest = membrane.RestState(np.asarray(rest_pos, dtype=np.float64), topo)
     return Model(dims=(lat.nx, lat.ny, lat.nz), bc=tuple(lat.bc), tau=float(lat.tau),
@@ -49,7 +49,9 @@ def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0,
                  kernel=int(lat.ibm_kernel), topo=topo, rest=rest,
                  k=np.asarray(k, dtype=np.float64),
                  traction=None if traction is None else np.asarray(traction, dtype=np.float64),
-                 le_u=float(le_u), interior_ratio=float(interior_ratio))
+                 le_u=float(le_u),
+                 interior_ratio=(float(interior_ratio) if np.ndim(interior_ratio) == 0
+                                 else np.asarray(interior_ratio, dtype=np.float64)))
 
 
 def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 0):
@@ -78,9 +80,9 @@ def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 
     else:
         U = np.zeros_like(X)
     tau = m.tau
-    if C and m.interior_ratio != 1.0:
-        tau = interior.site_tau(interior.inside_sites(X, m.topo.tri, m.dims, m.bc), m.tau,
-                                m.interior_ratio)
+    ratios = np.broadcast_to(np.asarray(m.interior_ratio, dtype=np.float64), (C,))
+    if C and np.any(ratios != 1.0):
+        tau = interior.tau_field(interior.ratio_field(X, m.topo.tri, m.dims, m.bc, ratios), m.tau)
     post = lattice.collide(f, rho, u, F, tau)
     if le:
         f_new = lees_edwards.stream(post, m.le_u, delta)

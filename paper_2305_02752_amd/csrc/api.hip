@@ -65,6 +65,16 @@ struct hc_ctx {
   int force_every = 1;
   int scheme = HC_EULER;
   bool have_prev = false;
+  // interior viscosity (Sec. 1, Sec. 3.4): sites inside the cells relax with
+  // ratio times the plasma viscosity.  One ratio for every cell
+  // (uniform_ratio; 1 switches the marking off) or one per cell, as up to
+  // kVisClasses distinct ratios (class_ratio, increasing) and a class per cell
+  float uniform_ratio = 1.f;
+  int n_vclass = 1;
+  float class_ratio[kVisClasses] = {1.f};
+  bool per_cell_ratio = false;
+  unsigned char* mask = nullptr;   // [np] site-ordered inside marks, zero between steps
+  unsigned char* cell_class = nullptr;   // [max_cells] viscosity class of each cell
   // optional per-kernel timing with events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -85,7 +95,7 @@ struct hc_ctx {
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
   size_t o_owner, o_ntouch, o_scan, o_slot, o_tcnt, o_tptr, o_touch, o_csr, o_flags;
-  size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist;
+  size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist, o_mask, o_cclass;
 };
 
 namespace {
@@ -149,6 +159,8 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_ctiles = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
   c->o_crank = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
   c->o_clist = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
+  c->o_mask = lay.add(N);
+  c->o_cclass = lay.add(std::max<int64_t>(1, C));
 }
 
 hc_status need_ws(hc_ctx* c) {
@@ -198,6 +210,29 @@ hc_status copy_d2d(hc_ctx* c, void* dst, const void* src, size_t bytes) {
 // Lees-Edwards image displacements U t mod nx (in double: t grows) for the
 // step about to run (IBM stencils) and for the step before it, whose
 // streaming the next pull completes.
+bool interior_on(const hc_ctx* c) { return c->n_vclass > 1 || c->class_ratio[0] != 1.f; }
+
+// Relaxation rates inside the cells: tau_in - 1/2 = ratio (tau - 1/2).
+void interior_update(hc_ctx* c) {
+  for (int k = 0; k < kVisClasses; ++k) {
+    const double r = k < c->n_vclass ? c->class_ratio[k] : 1.0;
+    c->L.omega_in[k] = (float)(1.0 / (0.5 + r * ((double)c->L.tau - 0.5)));
+  }
+}
+
+void interior_uniform(hc_ctx* c) {
+  c->per_cell_ratio = false;
+  c->n_vclass = 1;
+  c->class_ratio[0] = c->uniform_ratio;
+  interior_update(c);
+}
+
+hipError_t mark_interior(hc_ctx* c, const Cells& C) {
+  const bool multi = c->n_vclass > 1;
+  return launch_mark_interior(C, c->M, c->L, c->mask, multi ? c->cell_class : nullptr, multi,
+                              c->B.flags, c->stream);
+}
+
 void le_update(hc_ctx* c) {
   if (!c->L.le) return;
   auto shift = [&](int64_t t) {
@@ -225,9 +260,14 @@ hc_status one_step(hc_ctx* c) {
                             c->stream);
   }));
   if (adv) c->have_prev = true;
+  unsigned char* mask = nullptr;
+  if (interior_on(c) && C.n > 0) {
+    mask = c->mask;
+    HC_TRY(timed(c, HC_K_INTERIOR, "interior marking", [&] { return mark_interior(c, C); }));
+  }
   HC_TRY(timed(c, HC_K_LATTICE, "lattice pass", [&] {
     return launch_tile_step(C, c->M, c->L, c->B, c->pops[c->cur], c->pops[c->cur ^ 1], c->F,
-                            c->macro, c->partial, c->fields, c->stream);
+                            c->macro, c->partial, c->fields, mask, c->stream);
   }));
   c->advect_pending = C.n > 0;
   c->cur ^= 1;
@@ -305,7 +345,7 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
                                    false, c->stream),
                "cell step"));
   HC_TRY(check(c, launch_tile_step(Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
-                                   Fi, Mi, c->partial, true, c->stream),
+                                   Fi, Mi, c->partial, true, nullptr, c->stream),
                "lattice pass"));
   return HC_OK;
 }
@@ -527,6 +567,9 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   c->cell_tiles = at<int>(c, c->o_ctiles);
   c->cell_rank = at<int>(c, c->o_crank);
   c->cell_list = at<int>(c, c->o_clist);
+  c->mask = at<unsigned char>(c, c->o_mask);
+  c->cell_class = at<unsigned char>(c, c->o_cclass);
+  interior_update(c);
   HC_TRY(copy_h2d(c, (void*)M.tri, m.tri.data(), m.tri.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.edge, m.edge.data(), m.edge.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.L0, m.L0.data(), m.L0.size() * 4));
@@ -535,6 +578,8 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
   HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
   HC_TRY(check(c, launch_fill_i32(B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->mask), 0, c->L.np / 4, c->stream),
+               "clear interior marks"));
   HC_TRY(check(c, launch_init_equilibrium(c->pops[0], 1.f, 0.f, 0.f, 0.f, c->L, c->stream), "init"));
   return sync(c, "bind");
 }
@@ -558,6 +603,7 @@ hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float*
   c->have_cells = n > 0;
   c->advect_pending = false;
   c->have_prev = false;
+  if (c->per_cell_ratio) interior_uniform(c);   // per-cell ratios belong to the old cells
   HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
   return sync(c, "set_cells");
@@ -592,6 +638,10 @@ hc_status hc_sync(hc_ctx* c) {
     if (flags[1] & 2) return fail(c, HC_ERR_DEVICE, "touch slots overflow");
     if (flags[1] & 4) return fail(c, HC_ERR_UNSUPPORTED, "a tile list exceeded its capacity");
     if (flags[1] & 8) return fail(c, HC_ERR_UNSUPPORTED, "a cell reaches more than 256 tiles");
+    if (flags[1] & 16)
+      return fail(c, HC_ERR_UNSUPPORTED, "a cell spans more than 1024 node columns (interior marking)");
+    if (flags[1] & 32)
+      return fail(c, HC_ERR_UNSUPPORTED, "a node column crosses a membrane more than 8 times");
     return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");
   }
   return HC_OK;
@@ -809,6 +859,67 @@ hc_status hc_set_integration(hc_ctx* c, int32_t force_every, int32_t scheme) {
   return HC_OK;
 }
 
+hc_status hc_set_interior_viscosity(hc_ctx* c, float ratio) {
+  if (!c) return HC_ERR_ARG;
+  if (!std::isfinite(ratio) || !(ratio > 0.f)) return fail(c, HC_ERR_ARG, "ratio must be positive");
+  if (ratio != 1.f && c->L.le)
+    return fail(c, HC_ERR_UNSUPPORTED, "interior viscosity is not combined with Lees-Edwards images");
+  if (ratio != 1.f && c->adj_ready)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
+  c->uniform_ratio = ratio;
+  interior_uniform(c);
+  return HC_OK;
+}
+
+hc_status hc_set_cell_viscosity(hc_ctx* c, const float* ratio, int64_t n_cells) {
+  HC_TRY(need_ws(c));
+  if (!ratio || n_cells != c->C.n) return fail(c, HC_ERR_ARG, "one ratio per current cell");
+  std::vector<float> cls;
+  for (int64_t i = 0; i < n_cells; ++i) {
+    if (!std::isfinite(ratio[i]) || !(ratio[i] > 0.f)) return fail(c, HC_ERR_ARG, "ratios must be positive");
+    cls.push_back(ratio[i]);
+  }
+  std::sort(cls.begin(), cls.end());
+  cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+  if ((int)cls.size() > kVisClasses)
+    return fail(c, HC_ERR_UNSUPPORTED, "more than 8 distinct interior viscosity ratios");
+  const bool on = cls.size() > 1 || (!cls.empty() && cls[0] != 1.f);
+  if (on && c->L.le)
+    return fail(c, HC_ERR_UNSUPPORTED, "interior viscosity is not combined with Lees-Edwards images");
+  if (on && c->adj_ready)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
+  std::vector<uint8_t> k((size_t)n_cells);
+  for (int64_t i = 0; i < n_cells; ++i)
+    k[i] = (uint8_t)(std::lower_bound(cls.begin(), cls.end(), ratio[i]) - cls.begin());
+  HC_TRY(copy_h2d(c, c->cell_class, k.data(), (size_t)n_cells));
+  HC_TRY(sync(c, "set cell viscosity"));
+  c->per_cell_ratio = true;
+  c->n_vclass = std::max<int>(1, (int)cls.size());
+  for (int i = 0; i < kVisClasses; ++i) c->class_ratio[i] = i < (int)cls.size() ? cls[i] : 1.f;
+  interior_update(c);
+  return HC_OK;
+}
+
+hc_status hc_read_interior(hc_ctx* c, uint8_t* host, int64_t n_sites) {
+  HC_TRY(need_ws(c));
+  if (!host || n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
+  HC_TRY(flush(c));
+  Cells C = c->C;
+  C.n = c->have_cells ? c->C.n : 0;
+  const Lattice& L = c->L;
+  HC_TRY(check(c, mark_interior(c, C), "interior marking"));
+  std::vector<uint8_t> m((size_t)L.np);
+  HC_TRY(copy_d2h(c, m.data(), c->mask, (size_t)L.np));
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->mask), 0, L.np / 4, c->stream),
+               "clear interior marks"));
+  HC_TRY(hc_sync(c));
+  for (int z = 0; z < L.nz; ++z)
+    for (int y = 0; y < L.ny; ++y)
+      for (int x = 0; x < L.nx; ++x)
+        host[((int64_t)z * L.ny + y) * L.nx + x] = m[(size_t)site_of(L, x, y, z)];
+  return HC_OK;
+}
+
 hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (!dst || !src || ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) ||
       (bytes & 15))
@@ -824,6 +935,7 @@ hc_status hc_set_params(hc_ctx* c, const float* k, float tau) {
   if (k) HC_TRY(copy_h2d(c, (void*)c->C.k, k, (size_t)c->C.n * 16));
   c->L.tau = tau;
   c->L.omega = 1.0f / tau;
+  interior_update(c);
   return sync(c, "set params");
 }
 
@@ -841,6 +953,8 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   if (c->L.kernel != HC_PHI4)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
   if (c->L.le) return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover Lees-Edwards images");
+  if (interior_on(c))
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
   if (c->force_every != 1 || c->scheme != HC_EULER)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int ck = std::min(ckpt_every, n_steps);

@@ -26,6 +26,9 @@ constexpr double kFixInv = 1.0 / 1099511627776.0;
 // result.
 constexpr float kFix32Max = 2147483520.0f;
 
+// Distinct interior viscosity ratios (classes) one lattice may hold at once.
+constexpr int kVisClasses = 8;
+
 [[maybe_unused]] static __device__ __noinline__ void fix_add3_wide(long long* a0, long long* a1,
                                                                    long long* a2, float x, float y,
                                                                    float z) {
@@ -61,6 +64,8 @@ struct Lattice {
   float le_pull_delta;      // displacement of the previous step, whose streaming the pull completes
   int le_raw;               // the stored state is a plain permutation of the pre-collision
                             // populations (fresh from a write or init): pull periodically
+  float omega_in[kVisClasses];   // relaxation rates inside the cells, per viscosity class
+                                 // (classes in increasing viscosity ratio)
   int64_t n;                // nx * ny * nz
   int64_t np;               // ntiles * 512: site slots of every lattice field
   int tx, ty, tz, ntiles;   // tile grid
@@ -161,7 +166,15 @@ hipError_t launch_advect(const Cells& c, const Mesh& m, const Lattice& L, const 
 // with fields set it also writes the force field F and (u, rho) to macro
 hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float* gin, float* gout, float* F, float4* macro, float4* partial,
-                            bool fields, hipStream_t s);
+                            bool fields, unsigned char* mask, hipStream_t s);
+// Mark the sites inside the cells in the site-ordered mask, which must hold
+// zeros on entry: bit k of a site's byte is set when a cell of viscosity
+// class k (cls[c], or 0 for every cell when cls is null) contains it.  With
+// several classes (multi) the bits are OR-ed atomically, so overlapping
+// cells of different classes mark deterministically.  The lattice pass reads
+// and clears the mask.
+hipError_t launch_mark_interior(const Cells& c, const Mesh& m, const Lattice& L, unsigned char* mask,
+                                const unsigned char* cls, bool multi, int* flags, hipStream_t s);
 // fused per-cell kernel: [advect of the pending step] + membrane + binning
 // (src: offsets to move from, or null to move in place; refresh: compute
 // the membrane forces, else hold the stored ones; ab2: Adams-Bashforth move)

@@ -288,7 +288,9 @@ __host__ __device__ inline int tile_grid(const Lattice& L) { return ((L.ntiles +
 //  2. pull-stream + collide the tile's nodes (force = body force + spread
 //     field) and store their post-collision populations, keeping (u, rho)
 //     in LDS (and writing the force and (u, rho) fields out when fields is
-//     non-zero);
+//     non-zero); a site whose byte in mask (when given) is non-zero lies
+//     inside a cell and relaxes at L.omega_in of its highest set bit (the
+//     most viscous class containing it), and its byte is cleared;
 //  3. interpolate u to the tile's entries into their partial-sum slots.
 // The force and velocity fields never leave the chip.
 template <int K, bool LE>
@@ -297,7 +299,8 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
                                                    float* __restrict__ gout,
                                                    float* __restrict__ F,
                                                    float4* __restrict__ macro,
-                                                   float4* __restrict__ partial, int fields) {
+                                                   float4* __restrict__ partial, int fields,
+                                                   unsigned char* __restrict__ mask) {
   __shared__ long long acc[3][kTile * kTile * kTile];
   __shared__ float4 su[kTile * kTile * kTile];
   const int t = tile_of_block(L, blockIdx.x);
@@ -335,10 +338,18 @@ __global__ __launch_bounds__(256) void k_tile_step(Cells C, Mesh M, Lattice L, B
     const float fy = L.g[1] + (float)((double)acc[1][i] * kFixInv);
     const float fz = L.g[2] + (float)((double)acc[2][i] * kFixInv);
     float rho, ux, uy, uz;
-    lbm::collide(g, fx, fy, fz, L.omega, rho, ux, uy, uz);
+    const int64_t h = h0 + i;
+    float omega = L.omega;
+    if (mask) {
+      const unsigned b = mask[h];
+      if (b) {   // inside a cell: the most viscous class containing the site
+        omega = L.omega_in[31 - __clz(b)];
+        mask[h] = 0;
+      }
+    }
+    lbm::collide(g, fx, fy, fz, omega, rho, ux, uy, uz);
     const float4 m = make_float4(ux, uy, uz, rho);
     su[i] = m;
-    const int64_t h = h0 + i;
     if (fields) {
       macro[h] = m;
       F[h] = fx;
@@ -378,21 +389,21 @@ hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, co
 
 hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float* gin, float* gout, float* F, float4* macro, float4* partial,
-                            bool fields, hipStream_t s) {
+                            bool fields, unsigned char* mask, hipStream_t s) {
   const dim3 grid((unsigned)tile_grid(L));
   const int fl = fields ? 1 : 0;
   if (L.kernel == 4 && L.le)
     hipLaunchKernelGGL((k_tile_step<4, true>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
-                       macro, partial, fl);
+                       macro, partial, fl, mask);
   else if (L.kernel == 4)
     hipLaunchKernelGGL((k_tile_step<4, false>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
-                       macro, partial, fl);
+                       macro, partial, fl, mask);
   else if (L.le)
     hipLaunchKernelGGL((k_tile_step<2, true>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
-                       macro, partial, fl);
+                       macro, partial, fl, mask);
   else
     hipLaunchKernelGGL((k_tile_step<2, false>), grid, dim3(256), 0, s, c, m, L, b, gin, gout, F,
-                       macro, partial, fl);
+                       macro, partial, fl, mask);
   return hipGetLastError();
 }
 

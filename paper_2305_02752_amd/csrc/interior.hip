@@ -1,0 +1,196 @@
+// Lattice sites inside the cells, for the interior viscosity (Sec. 1: the
+// cytosol is five times more viscous than plasma; Sec. 3.4: stiffened cells
+// scale the internal viscosity ratio).  A site is inside a cell by ray
+// parity along z: the vertical line through the site's (x, y) crosses the
+// closed membrane at heights z_1 < z_2 < ..., and the site is inside when
+// it lies strictly between z_(2k-1) and z_(2k).
+//
+// One work-group per cell.  The cell's (x, y) node columns within its
+// bounding box are a small grid (at most kMaxCols); every triangle adds its
+// crossing height to each column its projection covers (edge points are
+// kept by exactly one of the two triangles sharing the edge: after orienting
+// the triangle counter-clockwise in projection, edge P -> Q keeps them when
+// Q.y > P.y, or Q.y == P.y and Q.x < P.x); each column then sorts its
+// crossings and marks the nodes between pairs.  The marks are bytes in the
+// site-ordered mask, one bit per viscosity class (cells of different
+// stiffness may carry different interior viscosities, Sec. 3.4), which the
+// lattice pass reads (and clears) to pick the relaxation time.
+#include "common.h"
+#include "stencil.h"
+
+namespace hc {
+namespace {
+
+constexpr int kMarkThreads = 256;
+constexpr int kMaxCols = 1024;   // (x, y) columns of one cell's bounding box
+constexpr int kMaxCross = 8;     // crossings per column
+constexpr float kMaxSpan = 1024.f;   // bounding-box side beyond which a cell is refused
+constexpr float kMaxOff = 16777216.f;   // offsets from the cell origin beyond which it is refused
+
+// The edge tests and crossing heights are evaluated without contraction to
+// fused multiply-adds, so every decision is the one plain float32 arithmetic
+// (each product and sum rounded) takes.
+#pragma clang fp contract(off)
+
+__device__ inline bool edge_in(float px, float py, float qx, float qy, float x, float y) {
+  const float w = (qx - px) * (y - py) - (qy - py) * (x - px);
+  const bool keep = qy > py || (qy == py && qx < px);
+  return w > 0.f || (w == 0.f && keep);
+}
+
+__global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M, Lattice L,
+                                                                unsigned char* __restrict__ mask,
+                                                                const unsigned char* __restrict__ cls,
+                                                                int multi, int* __restrict__ flags) {
+  extern __shared__ float sp[];   // [nv][3] offsets
+  __shared__ int cnt[kMaxCols];
+  __shared__ float zc[kMaxCols][kMaxCross];
+  __shared__ float bb[kMarkThreads / kWave][6];
+  __shared__ int box[4];          // lo_x, lo_y, ncx, ncy (cell-local node coordinates)
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t b3 = (int64_t)c * M.nv * 3;
+  float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+  for (int v = tid; v < M.nv; v += kMarkThreads) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float p = C.off[b3 + 3 * v + d];
+      sp[3 * v + d] = p;
+      lo[d] = fminf(lo[d], p);
+      hi[d] = fmaxf(hi[d], p);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+      lo[d] = fminf(lo[d], __shfl_xor(lo[d], m));
+      hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], m));
+    }
+  if ((tid & (kWave - 1)) == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      bb[tid / kWave][d] = lo[d];
+      bb[tid / kWave][3 + d] = hi[d];
+    }
+  __syncthreads();
+  if (tid == 0) {
+    float l[3] = {bb[0][0], bb[0][1], bb[0][2]}, h[3] = {bb[0][3], bb[0][4], bb[0][5]};
+    for (int w = 1; w < kMarkThreads / kWave; ++w)
+      for (int d = 0; d < 3; ++d) {
+        l[d] = fminf(l[d], bb[w][d]);
+        h[d] = fmaxf(h[d], bb[w][3 + d]);
+      }
+    const float sx = h[0] - l[0], sy = h[1] - l[1], sz = h[2] - l[2];
+    bool near = true;   // offsets small enough for exact integer conversion
+    for (int d = 0; d < 3; ++d) near = near && fabsf(l[d]) < kMaxOff && fabsf(h[d]) < kMaxOff;
+    if (near && sx < kMaxSpan && sy < kMaxSpan && sz < kMaxSpan) {
+      box[0] = (int)ceilf(l[0]);
+      box[1] = (int)ceilf(l[1]);
+      box[2] = (int)floorf(h[0]) - box[0] + 1;
+      box[3] = (int)floorf(h[1]) - box[1] + 1;
+    } else {   // non-finite positions (reported by the vertex move) or a cell far too large
+      box[2] = box[3] = 0;
+      if (sx >= kMaxSpan || sy >= kMaxSpan || sz >= kMaxSpan || !near) atomicOr(&flags[1], 16);
+    }
+  }
+  __syncthreads();
+  const int lx = box[0], ly = box[1], ncx = box[2], ncy = box[3];
+  if (ncx <= 0 || ncy <= 0) return;
+  if (ncx * ncy > kMaxCols) {   // a cell wider than the column grid
+    if (tid == 0) atomicOr(&flags[1], 16);
+    return;
+  }
+  for (int i = tid; i < ncx * ncy; i += kMarkThreads) cnt[i] = 0;
+  __syncthreads();
+
+  for (int t = tid; t < M.nt; t += kMarkThreads) {
+    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+    float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
+    float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
+    float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
+    const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+    if (area2 == 0.f) continue;
+    if (area2 < 0.f) {   // orient counter-clockwise in projection
+      float tx = bx, ty = by, tz = bz;
+      bx = cx, by = cy, bz = cz;
+      cx = tx, cy = ty, cz = tz;
+    }
+    const float A = fabsf(area2);
+    const int x0 = max((int)ceilf(fminf(ax, fminf(bx, cx))), lx);
+    const int x1 = min((int)floorf(fmaxf(ax, fmaxf(bx, cx))), lx + ncx - 1);
+    const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly);
+    const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + ncy - 1);
+    for (int iy = y0; iy <= y1; ++iy)
+      for (int ix = x0; ix <= x1; ++ix) {
+        const float x = (float)ix, y = (float)iy;
+        if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
+              edge_in(cx, cy, ax, ay, x, y)))
+          continue;
+        const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
+        const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
+        const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
+        const float z = (wa * az + wb * bz + wc * cz) / A;
+        const int col = (iy - ly) * ncx + (ix - lx);
+        const int slot = atomicAdd(&cnt[col], 1);
+        if (slot < kMaxCross) zc[col][slot] = z;
+        else atomicOr(&flags[1], 32);
+      }
+  }
+  __syncthreads();
+
+  const int ox = C.origin[3 * c], oy = C.origin[3 * c + 1], oz = C.origin[3 * c + 2];
+  const unsigned bit = 1u << (cls ? cls[c] : 0);
+  for (int col = tid; col < ncx * ncy; col += kMarkThreads) {
+    const int n = min(cnt[col], kMaxCross);
+    if (n < 2) continue;
+    float z[kMaxCross];
+    for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
+    for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
+      for (int j = i; j > 0; --j)
+        if (z[j] < z[j - 1]) {
+          const float s = z[j];
+          z[j] = z[j - 1];
+          z[j - 1] = s;
+        }
+    int xs = ox + lx + col % ncx, ys = oy + ly + col / ncx;
+    if (L.bc[0] == 1) {
+      if (xs < 0 || xs >= L.nx) continue;
+    } else {
+      xs = wrap(xs, L.nx);
+    }
+    if (L.bc[1] == 1) {
+      if (ys < 0 || ys >= L.ny) continue;
+    } else {
+      ys = wrap(ys, L.ny);
+    }
+    for (int k = 0; k + 1 < n; k += 2) {
+      // the heights lie within the cell's bounded z extent
+      const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
+      for (int iz = z0; iz <= z1; ++iz) {
+        int zs = oz + iz;
+        if (L.bc[2] == 1) {
+          if (zs < 0 || zs >= L.nz) continue;
+        } else {
+          zs = wrap(zs, L.nz);
+        }
+        const int64_t h = site_of(L, xs, ys, zs);
+        if (multi)   // the word holding the byte; the mask is 4-byte aligned
+          atomicOr(reinterpret_cast<unsigned*>(mask + (h & ~(int64_t)3)), bit << (8 * (h & 3)));
+        else
+          mask[h] = (unsigned char)bit;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mark_interior(const Cells& c, const Mesh& m, const Lattice& L, unsigned char* mask,
+                                const unsigned char* cls, bool multi, int* flags, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  const size_t lds = (size_t)m.nv * 3 * sizeof(float);
+  hipLaunchKernelGGL(k_mark_interior, dim3(c.n), dim3(kMarkThreads), lds, s, c, m, L, mask, cls, multi ? 1 : 0,
+                     flags);
+  return hipGetLastError();
+}
+
+}  // namespace hc

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhemo.so")
 
 HC_PERIODIC, HC_WALL = 0, 1
 HC_PHI2, HC_PHI4 = 2, 4
-KERNELS = ("cell", "lattice", "advect")
+KERNELS = ("cell", "lattice", "advect", "interior")
 STATUS = {0: "HC_OK", 1: "HC_ERR_ARG", 2: "HC_ERR_STATE", 3: "HC_ERR_DEVICE", 4: "HC_ERR_OOM",
           5: "HC_ERR_NONFINITE", 6: "HC_ERR_UNSUPPORTED"}
 
@@ -59,6 +59,9 @@ def _declare(lib):
         "hc_read_macro": [_P, _P, _P, i64],
         "hc_set_field_output": [_P, i32],
         "hc_set_integration": [_P, i32, i32],
+        "hc_set_interior_viscosity": [_P, C.c_float],
+        "hc_read_interior": [_P, _P, i64],
+        "hc_set_cell_viscosity": [_P, _P, i64],
         "hc_read_force_field": [_P, _P, i64],
         "hc_read_vertices": [_P, _P, _P, _P, i64],
         "hc_write_vertices": [_P, _P, _P, i64],
@@ -220,6 +223,24 @@ class Simulation:
         Euler or second-order Adams-Bashforth ("ab2") vertex moves."""
         code = {"euler": 0, "ab2": 1}[scheme]
         self._check(self.lib.hc_set_integration(self.ctx, int(force_every), code))
+
+    def set_interior_viscosity(self, ratio: float):
+        """Sites inside the cells relax with `ratio` times the plasma
+        viscosity (1: off)."""
+        self._check(self.lib.hc_set_interior_viscosity(self.ctx, float(ratio)))
+
+    def set_cell_viscosity(self, ratio):
+        """One interior viscosity ratio per cell (at most 8 distinct)."""
+        r = np.ascontiguousarray(ratio, dtype=np.float32).reshape(-1)
+        self._check(self.lib.hc_set_cell_viscosity(self.ctx, _ptr(r), r.size))
+
+    def read_interior(self):
+        """Inside marks of the current positions, uint8 [nz, ny, nx]: bit k
+        set inside a cell of viscosity class k (distinct ratios in
+        increasing order), 0 outside every cell."""
+        m = np.empty((self.nz, self.ny, self.nx), dtype=np.uint8)
+        self._check(self.lib.hc_read_interior(self.ctx, _ptr(m), m.size))
+        return m
 
     def set_field_output(self, enable: bool):
         """Whether each step writes its force and (u, rho) fields out (for

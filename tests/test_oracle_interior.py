@@ -85,3 +85,46 @@ def test_local_float32_mode_matches_positions():
     m32 = interior.inside_sites(off32, tri, dims, (0, 0, 0), origin=origin)
     assert m64.sum() > 1500
     assert np.array_equal(m64, m32)
+
+
+def test_ratio_field_per_cell():
+    """One ratio per cell: uniform ratios reproduce the single-ratio form;
+    disjoint cells keep their own ratio; overlaps take the largest, in any
+    cell order."""
+    rest, tri = rbc_mesh()
+    dims = (40, 24, 22)
+    A = rest + np.array([10.3, 11.6, 10.9])
+    B = rest + np.array([29.7, 12.2, 11.3])          # disjoint from A
+    Cc = rest + np.array([14.1, 12.4, 11.1])         # overlaps A
+    X = np.stack([A, B])
+    r = interior.ratio_field(X, tri, dims, (0, 0, 0), [5.0, 5.0])
+    assert np.array_equal(interior.tau_field(r, 0.9),
+                          interior.site_tau(interior.inside_sites(X, tri, dims, (0, 0, 0)), 0.9, 5.0))
+    r = interior.ratio_field(X, tri, dims, (0, 0, 0), [5.0, 2.0])
+    mA = interior.inside_sites(A[None], tri, dims, (0, 0, 0))
+    mB = interior.inside_sites(B[None], tri, dims, (0, 0, 0))
+    assert mA.sum() > 300 and mB.sum() > 300 and not (mA & mB).any()
+    assert (r[mA] == 5.0).all() and (r[mB] == 2.0).all() and (r[~(mA | mB)] == 0).all()
+    mC = interior.inside_sites(Cc[None], tri, dims, (0, 0, 0))
+    both = mA & mC
+    assert both.sum() > 50
+    r1 = interior.ratio_field(np.stack([A, Cc]), tri, dims, (0, 0, 0), [0.5, 3.0])
+    r2 = interior.ratio_field(np.stack([Cc, A]), tri, dims, (0, 0, 0), [3.0, 0.5])
+    assert np.array_equal(r1, r2)
+    assert (r1[both] == 3.0).all() and (r1[mA & ~mC] == 0.5).all()
+
+
+def test_per_site_relaxation_conserves_mass_and_momentum():
+    """BGK with a per-site relaxation time keeps the collision invariants:
+    mass unchanged, momentum changed by exactly the Guo force (Sec. 2.3)."""
+    rng = np.random.default_rng(9)
+    shape = (6, 5, 4)
+    f = lattice.init_equilibrium(shape) + 1e-3 * rng.standard_normal((19,) + shape)
+    F = 1e-5 * rng.standard_normal((3,) + shape)
+    rho, u = lattice.moments(f, F)
+    tau = 0.5 + rng.uniform(0.05, 4.0, shape)
+    post = lattice.collide(f, rho, u, F, tau)
+    e = np.array(lattice.E, dtype=np.float64)
+    assert np.allclose(post.sum(axis=0), f.sum(axis=0), rtol=0, atol=1e-15)
+    mom = lambda g: np.einsum("qd,q...->d...", e, g)
+    assert np.allclose(mom(post) - mom(f), F, rtol=0, atol=1e-15)
