@@ -12,14 +12,17 @@ The oracle follows the paper's model statement:
   * immersed-boundary coupling through external force terms with
     interpolation in both directions (Sec. 2.3);
   * membrane force F_total = F_link + F_bend + F_area + F_volume (Sec. 2.3);
-  * explicit Euler integration of the vertices (Sec. 2.6).
+  * explicit Euler integration of the vertices (Sec. 2.6);
+  * the force-bias packing of surrogate ellipsoids (Sec. 2.4).
 Where the paper leaves a choice open the oracle uses the readings listed in
 each module's docstring.
 
 Parity pinned for: lattice (Couette, Poiseuille, conservation, equilibrium
 moments), IBM (kernel moments, transpose identity), membrane (rest, rigid
 motions, energy gradient, convex-hull volume), binning (brute force), coupled
-step (uniform translation).  Parity unpinned: agreement of the membrane force
+step (uniform translation), interior marking (sphere inside/outside, ray
+direction independence), packing (lens volume, containment, balanced
+pushes).  Parity unpinned: agreement of the membrane force
 forms with the paper's own implementation, whose formulas are in a reference
 that is not reproduced in the paper.
 """
