@@ -179,6 +179,34 @@ def bench_lees_edwards(torch, w, warmup: int, steps: int, u_le: float = 0.02):
             "kernel_ms": {k: ms / max(c, 1) for k, (ms, c) in prof.items()}}
 
 
+def bench_packing(torch, n: int = 1_000_000, iters: int = 20):
+    """Force-bias packing of a million random surrogate ellipsoids (RBC
+    enclosing ellipsoids filling 35% of a periodic cube): time per
+    iteration and the overlap before and after."""
+    from paper_2305_02752_amd import Packer
+    from workloads.configs import RBC_SURROGATE, ellipsoid_suspension
+
+    c, R, s, side = ellipsoid_suspension(n=n)
+    pk = Packer((side,) * 3, (True,) * 3, max_semi=max(RBC_SURROGATE), eta=0.03, max_move=1.0, quad=8)
+    dev = torch.device("cuda:0")
+    tc = torch.tensor(c, device=dev)
+    tr = torch.tensor(R.reshape(-1, 9), device=dev)
+    ts = torch.tensor(s, device=dev)
+    before = pk.run_device(tc, tr, ts, 0)
+    pk.run_device(tc, tr, ts, 2, measure=False)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk.run_device(tc, tr, ts, iters, measure=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    after = pk.run_device(tc, tr, ts, 0)
+    return {"ellipsoids": n, "side": side, "volume_fraction": 0.35, "quad": 8, "iterations": iters,
+            "ms_per_iteration": dt / iters * 1e3, "ellipsoid_updates_per_s": n * iters / dt,
+            "overlap_volume_before": before[0], "overlapping_pairs_before": int(before[1]),
+            "overlap_volume_after": after[0], "overlapping_pairs_after": int(after[1]),
+            "iterations_before_after": 2 + iters}
+
+
 def bench_small(torch):
     """The single-cell shear box (32^3, 500 steps) and the dense channel
     (128x64x64, 220 cells, 1000 steps): whole runs, timed per step."""
@@ -392,8 +420,13 @@ def main():
         adj = bench_adjoint(torch, boxes=args.adjoint_boxes)
         log(f"adjoint: {adj['grads_per_s']:.2f} gradients/s, t_grad/t_fwd {adj['t_grad_over_t_forward']:.2f}")
 
-    small = lees = None
+    small = lees = packing = None
     if not args.no_extra:
+        log("force-bias packing of a million ellipsoids ...")
+        packing = bench_packing(torch)
+        torch.cuda.empty_cache()
+        log(f"  {packing['ms_per_iteration']:.3f} ms/iteration, overlapping pairs "
+            f"{packing['overlapping_pairs_before']} -> {packing['overlapping_pairs_after']}")
         log("Lees-Edwards shear of the same suspension ...")
         lees = bench_lees_edwards(torch, w, args.warmup, args.steps)
         torch.cuda.empty_cache()
@@ -435,6 +468,7 @@ def main():
         "interior_viscosity": interior,
         "small_workloads": small,
         "lees_edwards_shear": lees,
+        "force_bias_packing": packing,
         "batched_calibration": batched,
         "adjoint": adj,
     }

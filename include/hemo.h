@@ -257,6 +257,50 @@ hc_status hc_profile_read(hc_ctx* ctx, double* total_ms, int64_t* launches);
  * not overlap and must be 16-byte aligned. */
 hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Force-bias packing of surrogate ellipsoids (Sec. 2.4: random positions and
+ * orientations, then iterations that push every overlapping pair apart
+ * along the line through the centres in proportion to their overlapping
+ * volume).  Stateless; errors are reported by hc_last_error(NULL).
+ *
+ * Ellipsoid i: centre r_i, rotation R_i (row-major 3x3, columns = body axes
+ * in the world frame), semi-axes s_i along those axes.  Overlap volume:
+ * the unit ball is sampled at the centres of the quad^3 grid cells over
+ * [-1, 1]^3 that lie inside it (Q points) and mapped onto each ellipsoid;
+ * with n_i(j) of i's points inside j, V_ij = (V_i n_i(j) + V_j n_j(i)) / 2Q.
+ * One iteration moves every ellipsoid at once by
+ *   eta * sum_j V_ij (r_i - r_j) / |r_i - r_j|
+ * (minimum image on periodic axes; a pair with coincident centres exerts
+ * nothing), shortened to max_move when longer; periodic axes then wrap the
+ * centre into [0, box), wall axes clamp it so that the ellipsoid's extent
+ * along the axis stays within [lo, hi].  Orientations stay fixed.  The
+ * pushes are summed in fixed point, so a run is bitwise reproducible.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  float box[3];          /* domain sides */
+  int32_t periodic[3];   /* per axis: 1 periodic (side >= 4 max_semi), 0 walls */
+  float lo[3], hi[3];    /* wall axes: allowed extent, hi - lo >= 2 max_semi */
+  float max_semi;        /* bound on every semi-axis; sets the neighbour bins */
+  float eta;             /* displacement per unit overlapping volume (>= 0) */
+  float max_move;        /* longest move per iteration (> 0) */
+  int32_t quad;          /* quadrature grid per axis: 4, 8 or 16 */
+} hc_pack_desc;
+
+/* Device workspace bytes for n ellipsoids (256-byte aligned buffer). */
+hc_status hc_pack_query_workspace(const hc_pack_desc* desc, int32_t n, size_t* bytes);
+
+/* n_iter iterations on device arrays: centres [n][3] (in/out), rot [n][9],
+ * semi [n][3], all float32, enqueued on hip_stream.  overlap (host, may be
+ * NULL): double [4], {total overlapping volume sum_{i<j} V_ij, overlapping pairs}
+ * before the first move, then the same at the returned centres; when given,
+ * the call synchronises.  The call always ends by reading device flags
+ * (synchronous): HC_ERR_NONFINITE for a non-finite centre, HC_ERR_ARG for a
+ * semi-axis outside (0, max_semi], HC_ERR_UNSUPPORTED when a neighbour bin
+ * overflows its capacity. */
+hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
+                      int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* hip_stream,
+                      double* overlap);
+
 /* Steps taken since hc_set_cells / restore. */
 hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhemo.so")
 SOURCES = ["api.hip", "lbm.hip", "ibm.hip", "membrane.hip", "binning.hip", "batch_kernel.hip",
-           "batch_api.hip", "mesh_host.hip", "interior.hip",
+           "batch_api.hip", "mesh_host.hip", "interior.hip", "packing.hip",
            "adjoint.hip", "cell.hip"]
 
 FLAGS = [

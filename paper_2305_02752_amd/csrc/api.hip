@@ -494,6 +494,14 @@ hc_status hc_profile_read(hc_ctx* c, double* total_ms, int64_t* launches) {
   return HC_OK;
 }
 
+}  // extern "C"
+
+namespace hc {
+void set_global_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace hc
+
+extern "C" {
+
 const char* hc_last_error(const hc_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }

@@ -23,4 +23,7 @@ struct HostMesh {
 // Returns an empty string on success, else the reason.
 std::string build_mesh(const hc_mesh_desc* d, HostMesh& m);
 
+// Message returned by hc_last_error(NULL): errors of calls without a context.
+void set_global_error(const std::string& msg);
+
 }  // namespace hc

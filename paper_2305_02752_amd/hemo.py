@@ -81,6 +81,8 @@ def _declare(lib):
         "hc_adj_bind_workspace": [_P, _P, sz, i32, i32],
         "hc_adj_forward": [_P, _P, _P],
         "hc_adj_backward": [_P, _P],
+        "hc_pack_query_workspace": [_P, i32, _P],
+        "hc_pack_run": [_P, _P, _P, _P, i32, i32, _P, sz, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -351,6 +353,68 @@ def device_copy(dst, src, nbytes: int, stream_handle: int):
     rc = lib.hc_device_copy(C.c_void_p(dst), C.c_void_p(src), int(nbytes), C.c_void_p(stream_handle))
     if rc:
         raise HemoError(rc, lib.hc_last_error(None).decode())
+
+
+class PackDesc(C.Structure):
+    _fields_ = [("box", C.c_float * 3), ("periodic", C.c_int32 * 3), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3), ("max_semi", C.c_float), ("eta", C.c_float),
+                ("max_move", C.c_float), ("quad", C.c_int32)]
+
+
+class Packer:
+    """Force-bias packing of surrogate ellipsoids on the device.
+
+    box, periodic: domain sides and per-axis periodicity; lo, hi: allowed
+    extent on wall axes; max_semi: bound on every semi-axis; eta: move per
+    unit overlapping volume; max_move: longest move per iteration; quad:
+    quadrature grid per axis (4, 8 or 16).
+    """
+
+    def __init__(self, box, periodic, lo=(0.0, 0.0, 0.0), hi=(0.0, 0.0, 0.0), max_semi=9.0,
+                 eta=0.03, max_move=1.0, quad=8, device: str = "cuda:0"):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.desc = PackDesc((C.c_float * 3)(*box), (C.c_int32 * 3)(*[1 if p else 0 for p in periodic]),
+                             (C.c_float * 3)(*lo), (C.c_float * 3)(*hi), float(max_semi), float(eta),
+                             float(max_move), int(quad))
+        self._ws = None
+
+    def _check(self, rc):
+        if rc:
+            raise HemoError(rc, self.lib.hc_last_error(None).decode())
+
+    def workspace(self, n: int):
+        nbytes = C.c_size_t()
+        self._check(self.lib.hc_pack_query_workspace(C.byref(self.desc), int(n), C.byref(nbytes)))
+        if self._ws is None or self._ws.numel() < nbytes.value + 256:
+            self._ws = self.torch.empty(nbytes.value + 256, dtype=self.torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        return (base + 255) & ~255, nbytes.value
+
+    def run_device(self, centres, rot, semi, n_iter: int, measure: bool = True):
+        """Iterate on device tensors (float32, contiguous): centres [n,3]
+        in place, rot [n,3,3], semi [n,3].  Returns the overlap record
+        (initial volume, pairs, final volume, pairs) or None."""
+        n = int(centres.shape[0])
+        ws, nbytes = self.workspace(n)
+        out = np.zeros(4, dtype=np.float64)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.hc_pack_run(C.byref(self.desc), C.c_void_p(centres.data_ptr()),
+                                         C.c_void_p(rot.data_ptr()), C.c_void_p(semi.data_ptr()), n,
+                                         int(n_iter), C.c_void_p(ws), nbytes, C.c_void_p(stream),
+                                         _ptr(out) if measure else None))
+        return tuple(out) if measure else None
+
+    def run(self, centres, rot, semi, n_iter: int):
+        """Host arrays in, (centres [n,3] float32, overlap record) out."""
+        t = self.torch
+        c = t.tensor(np.ascontiguousarray(centres, dtype=np.float32), device=self.device)
+        r = t.tensor(np.ascontiguousarray(rot, dtype=np.float32).reshape(-1, 9), device=self.device)
+        s = t.tensor(np.ascontiguousarray(semi, dtype=np.float32), device=self.device)
+        rec = self.run_device(c, r, s, n_iter)
+        return c.cpu().numpy(), rec
 
 
 def _declare_batch(lib):

@@ -147,6 +147,38 @@ def _surrogate_spheres():
     return np.array(pts), 2.7
 
 
+# Semi-axes of an oblate ellipsoid enclosing the rest mesh (radius 8, half
+# thickness 2.62 at the rim of the dimple): every vertex satisfies
+# (r / 8.5)^2 + (z / 3.8)^2 <= 1.
+RBC_SURROGATE = (8.5, 8.5, 3.8)
+
+
+def random_rotations(rng, n: int) -> np.ndarray:
+    """n uniform random rotations [n, 3, 3] from normalised Gaussian quaternions."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], 1)
+
+
+def ellipsoid_suspension(seed: int = 6, n: int = 1_000_000, fraction: float = 0.35,
+                         semi=RBC_SURROGATE):
+    """Initial surrogate ellipsoids for packing (Sec. 2.4): n random centres
+    and uniform orientations in a periodic cube sized so that the ellipsoids
+    fill `fraction` of it.  Returns (centres [n,3], rotations [n,3,3],
+    semi-axes [n,3], side), all float32 (the side exactly representable)."""
+    rng = np.random.default_rng(seed)
+    vol = 4.0 / 3.0 * math.pi * float(np.prod(semi))
+    side = float(np.float32(np.cbrt(n * vol / fraction)))
+    centres = (rng.random((n, 3)) * side).astype(np.float32)
+    rots = random_rotations(rng, n).astype(np.float32)
+    s = np.tile(np.asarray(semi, dtype=np.float32), (n, 1))
+    return centres, rots, s, side
+
+
 def force_bias_pack(rng, n: int, lat: Lattice, wall_clear: float = 2.0,
                     max_iter: int = 400, tol: float = 0.05, step: float = 0.5,
                     max_move: float = 1.5):
