@@ -69,12 +69,21 @@ def min_image(d: np.ndarray, dom: Domain, dtype=np.float64) -> np.ndarray:
 def count_inside(dd, Ri, si, Rj, sj, U):
     """n_i(j): how many of ellipsoid i's quadrature points lie in ellipsoid j.
     dd = r_i - r_j (minimum image); all arrays in one dtype, evaluated
-    operation by operation."""
-    p0, p1, p2 = si[0] * U[:, 0], si[1] * U[:, 1], si[2] * U[:, 2]
-    y = [dd[d] + (Ri[d, 0] * p0 + Ri[d, 1] * p1 + Ri[d, 2] * p2) for d in range(3)]
-    t = [(Rj[0, e] * y[0] + Rj[1, e] * y[1] + Rj[2, e] * y[2]) / sj[e] for e in range(3)]
-    q = t[0] * t[0] + t[1] * t[1] + t[2] * t[2]
-    return int(np.count_nonzero(q <= q.dtype.type(1)))
+    operation by operation.
+
+    A point r_i + R_i (s_i u) lies in j when |t| <= 1 with
+    t = diag(1/s_j) R_j^T (dd + R_i diag(s_i) u) = A u + b, where
+    A = diag(1/s_j) (R_j^T R_i) diag(s_i) and b = diag(1/s_j) R_j^T dd are
+    formed once per pair (left-to-right sums, reciprocals 1/s_j)."""
+    one = dd.dtype.type(1)
+    inv = [one / sj[e] for e in range(3)]
+    M = [[(Rj[0, e] * Ri[0, c] + Rj[1, e] * Ri[1, c]) + Rj[2, e] * Ri[2, c] for c in range(3)]
+         for e in range(3)]
+    A = [[(M[e][c] * si[c]) * inv[e] for c in range(3)] for e in range(3)]
+    b = [((Rj[0, e] * dd[0] + Rj[1, e] * dd[1]) + Rj[2, e] * dd[2]) * inv[e] for e in range(3)]
+    t = [((A[e][0] * U[:, 0] + A[e][1] * U[:, 1]) + A[e][2] * U[:, 2]) + b[e] for e in range(3)]
+    q = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]
+    return int(np.count_nonzero(q <= one))
 
 
 def volume(s) -> float:
