@@ -336,13 +336,19 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint forms")
     ap.add_argument("--adjoint-boxes", type=int, default=8)
+    ap.add_argument("--packing-only", action="store_true",
+                    help="time only the force-bias packing of a million ellipsoids (one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the coupled step has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.packing_only:
+        print(json.dumps({"force_bias_packing": bench_packing(torch)}), flush=True)
+        return
 
     from paper_2305_02752_amd import Simulation
     from workloads import large_suspension

@@ -17,12 +17,13 @@
 //   2. k_pack_bin: one thread per ellipsoid appends it to the fixed-capacity
 //      list of its bin (bins are at least one pair reach wide, so
 //      overlapping pairs lie in neighbouring bins);
-//   3. k_pack_iter: one wavefront per ellipsoid walks the neighbouring bins;
-//      for every candidate the 64 lanes split the quadrature points of both
-//      one-sided counts, and the push is accumulated in 2^-32 fixed point, so
-//      the sum does not depend on the order of the bin lists.  The pushes of
-//      a pair are computed from the exact negatives of each other, so they
-//      cancel exactly.
+//   3. k_pack_iter: one wavefront per ellipsoid gathers the candidates of
+//      its neighbouring bins (one lane each) and keeps those whose bounding
+//      spheres meet; for each of these the 64 lanes split the quadrature
+//      points of both one-sided counts, and the push is accumulated in 2^-32
+//      fixed point, so the sum does not depend on the order of the bin
+//      lists.  The pushes of a pair are computed from the exact negatives of
+//      each other, so they cancel exactly.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -60,24 +61,81 @@ __device__ inline float min_image(const PackGeom& G, int a, float d) {
   return G.per[a] ? d - G.L[a] * rintf(d / G.L[a]) : d;
 }
 
-// Whether the quadrature point u of ellipsoid i (rotation Ri row-major,
-// semi-axes si) lies in ellipsoid j; dd = r_i - r_j (minimum image).
-__device__ inline bool point_inside(const float (&dd)[3], const float* Ri, const float* si,
-                                    const float* Rj, const float* sj, const float4 u) {
-  const float p0 = si[0] * u.x, p1 = si[1] * u.y, p2 = si[2] * u.z;
-  float y[3];
+// The frames of a pair, with dd = r_a - r_b (minimum image); R row-major
+// (R[3 d + e]: component d of body axis e).  A point r_a + R_a (s_a u) lies
+// inside b when |A u + bv| <= 1, with A = diag(1/s_b) (R_b^T R_a) diag(s_a)
+// and bv = diag(1/s_b) R_b^T dd (frame 1); frame 2 swaps a and b (and
+// negates dd).  M = R_b^T R_a serves both: R_a^T R_b is its transpose, with
+// the same products summed in the same order.
+__device__ inline void pair_frames(const float (&dd)[3], const float* Ra, const float* sa, const float* Rb,
+                                   const float* sb, float (&A1)[3][3], float (&b1)[3], float (&A2)[3][3],
+                                   float (&b2)[3]) {
+  float ia[3], ib[3], M[3][3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) y[d] = dd[d] + (Ri[3 * d] * p0 + Ri[3 * d + 1] * p1 + Ri[3 * d + 2] * p2);
-  float t[3];
+  for (int e = 0; e < 3; ++e) {
+    ia[e] = 1.f / sa[e];
+    ib[e] = 1.f / sb[e];
+  }
 #pragma unroll
-  for (int e = 0; e < 3; ++e) t[e] = (Rj[e] * y[0] + Rj[3 + e] * y[1] + Rj[6 + e] * y[2]) / sj[e];
-  const float q = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-  return q <= 1.f;
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M[e][c] = (Rb[e] * Ra[c] + Rb[3 + e] * Ra[3 + c]) + Rb[6 + e] * Ra[6 + c];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      A1[e][c] = (M[e][c] * sa[c]) * ib[e];
+      A2[c][e] = (M[e][c] * sb[e]) * ia[c];
+    }
+    b1[e] = ((Rb[e] * dd[0] + Rb[3 + e] * dd[1]) + Rb[6 + e] * dd[2]) * ib[e];
+    b2[e] = ((Ra[e] * -dd[0] + Ra[3 + e] * -dd[1]) + Ra[6 + e] * -dd[2]) * ia[e];
+  }
 }
 
-__device__ inline int wave_sum(int v) {
-  for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
-  return v;
+__device__ inline bool in_frame(const float (&A)[3][3], const float (&bv)[3], float4 u) {
+  float t[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) t[e] = ((A[e][0] * u.x + A[e][1] * u.y) + A[e][2] * u.z) + bv[e];
+  return (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2] <= 1.f;
+}
+
+// Whether the frame proves that no point of a lies in b: every quadrature
+// point has |u| <= 1, so |t_e - bv_e| <= |row e of A|; when |bv_e| exceeds
+// that bound plus 1 (with a margin far above the rounding of t), every
+// point has |t_e| > 1.  A shortcut only: it never changes a count.
+__device__ inline bool frame_separated(const float (&A)[3][3], const float (&bv)[3]) {
+  bool sep = false;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    // |bv| (1 - 1e-4) > |row e| (1 + 1e-4) + 1.001, compared in squares
+    const float r2 = A[e][0] * A[e][0] + A[e][1] * A[e][1] + A[e][2] * A[e][2];
+    const float g = fabsf(bv[e]) * 0.9999f - 1.001f;
+    sep = sep || (g > 0.f && g * g > r2 * 1.0003f);
+  }
+  return sep;
+}
+
+// n_a(b) from the frame of b seen from a: the 64 lanes split the points
+// (point k on lane k mod 64) and a ballot counts them.  R > 0: each lane
+// holds its R points in registers (up); R == 0: they are read from LDS (U).
+template <int R>
+__device__ inline int count_frame(const float (&A)[3][3], const float (&bv)[3],
+                                  const float4 (&up)[R > 0 ? R : 1], const float4* U, int Q, int lane) {
+  int n = 0;
+  if constexpr (R > 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = r * kWave + lane < Q && in_frame(A, bv, up[r]);
+      n += __popcll(__ballot(in));
+    }
+  } else {
+    for (int k0 = 0; k0 < Q; k0 += kWave) {
+      const int k = k0 + lane;
+      const bool in = k < Q && in_frame(A, bv, U[k]);
+      n += __popcll(__ballot(in));
+    }
+  }
+  return n;
 }
 
 __global__ __launch_bounds__(256) void k_pack_bin(PackGeom G, const float* __restrict__ r, int n,
@@ -115,9 +173,17 @@ __device__ inline int axis_bins(const PackGeom& G, int a, int b, int (&out)[3]) 
   return k;
 }
 
+__device__ inline float lane_f(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // One iteration for every ellipsoid: pushes from the positions rin, written
 // to rout when move is set; per ellipsoid, the fixed-point overlapping
 // volume with higher-indexed partners (vol) and their number (pairs).
+// A wavefront first gathers the candidates of all its neighbour bins at
+// once (one lane per candidate: index, separation, bounding-sphere test),
+// then takes the pairs that pass one after another, uniformly.
+template <int R>
 __global__ __launch_bounds__(kPackThreads) void k_pack_iter(
     PackGeom G, const float* __restrict__ rin, float* __restrict__ rout, const float* __restrict__ rot,
     const float* __restrict__ semi, int n, const int* __restrict__ cnt, const int* __restrict__ items,
@@ -138,6 +204,11 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_iter(
   __syncthreads();
   const int Q = nU;
   const int lane = threadIdx.x & (kWave - 1);
+  float4 up[R > 0 ? R : 1];
+  if constexpr (R > 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) up[r] = r * kWave + lane < Q ? U[r * kWave + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   const int i = blockIdx.x * kPackPerBlock + threadIdx.x / kWave;
   if (i >= n) return;
 
@@ -154,60 +225,88 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_iter(
     atomicOr(&flags[2], 1);
   const float Vi = 4.18879020478639f * si[0] * si[1] * si[2];   // 4 pi / 3 s0 s1 s2
 
+  // neighbour bins: lane l < nbn holds bin l, its candidate count and offset
   int Bz[3], By[3], Bx[3];
   const int nz = axis_bins(G, 2, bin_axis(G, 2, ri[2]), Bz);
   const int ny = axis_bins(G, 1, bin_axis(G, 1, ri[1]), By);
   const int nx = axis_bins(G, 0, bin_axis(G, 0, ri[0]), Bx);
+  const int nbn = nz * ny * nx;
+  int my_bin = 0, my_cnt = 0;
+  if (lane < nbn) {
+    const int a = lane / (ny * nx), b = (lane / nx) % ny, c = lane % nx;
+    my_bin = (Bz[a] * G.nb[1] + By[b]) * G.nb[0] + Bx[c];
+    my_cnt = min(cnt[my_bin], G.cap);
+  }
+  int incl = my_cnt;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  const int total = __shfl(incl, kWave - 1);
+  const int excl = incl - my_cnt;
+
   long long push[3] = {0, 0, 0};
   long long vsum = 0;
   int npair = 0;
-  for (int a = 0; a < nz; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nx; ++c) {
-        const int bin = (Bz[a] * G.nb[1] + By[b]) * G.nb[0] + Bx[c];
-        const int m = min(cnt[bin], G.cap);
-        for (int t = 0; t < m; ++t) {
-          const int j = items[(int64_t)bin * G.cap + t];
-          if (j == i) continue;
-          float dd[3], sj[3], Rj[9];
+  for (int base = 0; base < total; base += kWave) {
+    const int k = base + lane;
+    // owning bin of candidate k: the last bin whose offset is <= k
+    int owner = 0;
+    for (int l = 1; l < nbn; ++l) owner = __shfl(excl, l) <= k ? l : owner;
+    const int bin = __shfl(my_bin, owner);
+    const int slot = k - __shfl(excl, owner);
+    bool pass = false;
+    int j = -1;
+    float dd[3] = {0.f, 0.f, 0.f}, sj[3] = {1.f, 1.f, 1.f};
+    if (k < total) {
+      j = items[(int64_t)bin * G.cap + slot];
+      if (j != i) {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            dd[d] = min_image(G, d, ri[d] - rin[3 * j + d]);
-            sj[d] = semi[3 * j + d];
-          }
-          const float d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
-          const float reach = smax_i + fmaxf(sj[0], fmaxf(sj[1], sj[2]));
-          if (!(d2 < reach * reach)) continue;
+        for (int d = 0; d < 3; ++d) {
+          dd[d] = min_image(G, d, ri[d] - rin[3 * j + d]);
+          sj[d] = semi[3 * j + d];
+        }
+        const float d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+        const float reach = smax_i + fmaxf(sj[0], fmaxf(sj[1], sj[2]));
+        pass = d2 < reach * reach;
+      }
+    }
+    unsigned long long todo = __ballot(pass);
+    while (todo) {
+      const int src = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int jj = __builtin_amdgcn_readlane(j, src);
+      const float pd[3] = {lane_f(dd[0], src), lane_f(dd[1], src), lane_f(dd[2], src)};
+      const float ps[3] = {lane_f(sj[0], src), lane_f(sj[1], src), lane_f(sj[2], src)};
+      float Rj[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) Rj[e] = rot[9 * j + e];
-          const float nd[3] = {-dd[0], -dd[1], -dd[2]};
-          int cij = 0, cji = 0;
-          for (int k = lane; k < Q; k += kWave) {
-            const float4 u = U[k];
-            cij += point_inside(dd, Ri, si, Rj, sj, u) ? 1 : 0;
-            cji += point_inside(nd, Rj, sj, Ri, si, u) ? 1 : 0;
-          }
-          cij = wave_sum(cij);
-          cji = wave_sum(cji);
-          if (cij == 0 && cji == 0) continue;
-          const float Vj = 4.18879020478639f * sj[0] * sj[1] * sj[2];
-          const float V = (Vi * (float)cij + Vj * (float)cji) / (2.f * (float)Q);
-          if (j > i) {
-            vsum += llrint((double)V * kVolScale);
-            npair += 1;
-          }
-          const float len = sqrtf(d2);
-          if (len > 0.f) {
-            const float f = G.eta * V / len;
+      for (int e = 0; e < 9; ++e) Rj[e] = rot[9 * (int64_t)jj + e];
+      float A1[3][3], b1[3], A2[3][3], b2[3];
+      // frame 1: i's points in j; frame 2: j's points in i
+      pair_frames(pd, Ri, si, Rj, ps, A1, b1, A2, b2);
+      // disjoint along a principal axis of either: both counts are zero
+      if (frame_separated(A1, b1) || frame_separated(A2, b2)) continue;
+      const int cij = count_frame<R>(A1, b1, up, U, Q, lane);
+      const int cji = count_frame<R>(A2, b2, up, U, Q, lane);
+      if (cij == 0 && cji == 0) continue;
+      const float Vj = 4.18879020478639f * ps[0] * ps[1] * ps[2];
+      const float V = (Vi * (float)cij + Vj * (float)cji) / (2.f * (float)Q);
+      if (jj > i) {
+        vsum += llrint((double)V * kVolScale);
+        npair += 1;
+      }
+      const float len = sqrtf(pd[0] * pd[0] + pd[1] * pd[1] + pd[2] * pd[2]);
+      if (len > 0.f) {
+        const float f = G.eta * V / len;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              // pushes beyond 1e6 lattice units are clamped (the move is capped anyway)
-              const double c = fmin(fmax((double)(f * dd[d]), -1e6), 1e6);
-              push[d] += llrint(c * kPushScale);
-            }
-          }
+        for (int d = 0; d < 3; ++d) {
+          // pushes beyond 1e6 lattice units are clamped (the move is capped anyway)
+          const double c = fmin(fmax((double)(f * pd[d]), -1e6), 1e6);
+          push[d] += llrint(c * kPushScale);
         }
       }
+    }
+  }
   if (lane != 0) return;
   vol[i] = vsum;
   pairs[i] = npair;
@@ -392,8 +491,16 @@ hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot
     PK_TRY(launch_fill_i32(cnt, 0, P.nbins, s), "clear bins");
     hipLaunchKernelGGL(k_pack_bin, gb, dim3(256), 0, s, P.G, cur, n, cnt, items, flags);
     PK_TRY(hipGetLastError(), "bin");
-    hipLaunchKernelGGL(k_pack_iter, gi, dim3(kPackThreads), lds, s, P.G, cur, nxt, rot, semi, n, cnt,
-                       items, vol, pairs, move ? 1 : 0, flags);
+    // the 32 (m = 4) and 280 (m = 8) points stay in registers, 1 and 5 per lane
+    if (P.G.m == 4)
+      hipLaunchKernelGGL(k_pack_iter<1>, gi, dim3(kPackThreads), lds, s, P.G, cur, nxt, rot, semi, n, cnt,
+                         items, vol, pairs, move ? 1 : 0, flags);
+    else if (P.G.m == 8)
+      hipLaunchKernelGGL(k_pack_iter<5>, gi, dim3(kPackThreads), lds, s, P.G, cur, nxt, rot, semi, n, cnt,
+                         items, vol, pairs, move ? 1 : 0, flags);
+    else
+      hipLaunchKernelGGL(k_pack_iter<0>, gi, dim3(kPackThreads), lds, s, P.G, cur, nxt, rot, semi, n, cnt,
+                         items, vol, pairs, move ? 1 : 0, flags);
     PK_TRY(hipGetLastError(), "iterate");
     if (overlap && (it == 0 || !move)) {
       hipLaunchKernelGGL(k_pack_total, dim3(1), dim3(1024), 0, s, vol, pairs, n, tot);
