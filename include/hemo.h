@@ -301,6 +301,16 @@ hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot
                       int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* hip_stream,
                       double* overlap);
 
+/* Cells from packed ellipsoids without a host round trip (Sec. 2.4: each
+ * ellipsoid encloses one cell): the context's rest mesh, rotated by rot
+ * (device [n][9], as for hc_pack_run) and translated to centres (device
+ * [n][3]), becomes cell c with origin floor(centre) and offsets
+ * R rest + (centre - origin), computed in float32.  k (host [n][4]) and
+ * traction (host [n][3] or NULL) as for hc_set_cells, whose resets this
+ * call shares. */
+hc_status hc_place_cells(hc_ctx* ctx, int32_t n, const float* centres, const float* rot, const float* k,
+                         const float* traction);
+
 /* Steps taken since hc_set_cells / restore. */
 hc_status hc_get_step(const hc_ctx* ctx, int64_t* step);
 

@@ -95,7 +95,8 @@ struct hc_ctx {
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
   size_t o_owner, o_ntouch, o_scan, o_slot, o_tcnt, o_tptr, o_touch, o_csr, o_flags;
-  size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist, o_mask, o_cclass;
+  size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist, o_mask, o_cclass, o_rest;
+  std::vector<float> rest;   // the rest mesh [nv][3], copied at create
 };
 
 namespace {
@@ -161,6 +162,7 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_clist = lay.add(std::max<int64_t>(1, C * kMaxCellTiles) * 4);
   c->o_mask = lay.add(N);
   c->o_cclass = lay.add(std::max<int64_t>(1, C));
+  c->o_rest = lay.add(nv * 3 * 4);
 }
 
 hc_status need_ws(hc_ctx* c) {
@@ -414,6 +416,7 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     delete c;
     return fail(nullptr, HC_ERR_ARG, e);
   }
+  c->rest.assign(mesh->rest_pos, mesh->rest_pos + 3 * (size_t)mesh->n_vert);
   Lattice& L = c->L;
   L.nx = lat->nx;
   L.ny = lat->ny;
@@ -584,6 +587,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   HC_TRY(copy_h2d(c, (void*)M.hinge_v, m.hinge_v.data(), m.hinge_v.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.theta0, m.theta0.data(), m.theta0.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
+  HC_TRY(copy_h2d(c, at<float>(c, c->o_rest), c->rest.data(), c->rest.size() * 4));
   HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
   HC_TRY(check(c, launch_fill_i32(B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->mask), 0, c->L.np / 4, c->stream),
@@ -592,14 +596,9 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   return sync(c, "bind");
 }
 
-hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float* offsets,
-                       const float* k, const float* traction) {
-  HC_TRY(need_ws(c));
-  if (n < 0 || n > c->max_cells) return fail(c, HC_ERR_ARG, "cell count outside [0, max_cells]");
-  if (n > 0 && (!origin || !offsets || !k)) return fail(c, HC_ERR_ARG, "null cell array");
-  const int64_t nv = c->hm.nv;
-  HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n * 3 * 4));
-  HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n * nv * 3 * 4));
+// Shared by the two ways of setting cells: stiffnesses, traction and the
+// reset of everything that belonged to the previous cells.
+static hc_status cells_changed(hc_ctx* c, int32_t n, const float* k, const float* traction) {
   HC_TRY(copy_h2d(c, (void*)c->C.k, k, (size_t)n * 4 * 4));
   if (traction) {
     HC_TRY(copy_h2d(c, at<float>(c, c->o_trac), traction, (size_t)n * 3 * 4));
@@ -615,6 +614,27 @@ hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float*
   HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
   return sync(c, "set_cells");
+}
+
+hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float* offsets,
+                       const float* k, const float* traction) {
+  HC_TRY(need_ws(c));
+  if (n < 0 || n > c->max_cells) return fail(c, HC_ERR_ARG, "cell count outside [0, max_cells]");
+  if (n > 0 && (!origin || !offsets || !k)) return fail(c, HC_ERR_ARG, "null cell array");
+  const int64_t nv = c->hm.nv;
+  HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n * 3 * 4));
+  HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n * nv * 3 * 4));
+  return cells_changed(c, n, k, traction);
+}
+
+hc_status hc_place_cells(hc_ctx* c, int32_t n, const float* centres, const float* rot, const float* k,
+                         const float* traction) {
+  HC_TRY(need_ws(c));
+  if (n < 0 || n > c->max_cells) return fail(c, HC_ERR_ARG, "cell count outside [0, max_cells]");
+  if (n > 0 && (!centres || !rot || !k)) return fail(c, HC_ERR_ARG, "null cell array");
+  HC_TRY(check(c, launch_place_cells(c->C, c->hm.nv, at<float>(c, c->o_rest), centres, rot, n, c->stream),
+               "place cells"));
+  return cells_changed(c, n, k, traction);
 }
 
 hc_status hc_init_equilibrium(hc_ctx* c, float rho0, const float u0[3]) {

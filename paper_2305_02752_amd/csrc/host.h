@@ -26,4 +26,10 @@ std::string build_mesh(const hc_mesh_desc* d, HostMesh& m);
 // Message returned by hc_last_error(NULL): errors of calls without a context.
 void set_global_error(const std::string& msg);
 
+// Place the rest mesh (rest [nv][3]) at every centre with every rotation
+// (device arrays centres [n][3], rot [n][9] row-major, columns = body axes):
+// origin = floor(centre), offsets = R rest + (centre - origin), into C.
+hipError_t launch_place_cells(const Cells& c, int nv, const float* rest, const float* centres,
+                              const float* rot, int n, hipStream_t s);
+
 }  // namespace hc

@@ -375,6 +375,33 @@ int ball_points(int m) {
   return q;
 }
 
+// One work-group per cell: the rest mesh rotated and translated to the
+// cell's ellipsoid.
+__global__ __launch_bounds__(256) void k_place_cells(Cells C, int nv, const float* __restrict__ rest,
+                                                     const float* __restrict__ centres,
+                                                     const float* __restrict__ rot) {
+  const int c = blockIdx.x;
+  float o[3], R[9];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) o[d] = centres[3 * c + d];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) R[e] = rot[9 * c + e];
+  int org[3];
+  float frac[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    org[d] = (int)floorf(o[d]);
+    frac[d] = o[d] - (float)org[d];
+  }
+  if (threadIdx.x < 3) C.origin[3 * c + threadIdx.x] = org[threadIdx.x];
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    const float p0 = rest[3 * v], p1 = rest[3 * v + 1], p2 = rest[3 * v + 2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      C.off[((int64_t)c * nv + v) * 3 + d] = ((R[3 * d] * p0 + R[3 * d + 1] * p1) + R[3 * d + 2] * p2) + frac[d];
+  }
+}
+
 struct PackPlan {
   PackGeom G;
   int64_t nbins = 0;
@@ -443,6 +470,14 @@ hc_status pack_fail(hc_status s, const std::string& msg) {
   } while (0)
 
 }  // namespace
+
+hipError_t launch_place_cells(const Cells& c, int nv, const float* rest, const float* centres,
+                              const float* rot, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_place_cells, dim3(n), dim3(256), 0, s, c, nv, rest, centres, rot);
+  return hipGetLastError();
+}
+
 }  // namespace hc
 
 using namespace hc;

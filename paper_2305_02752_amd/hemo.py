@@ -83,6 +83,7 @@ def _declare(lib):
         "hc_adj_backward": [_P, _P],
         "hc_pack_query_workspace": [_P, i32, _P],
         "hc_pack_run": [_P, _P, _P, _P, i32, i32, _P, sz, _P, _P],
+        "hc_place_cells": [_P, i32, _P, _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -225,6 +226,18 @@ class Simulation:
         Euler or second-order Adams-Bashforth ("ab2") vertex moves."""
         code = {"euler": 0, "ab2": 1}[scheme]
         self._check(self.lib.hc_set_integration(self.ctx, int(force_every), code))
+
+    def place_cells(self, centres, rot, k, traction=None):
+        """Cells from packed ellipsoids on the device: centres [n,3] and rot
+        [n,3,3] (or [n,9]) float32 device tensors; k [n,4] and traction
+        [n,3] host arrays."""
+        n = int(centres.shape[0])
+        kk = np.ascontiguousarray(k, dtype=np.float32).reshape(n, 4)
+        tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float32).reshape(n, 3)
+        self._check(self.lib.hc_place_cells(self.ctx, n, C.c_void_p(centres.data_ptr()),
+                                            C.c_void_p(rot.data_ptr()), _ptr(kk),
+                                            None if tr is None else _ptr(tr)))
+        self.n_cells = n
 
     def set_interior_viscosity(self, ratio: float):
         """Sites inside the cells relax with `ratio` times the plasma

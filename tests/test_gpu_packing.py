@@ -171,3 +171,42 @@ def test_large_sampled_parity():
         sub = np.r_[[i], near[near != i]]
         ref, _ = P.iterate(r[sub], R[sub], s[sub], dom, 0.03, 1.0, 8, np.float32)
         assert _close(new[i:i + 1], ref[:1], dom, np.abs(P.min_image(ref[:1] - r[i:i + 1], dom)).max() + 1e-3)
+
+
+def test_pack_then_place_cells_on_device():
+    """Packed ellipsoids become cells without leaving the device: the
+    placement matches the host placement of the same centres and rotations
+    (float32 offsets within 4e-6, a few ulp), and the packed suspension steps."""
+    import torch
+
+    from paper_2305_02752_amd import Simulation
+    from workloads import rbc_mesh
+    from workloads.configs import RBC_SURROGATE, Lattice, place_cells
+
+    rng = np.random.default_rng(25)
+    lat = Lattice(64, 48, 48, tau=1.0, body_force=(1e-6, 0.0, 0.0))
+    box = (64.0, 48.0, 48.0)
+    n = int(0.25 * 64 * 48 * 48 / P.volume(RBC_SURROGATE))
+    r, R, s = _config(rng, n, box, RBC_SURROGATE)
+    s[:] = np.asarray(RBC_SURROGATE, dtype=np.float32)
+    pk = _packer(_domain(box), max(RBC_SURROGATE), 0.03, 1.0, 8)
+    dev = torch.device("cuda:0")
+    tc = torch.tensor(r, device=dev)
+    tr = torch.tensor(R.reshape(-1, 9), device=dev)
+    ts = torch.tensor(s, device=dev)
+    rec = pk.run_device(tc, tr, ts, 60)
+    assert rec[3] < 0.2 * rec[1]
+    rest64, tri = rbc_mesh()
+    k = np.tile([1.5e-4, 1e-5, 5e-2, 1e-2], (n, 1))
+    sim = Simulation(lat, rest64.astype(np.float32), tri, max_cells=n)
+    sim.place_cells(tc, tr, k)
+    o, off, _ = sim.read_vertices()
+    ref = place_cells(rest64.astype(np.float32).astype(np.float64), tc.cpu().numpy().astype(np.float64),
+                      R.astype(np.float64), k)
+    assert np.array_equal(o, ref.origin)
+    assert np.abs(off - ref.offsets).max() <= 4e-6
+    sim.init_equilibrium()
+    sim.step(5)
+    sim.sync()
+    o2, off2, _ = sim.read_vertices()
+    assert np.isfinite(off2).all()
