@@ -520,9 +520,10 @@ hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot
   const size_t lds = (size_t)ball_points(P.G.m) * sizeof(float4);
   float* cur = centres;
   float* nxt = buf;
-  // n_iter moves, then one evaluation at the final positions
+  // n_iter moves, then one evaluation at the final positions (when asked for)
   for (int it = 0; it <= n_iter && n > 0; ++it) {
     const bool move = it < n_iter;
+    if (!move && !overlap) break;   // the final evaluation only feeds the overlap record
     PK_TRY(launch_fill_i32(cnt, 0, P.nbins, s), "clear bins");
     hipLaunchKernelGGL(k_pack_bin, gb, dim3(256), 0, s, P.G, cur, n, cnt, items, flags);
     PK_TRY(hipGetLastError(), "bin");
