@@ -101,6 +101,16 @@ __device__ inline void tile_origin(const Lattice& L, int t, int& x0, int& y0, in
   z0 = (t / (L.tx * L.ty)) * kTile;
 }
 
+// acc += trunc(q) for contributions of 2^31 or more (out of line, rare).
+// Node contributions are converted to fixed point by truncation in both
+// paths, so which path an entry takes never changes an integer.
+__device__ __noinline__ void spread_add_wide(long long* a0, long long* a1, long long* a2, float x, float y,
+                                             float z) {
+  atomicAdd((unsigned long long*)a0, (unsigned long long)(long long)x);
+  atomicAdd((unsigned long long*)a1, (unsigned long long)(long long)y);
+  atomicAdd((unsigned long long*)a2, (unsigned long long)(long long)z);
+}
+
 // Spread phase of one tile: one thread per (vertex, tile) entry of the
 // tile's list; the thread evaluates its 3 x K axis weights once and adds the
 // contributions of the stencil nodes inside the tile to the LDS accumulator
@@ -149,6 +159,13 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
       for (int kz = 0; kz < K; ++kz) {
         if (lz[kz] < 0) continue;
         pick_x(kz);
+        float gx[K], gy[K], gz[K];
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+          gx[kx] = wx[kx] * fx;
+          gy[kx] = wx[kx] * fy;
+          gz[kx] = wx[kx] * fz;
+        }
 #pragma unroll
         for (int ky = 0; ky < K; ++ky) {
           if (ly[ky] < 0) continue;
@@ -157,11 +174,10 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
 #pragma unroll
           for (int kx = 0; kx < K; ++kx) {
             if (lx[kx] < 0) continue;
-            const float w = wzy * wx[kx];
             const int li = row + lx[kx];
-            atomicAdd((unsigned long long*)&acc[0][li], (unsigned long long)(long long)__float2int_rn(w * fx));
-            atomicAdd((unsigned long long*)&acc[1][li], (unsigned long long)(long long)__float2int_rn(w * fy));
-            atomicAdd((unsigned long long*)&acc[2][li], (unsigned long long)(long long)__float2int_rn(w * fz));
+            atomicAdd((unsigned long long*)&acc[0][li], (unsigned long long)(long long)(int)(wzy * gx[kx]));
+            atomicAdd((unsigned long long*)&acc[1][li], (unsigned long long)(long long)(int)(wzy * gy[kx]));
+            atomicAdd((unsigned long long*)&acc[2][li], (unsigned long long)(long long)(int)(wzy * gz[kx]));
           }
         }
       }
@@ -175,9 +191,10 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
           const int row = (lz[kz] * kTile + ly[ky]) * kTile;
           for (int kx = 0; kx < K; ++kx) {
             if (lx[kx] < 0) continue;
-            const float w = wzy * wx[kx];
             const int li = row + lx[kx];
-            fix_add3_wide(&acc[0][li], &acc[1][li], &acc[2][li], w * fx, w * fy, w * fz);
+            // the same products as the 32-bit path: wzy * (wx * f)
+            spread_add_wide(&acc[0][li], &acc[1][li], &acc[2][li], wzy * (wx[kx] * fx), wzy * (wx[kx] * fy),
+                            wzy * (wx[kx] * fz));
           }
         }
       }
