@@ -133,6 +133,28 @@ def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int
             "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
 
 
+def bench_fluid_only(torch, w, warmup: int, steps: int):
+    """The same lattice with no cells: the fused lattice pass reduced to
+    pull-stream + collide, against the same 152 B/site and the same peak.
+    Splits the coupled pass's time into its streaming part and its IBM
+    phases."""
+    from paper_2305_02752_amd import Simulation
+    lat = w.lattice
+    sim = Simulation(lat, w.rest_pos, w.tri, max_cells=1)
+    sim.init_equilibrium()
+    sim.set_field_output(False)
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    sim.step(steps)
+    sim.sync()
+    ms, n = sim.profile_read()["lattice"]
+    sim.close()
+    avg = ms / max(n, 1)
+    gbps = BYTES_PER_SITE * lat.n_sites / (avg * 1e-3) / 1e9
+    return {"steps": steps, "lattice_pass_ms": avg, "achieved_GBps": gbps, "frac": gbps / PEAK_HBM_GBPS}
+
+
 def bench_interior(sim, n_sites: int, warmup: int, steps: int, ratio: float = 5.0):
     """The same suspension with the cytosol `ratio` times as viscous as the
     plasma: the sites inside the cells are marked every step and relax with
@@ -426,8 +448,13 @@ def main():
         adj = bench_adjoint(torch, boxes=args.adjoint_boxes)
         log(f"adjoint: {adj['grads_per_s']:.2f} gradients/s, t_grad/t_fwd {adj['t_grad_over_t_forward']:.2f}")
 
-    small = lees = packing = None
+    small = lees = packing = fluid = None
     if not args.no_extra:
+        log("the same lattice without cells ...")
+        fluid = bench_fluid_only(torch, w, args.warmup, args.steps)
+        torch.cuda.empty_cache()
+        log(f"  lattice pass {fluid['lattice_pass_ms']:.3f} ms, {fluid['achieved_GBps']:.0f} GB/s "
+            f"({100 * fluid['frac']:.1f}% of peak)")
         log("force-bias packing of a million ellipsoids ...")
         packing = bench_packing(torch)
         torch.cuda.empty_cache()
@@ -475,6 +502,7 @@ def main():
         "small_workloads": small,
         "lees_edwards_shear": lees,
         "force_bias_packing": packing,
+        "fluid_only_lattice_pass": fluid,
         "batched_calibration": batched,
         "adjoint": adj,
     }

@@ -212,8 +212,9 @@ hc_status hc_set_integration(hc_ctx* ctx, int32_t force_every, int32_t scheme);
  * edge is counted by exactly one of the two triangles sharing the edge.
  * The marks are recomputed every step from the positions the step spreads
  * from.  ratio > 0; 1 (the default) switches the marking off.  Limits per
- * cell: a bounding box of at most 1024 (x, y) node columns and 8 membrane
- * crossings per column (hc_sync reports HC_ERR_UNSUPPORTED beyond).  Not
+ * cell: at most 320 node columns along x, bounding-box sides under 1024,
+ * and 8 membrane crossings per column (hc_sync reports HC_ERR_UNSUPPORTED
+ * beyond).  Not
  * combined with Lees-Edwards images or the adjoint calls
  * (HC_ERR_UNSUPPORTED). */
 hc_status hc_set_interior_viscosity(hc_ctx* ctx, float ratio);

@@ -667,7 +667,8 @@ hc_status hc_sync(hc_ctx* c) {
     if (flags[1] & 4) return fail(c, HC_ERR_UNSUPPORTED, "a tile list exceeded its capacity");
     if (flags[1] & 8) return fail(c, HC_ERR_UNSUPPORTED, "a cell reaches more than 256 tiles");
     if (flags[1] & 16)
-      return fail(c, HC_ERR_UNSUPPORTED, "a cell spans more than 1024 node columns (interior marking)");
+      return fail(c, HC_ERR_UNSUPPORTED,
+                  "a cell is too wide for the interior marking (over 320 columns along x)");
     if (flags[1] & 32)
       return fail(c, HC_ERR_UNSUPPORTED, "a node column crosses a membrane more than 8 times");
     return fail(c, HC_ERR_UNSUPPORTED, "a cell covers more than 216 tiles");

@@ -6,8 +6,9 @@
 // it lies strictly between z_(2k-1) and z_(2k).
 //
 // One work-group per cell.  The cell's (x, y) node columns within its
-// bounding box are a small grid (at most kMaxCols); every triangle adds its
-// crossing height to each column its projection covers (edge points are
+// bounding box form a small grid, held in LDS in chunks of whole rows of at
+// most kMaxCols columns (one chunk for an undeformed cell); every triangle
+// adds its crossing height to each column its projection covers (edge points are
 // kept by exactly one of the two triangles sharing the edge: after orienting
 // the triangle counter-clockwise in projection, edge P -> Q keeps them when
 // Q.y > P.y, or Q.y == P.y and Q.x < P.x); each column then sorts its
@@ -22,7 +23,7 @@ namespace hc {
 namespace {
 
 constexpr int kMarkThreads = 256;
-constexpr int kMaxCols = 1024;   // (x, y) columns of one cell's bounding box
+constexpr int kMaxCols = 320;    // (x, y) columns held in LDS at once (whole rows)
 constexpr int kMaxCross = 8;     // crossings per column
 constexpr float kMaxSpan = 1024.f;   // bounding-box side beyond which a cell is refused
 constexpr float kMaxOff = 16777216.f;   // offsets from the cell origin beyond which it is refused
@@ -95,90 +96,95 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
   __syncthreads();
   const int lx = box[0], ly = box[1], ncx = box[2], ncy = box[3];
   if (ncx <= 0 || ncy <= 0) return;
-  if (ncx * ncy > kMaxCols) {   // a cell wider than the column grid
+  if (ncx > kMaxCols) {   // a cell wider than the column grid along x
     if (tid == 0) atomicOr(&flags[1], 16);
     return;
   }
-  for (int i = tid; i < ncx * ncy; i += kMarkThreads) cnt[i] = 0;
-  __syncthreads();
-
-  for (int t = tid; t < M.nt; t += kMarkThreads) {
-    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-    float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
-    float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
-    float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
-    const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-    if (area2 == 0.f) continue;
-    if (area2 < 0.f) {   // orient counter-clockwise in projection
-      float tx = bx, ty = by, tz = bz;
-      bx = cx, by = cy, bz = cz;
-      cx = tx, cy = ty, cz = tz;
-    }
-    const float A = fabsf(area2);
-    const int x0 = max((int)ceilf(fminf(ax, fminf(bx, cx))), lx);
-    const int x1 = min((int)floorf(fmaxf(ax, fmaxf(bx, cx))), lx + ncx - 1);
-    const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly);
-    const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + ncy - 1);
-    for (int iy = y0; iy <= y1; ++iy)
-      for (int ix = x0; ix <= x1; ++ix) {
-        const float x = (float)ix, y = (float)iy;
-        if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
-              edge_in(cx, cy, ax, ay, x, y)))
-          continue;
-        const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
-        const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
-        const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
-        const float z = (wa * az + wb * bz + wc * cz) / A;
-        const int col = (iy - ly) * ncx + (ix - lx);
-        const int slot = atomicAdd(&cnt[col], 1);
-        if (slot < kMaxCross) zc[col][slot] = z;
-        else atomicOr(&flags[1], 32);
-      }
-  }
-  __syncthreads();
-
   const int ox = C.origin[3 * c], oy = C.origin[3 * c + 1], oz = C.origin[3 * c + 2];
   const unsigned bit = 1u << (cls ? cls[c] : 0);
-  for (int col = tid; col < ncx * ncy; col += kMarkThreads) {
-    const int n = min(cnt[col], kMaxCross);
-    if (n < 2) continue;
-    float z[kMaxCross];
-    for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
-    for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
-      for (int j = i; j > 0; --j)
-        if (z[j] < z[j - 1]) {
-          const float s = z[j];
-          z[j] = z[j - 1];
-          z[j - 1] = s;
+  // the columns in chunks of whole rows that fit the LDS grid (one chunk for
+  // an undeformed cell)
+  const int rows = kMaxCols / ncx;
+  for (int r0 = 0; r0 < ncy; r0 += rows) {
+    const int nr = min(rows, ncy - r0);
+    for (int i = tid; i < nr * ncx; i += kMarkThreads) cnt[i] = 0;
+    __syncthreads();
+    for (int t = tid; t < M.nt; t += kMarkThreads) {
+      const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+      float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
+      float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
+      float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
+      const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+      if (area2 == 0.f) continue;
+      if (area2 < 0.f) {   // orient counter-clockwise in projection
+        float tx = bx, ty = by, tz = bz;
+        bx = cx, by = cy, bz = cz;
+        cx = tx, cy = ty, cz = tz;
+      }
+      const float A = fabsf(area2);
+      const int x0 = max((int)ceilf(fminf(ax, fminf(bx, cx))), lx);
+      const int x1 = min((int)floorf(fmaxf(ax, fmaxf(bx, cx))), lx + ncx - 1);
+      const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly + r0);
+      const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + r0 + nr - 1);
+      for (int iy = y0; iy <= y1; ++iy)
+        for (int ix = x0; ix <= x1; ++ix) {
+          const float x = (float)ix, y = (float)iy;
+          if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
+                edge_in(cx, cy, ax, ay, x, y)))
+            continue;
+          const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
+          const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
+          const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
+          const float z = (wa * az + wb * bz + wc * cz) / A;
+          const int col = (iy - ly - r0) * ncx + (ix - lx);
+          const int slot = atomicAdd(&cnt[col], 1);
+          if (slot < kMaxCross) zc[col][slot] = z;
+          else atomicOr(&flags[1], 32);
         }
-    int xs = ox + lx + col % ncx, ys = oy + ly + col / ncx;
-    if (L.bc[0] == 1) {
-      if (xs < 0 || xs >= L.nx) continue;
-    } else {
-      xs = wrap(xs, L.nx);
     }
-    if (L.bc[1] == 1) {
-      if (ys < 0 || ys >= L.ny) continue;
-    } else {
-      ys = wrap(ys, L.ny);
-    }
-    for (int k = 0; k + 1 < n; k += 2) {
-      // the heights lie within the cell's bounded z extent
-      const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
-      for (int iz = z0; iz <= z1; ++iz) {
-        int zs = oz + iz;
-        if (L.bc[2] == 1) {
-          if (zs < 0 || zs >= L.nz) continue;
-        } else {
-          zs = wrap(zs, L.nz);
+    __syncthreads();
+    for (int col = tid; col < nr * ncx; col += kMarkThreads) {
+      const int n = min(cnt[col], kMaxCross);
+      if (n < 2) continue;
+      float z[kMaxCross];
+      for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
+      for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
+        for (int j = i; j > 0; --j)
+          if (z[j] < z[j - 1]) {
+            const float s = z[j];
+            z[j] = z[j - 1];
+            z[j - 1] = s;
+          }
+      int xs = ox + lx + col % ncx, ys = oy + ly + r0 + col / ncx;
+      if (L.bc[0] == 1) {
+        if (xs < 0 || xs >= L.nx) continue;
+      } else {
+        xs = wrap(xs, L.nx);
+      }
+      if (L.bc[1] == 1) {
+        if (ys < 0 || ys >= L.ny) continue;
+      } else {
+        ys = wrap(ys, L.ny);
+      }
+      for (int k = 0; k + 1 < n; k += 2) {
+        // the heights lie within the cell's bounded z extent
+        const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
+        for (int iz = z0; iz <= z1; ++iz) {
+          int zs = oz + iz;
+          if (L.bc[2] == 1) {
+            if (zs < 0 || zs >= L.nz) continue;
+          } else {
+            zs = wrap(zs, L.nz);
+          }
+          const int64_t h = site_of(L, xs, ys, zs);
+          if (multi)   // the word holding the byte; the mask is 4-byte aligned
+            atomicOr(reinterpret_cast<unsigned*>(mask + (h & ~(int64_t)3)), bit << (8 * (h & 3)));
+          else
+            mask[h] = (unsigned char)bit;
         }
-        const int64_t h = site_of(L, xs, ys, zs);
-        if (multi)   // the word holding the byte; the mask is 4-byte aligned
-          atomicOr(reinterpret_cast<unsigned*>(mask + (h & ~(int64_t)3)), bit << (8 * (h & 3)));
-        else
-          mask[h] = (unsigned char)bit;
       }
     }
+    __syncthreads();   // the grid is reused by the next chunk
   }
 }
 

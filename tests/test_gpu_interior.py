@@ -201,3 +201,53 @@ def test_no_cells_with_interior_viscosity():
     sim.set_interior_viscosity(5.0)
     sim.step(2)
     assert not sim.read_interior().any()
+
+
+def test_interior_with_separated_time_scales():
+    """Interior viscosity combined with forces every 3 steps and
+    Adams-Bashforth moves: the marks follow the moving cells every step."""
+    from oracle import integrate
+    w = tiny_periodic(seed=52, n=(24, 22, 20), n_cells=2, walls=1, body=(1e-5, 0, 0))
+    rng = np.random.default_rng(53)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    g0 = random_shifted_populations(rng, w.lattice, 1e-3)
+    sim = make_sim(w, cells)
+    sim.write_populations(g0)
+    sim.set_interior_viscosity(4.0)
+    sim.set_integration(3, "ab2")
+    n = 10
+    sim.step(n)
+    sim.sync()
+    m = step.make_model(w.lattice, w.rest_pos.astype(np.float64), w.tri, cells.k.astype(np.float64),
+                        cells.traction.astype(np.float64), interior_ratio=4.0)
+    f0, X0 = oracle_state(g0, cells)
+    f, X, _ = integrate.run(m, f0, X0, n, force_every=3, scheme="ab2")
+    o, off, _ = sim.read_vertices()
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    Xg = o[:, None, :] + off.astype(np.float64)
+    bound = n * 6e-8 * np.abs(off).max() + TOL * np.abs(X - X0).max()
+    e_x = np.abs(Xg - X).max()
+    print("pops", e_g, "position", e_x, "bound", bound, flush=True)
+    assert e_g <= TOL and e_x <= bound
+
+
+def test_marks_of_a_stretched_cell_in_row_chunks():
+    """A cell stretched along y to a bounding box of more than 320 columns
+    is marked in several row chunks; the marks still match the oracle."""
+    rest64, tri = rbc_mesh()
+    lat = Lattice(40, 64, 24, tau=0.9)
+    stretch = np.diag([1.0, 2.6, 1.0])
+    from workloads.configs import place_cells as pc
+    cells = pc(rest64 @ stretch.T, np.array([[19.3, 31.7, 11.4]]), np.eye(3)[None], np.ones((1, 4)) * 1e-3)
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri,
+                                   cells=cells), cells)
+    sim.init_equilibrium()
+    sim.set_interior_viscosity(2.0)
+    o, off = cells.origin, cells.offsets
+    span = np.floor(off[0].max(0)) - np.ceil(off[0].min(0)) + 1
+    assert span[0] * span[1] > 320          # more than one chunk
+    dev = sim.read_interior()
+    ref = interior.inside_sites(off, tri, (40, 64, 24), lat.bc, origin=o)
+    assert ref.sum() > 1000
+    assert np.array_equal(dev, ref.astype(np.uint8))
