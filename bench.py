@@ -175,6 +175,35 @@ def bench_interior(sim, n_sites: int, warmup: int, steps: int, ratio: float = 5.
             "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()}}
 
 
+def bench_mixture(sim, w, n_sites: int, warmup: int, steps: int, stiff_fraction: float = 0.5,
+                  link_scale: float = 5.0, ratio_healthy: float = 5.0, ratio_stiff: float = 10.0):
+    """Stiffened/healthy mixture of the same suspension (Sec. 3.4: stiffened
+    cells scale the link coefficient and the internal viscosity ratio; the
+    paper gives no factors, these are readings): every other cell stiffened,
+    one interior viscosity ratio per cell."""
+    n = w.cells.n
+    stiff = (np.arange(n) % int(round(1.0 / stiff_fraction))) == 0
+    k = w.cells.k.astype(np.float32).copy()
+    k[stiff, 0] *= link_scale
+    sim.set_params(k=k)
+    sim.set_cell_viscosity(np.where(stiff, ratio_stiff, ratio_healthy))
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.set_interior_viscosity(1.0)
+    sim.set_params(k=w.cells.k)
+    return {"stiff_fraction": float(stiff.mean()), "link_scale": link_scale,
+            "ratios": [ratio_healthy, ratio_stiff], "steps": steps, "ms_per_step": dt / steps * 1e3,
+            "MLUPS": n_sites * steps / dt / 1e6,
+            "kernel_ms": {kk: ms / max(c, 1) for kk, (ms, c) in prof.items()}}
+
+
 def bench_lees_edwards(torch, w, warmup: int, steps: int, u_le: float = 0.02):
     """The large suspension as a boundary-free shear: the same lattice and
     cells with Lees-Edwards images (gradient z, flow x, image velocity u_le)
@@ -426,7 +455,7 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_s * 1e3}
 
-    tss = interior = None
+    tss = interior = mixture = None
     if not args.no_extra:
         tss = bench_separated(sim, n_sites, args.warmup, args.steps)
         log(f"separated time scales (forces every {tss['force_every']}, {tss['scheme']}): "
@@ -434,6 +463,9 @@ def main():
         interior = bench_interior(sim, n_sites, args.warmup, args.steps)
         log(f"interior viscosity ratio {interior['ratio']}: {interior['ms_per_step']:.3f} ms/step, "
             f"marking {interior['kernel_ms']['interior']:.3f} ms")
+        mixture = bench_mixture(sim, w, n_sites, args.warmup, args.steps)
+        log(f"stiffened/healthy mixture: {mixture['ms_per_step']:.3f} ms/step, "
+            f"marking {mixture['kernel_ms']['interior']:.3f} ms")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -499,6 +531,7 @@ def main():
         "cpu_baseline": cpu,
         "separated_time_scales": tss,
         "interior_viscosity": interior,
+        "stiffened_mixture": mixture,
         "small_workloads": small,
         "lees_edwards_shear": lees,
         "force_bias_packing": packing,

@@ -1,0 +1,139 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/hemo.h declares, the Python binding declares them all, and the
+host-side validation of the calls that touch no device memory behaves as
+the header documents (creation, workspace sizing, settings, packing plans).
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hemo.h")
+
+OK, ARG, UNSUPPORTED = 0, 1, 6
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:hc_status|const char\s*\*|void)\s+(hc_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2305_02752_amd import hemo
+    if not os.path.exists(hemo.LIB_PATH):
+        from paper_2305_02752_amd import build
+        build.build()
+    return hemo.load_library()
+
+
+def test_header_declares_the_calls():
+    names = declared_functions()
+    for must in ("hc_create", "hc_step", "hc_sync", "hc_read_populations", "hc_adj_backward",
+                 "hc_batch_run", "hc_pack_run", "hc_place_cells", "hc_set_interior_viscosity"):
+        assert must in names
+    assert len(names) > 50
+
+
+def test_every_declared_function_is_exported(lib):
+    from paper_2305_02752_amd import hemo
+    out = subprocess.run(["nm", "-D", "--defined-only", hemo.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s+(hc_\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_binding_declares_every_function(lib):
+    # every exported call has its argument types set by the binding (the
+    # batched calls are declared when the first Batch is made)
+    from paper_2305_02752_amd import hemo
+    hemo._declare_batch(lib)
+    missing = [n for n in declared_functions() if getattr(lib, n).argtypes is None]
+    assert not missing, missing
+
+
+def _mesh(rbc):
+    from paper_2305_02752_amd import hemo
+    rest, tri = rbc
+    rest = np.ascontiguousarray(rest, dtype=np.float32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    m = hemo.MeshDesc(rest.shape[0], tri.shape[0], tri.ctypes.data_as(C.POINTER(C.c_int32)),
+                      rest.ctypes.data_as(C.POINTER(C.c_float)))
+    return m, (rest, tri)
+
+
+def _create(lib, lat, rbc, max_cells=4):
+    from paper_2305_02752_amd import hemo
+    d = hemo.lattice_desc(lat)
+    m, keep = _mesh(rbc)
+    ctx = C.c_void_p()
+    rc = lib.hc_create(C.byref(d), C.byref(m), max_cells, C.byref(ctx))
+    return rc, ctx, keep
+
+
+def test_create_validates_without_a_device(lib, rbc):
+    from workloads.configs import Lattice
+    rc, ctx, _ = _create(lib, Lattice(32, 24, 16, tau=1.0), rbc)
+    assert rc == OK
+    n = C.c_size_t()
+    assert lib.hc_query_workspace(ctx, C.byref(n)) == OK and n.value > 19 * 32 * 24 * 16 * 4 * 2
+    lib.hc_destroy(ctx)
+    for lat, code, msg in [
+        (Lattice(32, 24, 16, tau=0.5), ARG, b"tau"),
+        (Lattice(32, 24, 16, tau=1.0, bc=(1, 1, 0)), UNSUPPORTED, b""),
+        (Lattice(32, 24, 16, tau=1.0, bc=(0, 0, 1), lees_edwards_u=0.01), UNSUPPORTED, b"Lees-Edwards"),
+        (Lattice(30, 24, 16, tau=1.0, lees_edwards_u=0.01), UNSUPPORTED, b"multiples of 8"),
+    ]:
+        rc, ctx, _ = _create(lib, lat, rbc)
+        assert rc == code, (lat, rc)
+        assert msg in lib.hc_last_error(None)
+
+
+def test_settings_validate_without_a_device(lib, rbc):
+    from workloads.configs import Lattice
+    rc, ctx, _ = _create(lib, Lattice(32, 24, 16, tau=1.0), rbc)
+    assert rc == OK
+    assert lib.hc_set_integration(ctx, 0, 0) == ARG
+    assert lib.hc_set_integration(ctx, 2, 7) == ARG
+    assert lib.hc_set_integration(ctx, 4, 1) == OK
+    assert lib.hc_set_interior_viscosity(ctx, 0.0) == ARG
+    assert lib.hc_set_interior_viscosity(ctx, float("inf")) == ARG
+    assert lib.hc_set_interior_viscosity(ctx, 5.0) == OK
+    assert lib.hc_set_field_output(ctx, 0) == OK
+    # calls that need the device workspace refuse before touching the device
+    assert lib.hc_step(ctx, 1) == 2    # HC_ERR_STATE: no workspace bound
+    lib.hc_destroy(ctx)
+    rc, ctx, _ = _create(lib, Lattice(32, 24, 16, tau=1.0, lees_edwards_u=0.02), rbc)
+    assert rc == OK
+    assert lib.hc_set_interior_viscosity(ctx, 5.0) == UNSUPPORTED
+    lib.hc_destroy(ctx)
+
+
+def _pack(box=(100.0, 100.0, 100.0), per=(1, 1, 1), lo=(0, 0, 0), hi=(0, 0, 0), max_semi=8.5, eta=0.03,
+          max_move=1.0, quad=8):
+    from paper_2305_02752_amd import hemo
+    return hemo.PackDesc((C.c_float * 3)(*box), (C.c_int32 * 3)(*per), (C.c_float * 3)(*lo),
+                         (C.c_float * 3)(*hi), max_semi, eta, max_move, quad)
+
+
+def test_packing_plan_validation(lib):
+    n = C.c_size_t()
+    assert lib.hc_pack_query_workspace(C.byref(_pack()), 1000, C.byref(n)) == OK
+    small = n.value
+    assert lib.hc_pack_query_workspace(C.byref(_pack()), 100000, C.byref(n)) == OK and n.value > small
+    for d, why in [(_pack(quad=5), b"quad"), (_pack(box=(30.0, 100.0, 100.0)), b"periodic side"),
+                   (_pack(per=(1, 1, 0), lo=(0, 0, 2), hi=(0, 0, 10)), b"wall axis"),
+                   (_pack(eta=float("nan")), b"eta"), (_pack(max_move=0.0), b"max_move"),
+                   (_pack(max_semi=-1.0), b"max_semi")]:
+        assert lib.hc_pack_query_workspace(C.byref(d), 1000, C.byref(n)) == ARG
+        assert why in lib.hc_last_error(None)
+    # run-time checks that precede any device work
+    assert lib.hc_pack_run(C.byref(_pack()), None, None, None, 10, 1, None, 0, None, None) == ARG
