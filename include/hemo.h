@@ -230,10 +230,10 @@ hc_status hc_set_interior_viscosity(hc_ctx* ctx, float ratio);
 hc_status hc_set_cell_viscosity(hc_ctx* ctx, const float* ratio, int64_t n_cells);
 
 /* The inside marks of the current positions (after applying a pending
- * vertex move), uint8 [N] in natural site order (x fastest): bit k is set
- * when a cell of viscosity class k contains the site (classes are the
- * distinct ratios in increasing order; a single ratio is class 0), 0
- * outside every cell.  Synchronous; reports marking overflows as hc_sync
+ * vertex move), uint8 [N] in natural site order (x fastest): 1 << k for a
+ * site inside a cell of viscosity class k, the highest such k where cells
+ * of several classes overlap (classes are the distinct ratios in
+ * increasing order; a single ratio is class 0), 0 outside every cell.  Synchronous; reports marking overflows as hc_sync
  * does. */
 hc_status hc_read_interior(hc_ctx* ctx, uint8_t* inside, int64_t n_sites);
 

@@ -229,10 +229,17 @@ void interior_uniform(hc_ctx* c) {
   interior_update(c);
 }
 
+// One marking pass, or one per viscosity class in increasing order, so that
+// a site inside cells of several classes keeps the most viscous one.
 hipError_t mark_interior(hc_ctx* c, const Cells& C) {
-  const bool multi = c->n_vclass > 1;
-  return launch_mark_interior(C, c->M, c->L, c->mask, multi ? c->cell_class : nullptr, multi,
-                              c->B.flags, c->stream);
+  if (c->n_vclass <= 1)
+    return launch_mark_interior(C, c->M, c->L, c->mask, nullptr, -1, c->B.flags, c->stream);
+  for (int k = 0; k < c->n_vclass; ++k) {
+    const hipError_t e =
+        launch_mark_interior(C, c->M, c->L, c->mask, c->cell_class, k, c->B.flags, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void le_update(hc_ctx* c) {

@@ -168,13 +168,14 @@ hipError_t launch_tile_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             const float* gin, float* gout, float* F, float4* macro, float4* partial,
                             bool fields, unsigned char* mask, hipStream_t s);
 // Mark the sites inside the cells in the site-ordered mask, which must hold
-// zeros on entry: bit k of a site's byte is set when a cell of viscosity
-// class k (cls[c], or 0 for every cell when cls is null) contains it.  With
-// several classes (multi) the bits are OR-ed atomically, so overlapping
-// cells of different classes mark deterministically.  The lattice pass reads
-// and clears the mask.
+// zeros on entry: a site inside a cell of viscosity class k (cls[c], or 0
+// for every cell when cls is null) gets the byte 1 << k.  With several
+// classes the marking runs once per class in increasing order (only_class),
+// so a site inside cells of different classes ends with the highest class,
+// whatever the order of the cells.  The lattice pass reads and clears the
+// mask.
 hipError_t launch_mark_interior(const Cells& c, const Mesh& m, const Lattice& L, unsigned char* mask,
-                                const unsigned char* cls, bool multi, int* flags, hipStream_t s);
+                                const unsigned char* cls, int only_class, int* flags, hipStream_t s);
 // fused per-cell kernel: [advect of the pending step] + membrane + binning
 // (src: offsets to move from, or null to move in place; refresh: compute
 // the membrane forces, else hold the stored ones; ab2: Adams-Bashforth move)

@@ -13,7 +13,7 @@
 // the triangle counter-clockwise in projection, edge P -> Q keeps them when
 // Q.y > P.y, or Q.y == P.y and Q.x < P.x); each column then sorts its
 // crossings and marks the nodes between pairs.  The marks are bytes in the
-// site-ordered mask, one bit per viscosity class (cells of different
+// site-ordered mask as one bit for the viscosity class (cells of different
 // stiffness may carry different interior viscosities, Sec. 3.4), which the
 // lattice pass reads (and clears) to pick the relaxation time.
 #include "common.h"
@@ -42,13 +42,14 @@ __device__ inline bool edge_in(float px, float py, float qx, float qy, float x, 
 __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M, Lattice L,
                                                                 unsigned char* __restrict__ mask,
                                                                 const unsigned char* __restrict__ cls,
-                                                                int multi, int* __restrict__ flags) {
+                                                                int only_class, int* __restrict__ flags) {
   extern __shared__ float sp[];   // [nv][3] offsets
   __shared__ int cnt[kMaxCols];
   __shared__ float zc[kMaxCols][kMaxCross];
   __shared__ float bb[kMarkThreads / kWave][6];
   __shared__ int box[4];          // lo_x, lo_y, ncx, ncy (cell-local node coordinates)
   const int c = blockIdx.x, tid = threadIdx.x;
+  if (only_class >= 0 && cls[c] != only_class) return;   // another class's pass
   const int64_t b3 = (int64_t)c * M.nv * 3;
   float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
   for (int v = tid; v < M.nv; v += kMarkThreads) {
@@ -177,10 +178,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
             zs = wrap(zs, L.nz);
           }
           const int64_t h = site_of(L, xs, ys, zs);
-          if (multi)   // the word holding the byte; the mask is 4-byte aligned
-            atomicOr(reinterpret_cast<unsigned*>(mask + (h & ~(int64_t)3)), bit << (8 * (h & 3)));
-          else
-            mask[h] = (unsigned char)bit;
+          mask[h] = (unsigned char)bit;
         }
       }
     }
@@ -191,10 +189,10 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
 }  // namespace
 
 hipError_t launch_mark_interior(const Cells& c, const Mesh& m, const Lattice& L, unsigned char* mask,
-                                const unsigned char* cls, bool multi, int* flags, hipStream_t s) {
+                                const unsigned char* cls, int only_class, int* flags, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * 3 * sizeof(float);
-  hipLaunchKernelGGL(k_mark_interior, dim3(c.n), dim3(kMarkThreads), lds, s, c, m, L, mask, cls, multi ? 1 : 0,
+  hipLaunchKernelGGL(k_mark_interior, dim3(c.n), dim3(kMarkThreads), lds, s, c, m, L, mask, cls, only_class,
                      flags);
   return hipGetLastError();
 }

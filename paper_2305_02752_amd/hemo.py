@@ -250,9 +250,9 @@ class Simulation:
         self._check(self.lib.hc_set_cell_viscosity(self.ctx, _ptr(r), r.size))
 
     def read_interior(self):
-        """Inside marks of the current positions, uint8 [nz, ny, nx]: bit k
-        set inside a cell of viscosity class k (distinct ratios in
-        increasing order), 0 outside every cell."""
+        """Inside marks of the current positions, uint8 [nz, ny, nx]: 1 << k
+        inside a cell of viscosity class k (distinct ratios in increasing
+        order; the highest class where cells overlap), 0 outside."""
         m = np.empty((self.nz, self.ny, self.nx), dtype=np.uint8)
         self._check(self.lib.hc_read_interior(self.ctx, _ptr(m), m.size))
         return m

@@ -99,19 +99,21 @@ def test_coupled_parity_interior_viscosity(walls):
 
 
 def _class_bits(off, origin, tri, lat, ratios):
-    """Expected mask bytes: bit k for the cells of the k-th smallest ratio."""
+    """Expected mask bytes: 1 << k for the cells of the k-th smallest ratio,
+    the highest k where cells overlap (the largest ratio wins, as in the
+    oracle's ratio field)."""
     cls = np.searchsorted(np.unique(ratios), ratios)
     out = np.zeros((lat.nz, lat.ny, lat.nx), dtype=np.uint8)
     for c in range(len(ratios)):
         m = interior.inside_sites(off[c:c + 1], tri, (lat.nx, lat.ny, lat.nz), lat.bc,
                                   origin=origin[c:c + 1])
-        out[m] |= np.uint8(1 << cls[c])
+        out[m] = np.maximum(out[m], np.uint8(1 << cls[c]))
     return out
 
 
 def test_per_cell_classes_marks_and_overlap():
-    """Three viscosity classes; two cells overlap, so some sites carry two
-    class bits (deterministic OR)."""
+    """Three viscosity classes; two cells of different classes overlap, and
+    their shared sites carry the higher class, whatever the cell order."""
     rest64, tri = rbc_mesh()
     rng = np.random.default_rng(48)
     lat = Lattice(40, 32, 24, tau=0.9)
@@ -127,7 +129,10 @@ def test_per_cell_classes_marks_and_overlap():
     dev = sim.read_interior()
     ref = _class_bits(cells.offsets, cells.origin, tri, lat, ratios)
     print("bits", np.unique(ref, return_counts=True), flush=True)
-    assert (ref == 6).sum() > 20          # overlap of a ratio-5 and a ratio-2 cell
+    mA = interior.inside_sites(cells.offsets[:1], tri, (40, 32, 24), lat.bc, origin=cells.origin[:1])
+    mB = interior.inside_sites(cells.offsets[1:2], tri, (40, 32, 24), lat.bc, origin=cells.origin[1:2])
+    assert (mA & mB).sum() > 20           # overlap of a ratio-5 and a ratio-2 cell
+    assert (ref[mA & mB] == 4).all()      # the ratio-5 class (k = 2) wins
     assert np.array_equal(dev, ref)
     # a new cell set returns to the single ratio (here never set: off)
     sim.set_cells(cells.origin, cells.offsets, cells.k, None)
