@@ -55,50 +55,68 @@ def crossings(V: np.ndarray, tri: np.ndarray, x: np.ndarray, y: np.ndarray):
     return [np.sort(z[j][inside[j]]) for j in range(x.shape[0])]
 
 
-def inside_sites(X: np.ndarray, tri: np.ndarray, dims, bc, origin=None) -> np.ndarray:
+def _floor_div(a, b):
+    return np.floor_divide(a, b)
+
+
+def inside_sites(X: np.ndarray, tri: np.ndarray, dims, bc, origin=None, le_delta: float = 0.0) -> np.ndarray:
     """Boolean [nz, ny, nx]: the sites inside any cell.  X [C, nv, 3] holds
     positions (float64 arithmetic), or, with integer origins [C, 3], each
     cell's vertex offsets from its origin: then the crossings are found in
     those local coordinates in X's own precision, which lets a float32
-    caller reproduce the decisions of a float32 implementation exactly."""
+    caller reproduce the decisions of a float32 implementation exactly.
+
+    le_delta: with sheared periodic images (Sec. 2.5 reading: gradient axis
+    z, flow axis x, image m displaced by m * le_delta along x) a node whose
+    unwrapped z lies in image m = floor(z / nz) is inside when the cell's
+    copy displaced by -m * le_delta contains it, i.e. its column is taken at
+    cell-frame x + m * le_delta."""
     nx, ny, nz = dims
     n = (nx, ny, nz)
     mask = np.zeros((nz, ny, nx), dtype=bool)
     tri = np.asarray(tri, dtype=np.int64)
     X = np.asarray(X)
-    dt = X.dtype if origin is not None else np.float64
+    dt = X.dtype.type if origin is not None else np.float64
     for c, V in enumerate(X.astype(dt)):
         o = np.zeros(3, np.int64) if origin is None else np.asarray(origin[c], dtype=np.int64)
         lo = np.ceil(V.min(axis=0)).astype(np.int64)
         hi = np.floor(V.max(axis=0)).astype(np.int64)
-        gx, gy = np.meshgrid(np.arange(lo[0], hi[0] + 1), np.arange(lo[1], hi[1] + 1), indexing="ij")
-        gx, gy = gx.ravel(), gy.ravel()
-        zs = crossings(V, tri, gx.astype(dt), gy.astype(dt))
-        for ix, iy, z in zip(gx, gy, zs):
-            for k in range(0, len(z) - 1, 2):
-                iz = np.arange(np.floor(z[k]) + 1, np.ceil(z[k + 1])).astype(np.int64) + o[2]
-                idx = [np.int64(ix) + o[0], np.int64(iy) + o[1], iz]
-                ok = np.ones(iz.shape, dtype=bool)
-                for d in range(3):
-                    if bc[d] == WALL:
-                        ok &= (idx[d] >= 0) & (idx[d] < n[d])
-                    else:
-                        idx[d] = np.mod(idx[d], n[d])
-                mask[idx[2][ok], np.broadcast_to(idx[1], iz.shape)[ok],
-                     np.broadcast_to(idx[0], iz.shape)[ok]] = True
+        images = [0] if le_delta == 0.0 else range(int(_floor_div(o[2] + lo[2], nz)),
+                                                   int(_floor_div(o[2] + hi[2], nz)) + 1)
+        for m in images:
+            shift = dt(m) * dt(le_delta)
+            xl = np.arange(np.ceil(V[:, 0].min() - shift), np.floor(V[:, 0].max() - shift) + 1).astype(np.int64)
+            gx, gy = np.meshgrid(xl, np.arange(lo[1], hi[1] + 1), indexing="ij")
+            gx, gy = gx.ravel(), gy.ravel()
+            zs = crossings(V, tri, gx.astype(dt) + shift, gy.astype(dt))
+            for ix, iy, z in zip(gx, gy, zs):
+                for k in range(0, len(z) - 1, 2):
+                    iz = np.arange(np.floor(z[k]) + 1, np.ceil(z[k + 1])).astype(np.int64) + o[2]
+                    if le_delta != 0.0:
+                        iz = iz[_floor_div(iz, nz) == m]   # the nodes of this image only
+                    idx = [np.int64(ix) + o[0], np.int64(iy) + o[1], iz]
+                    ok = np.ones(iz.shape, dtype=bool)
+                    for d in range(3):
+                        if bc[d] == WALL:
+                            ok &= (idx[d] >= 0) & (idx[d] < n[d])
+                        else:
+                            idx[d] = np.mod(idx[d], n[d])
+                    mask[idx[2][ok], np.broadcast_to(idx[1], iz.shape)[ok],
+                         np.broadcast_to(idx[0], iz.shape)[ok]] = True
     return mask
 
 
-def ratio_field(X: np.ndarray, tri: np.ndarray, dims, bc, ratios, origin=None) -> np.ndarray:
+def ratio_field(X: np.ndarray, tri: np.ndarray, dims, bc, ratios, origin=None,
+                le_delta: float = 0.0) -> np.ndarray:
     """Viscosity ratio per site [nz, ny, nx] with one ratio per cell
     (mixtures of healthy and stiffened cells, Sec. 3.4): the ratio of the
     cell containing the site, the largest one where cells overlap, and 0
-    where no cell does.  X, origin: as for inside_sites."""
+    where no cell does.  X, origin, le_delta: as for inside_sites."""
     nx, ny, nz = dims
     r = np.zeros((nz, ny, nx))
     for c in range(np.asarray(X).shape[0]):
         m = inside_sites(np.asarray(X)[c:c + 1], tri, dims, bc,
-                         None if origin is None else np.asarray(origin)[c:c + 1])
+                         None if origin is None else np.asarray(origin)[c:c + 1], le_delta)
         r[m] = np.maximum(r[m], float(ratios[c]))
     return r
 

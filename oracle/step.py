@@ -82,7 +82,8 @@ def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 
     tau = m.tau
     ratios = np.broadcast_to(np.asarray(m.interior_ratio, dtype=np.float64), (C,))
     if C and np.any(ratios != 1.0):
-        tau = interior.tau_field(interior.ratio_field(X, m.topo.tri, m.dims, m.bc, ratios), m.tau)
+        tau = interior.tau_field(interior.ratio_field(X, m.topo.tri, m.dims, m.bc, ratios,
+                                                      le_delta=delta if le else 0.0), m.tau)
     post = lattice.collide(f, rho, u, F, tau)
     if le:
         f_new = lees_edwards.stream(post, m.le_u, delta)

@@ -128,3 +128,33 @@ def test_per_site_relaxation_conserves_mass_and_momentum():
     assert np.allclose(post.sum(axis=0), f.sum(axis=0), rtol=0, atol=1e-15)
     mom = lambda g: np.einsum("qd,q...->d...", e, g)
     assert np.allclose(mom(post) - mom(f), F, rtol=0, atol=1e-15)
+
+
+def test_sheared_images_marks():
+    """Lees-Edwards images (Sec. 2.5 reading): with no shift the marks are the
+    periodic ones; with an integer shift D the nodes that lie in the image
+    above (z wrapped from nz) are the periodic marks moved by -D along x,
+    and the nodes of the cell's own image are unchanged; float32 local
+    decisions agree with float64 positions for a fractional shift."""
+    rest, tri = rbc_mesh()
+    dims = (40, 28, 24)
+    X = (rest @ np.linalg.qr(np.random.default_rng(10).standard_normal((3, 3)))[0].T
+         + np.array([19.37, 13.81, 22.64]))[None]     # straddles z = nz
+    m0 = interior.inside_sites(X, tri, dims, (0, 0, 0))
+    assert np.array_equal(interior.inside_sites(X, tri, dims, (0, 0, 0), le_delta=0.0), m0)
+    D = 7
+    mD = interior.inside_sites(X, tri, dims, (0, 0, 0), le_delta=float(D))
+    zu = np.arange(int(np.ceil(X[0, :, 2].min())), int(np.floor(X[0, :, 2].max())) + 1)
+    above = np.unique(np.mod(zu[zu >= dims[2]], dims[2]))
+    below = np.unique(zu[zu < dims[2]])
+    assert above.size > 0 and below.size > 0 and not np.intersect1d(above, below).size
+    assert m0[above].sum() > 100
+    assert np.array_equal(mD[above], np.roll(m0[above], -D, axis=2))
+    assert np.array_equal(mD[below], m0[below])
+    # fractional shift: float32 local decisions equal float64 positions
+    origin = np.floor(X[0].mean(axis=0)).astype(np.int64)[None]
+    off32 = (X - origin[:, None, :]).astype(np.float32)
+    X64 = origin[:, None, :] + off32.astype(np.float64)
+    d = 5.37
+    assert np.array_equal(interior.inside_sites(off32, tri, dims, (0, 0, 0), origin=origin, le_delta=d),
+                          interior.inside_sites(X64, tri, dims, (0, 0, 0), le_delta=d))
