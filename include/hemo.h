@@ -214,9 +214,10 @@ hc_status hc_set_integration(hc_ctx* ctx, int32_t force_every, int32_t scheme);
  * from.  ratio > 0; 1 (the default) switches the marking off.  Limits per
  * cell: at most 320 node columns along x, bounding-box sides under 1024,
  * and 8 membrane crossings per column (hc_sync reports HC_ERR_UNSUPPORTED
- * beyond).  Not
- * combined with Lees-Edwards images or the adjoint calls
- * (HC_ERR_UNSUPPORTED). */
+ * beyond).  With Lees-Edwards images, a node in the image above or below
+ * is inside when the cell's copy displaced by -/+ the image shift contains
+ * it (the reading the IBM stencils follow).  Not combined with the adjoint
+ * calls (HC_ERR_UNSUPPORTED). */
 hc_status hc_set_interior_viscosity(hc_ctx* ctx, float ratio);
 
 /* One interior viscosity ratio per current cell, ratio [n_cells] (mixtures

@@ -898,8 +898,6 @@ hc_status hc_set_integration(hc_ctx* c, int32_t force_every, int32_t scheme) {
 hc_status hc_set_interior_viscosity(hc_ctx* c, float ratio) {
   if (!c) return HC_ERR_ARG;
   if (!std::isfinite(ratio) || !(ratio > 0.f)) return fail(c, HC_ERR_ARG, "ratio must be positive");
-  if (ratio != 1.f && c->L.le)
-    return fail(c, HC_ERR_UNSUPPORTED, "interior viscosity is not combined with Lees-Edwards images");
   if (ratio != 1.f && c->adj_ready)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
   c->uniform_ratio = ratio;
@@ -920,8 +918,6 @@ hc_status hc_set_cell_viscosity(hc_ctx* c, const float* ratio, int64_t n_cells) 
   if ((int)cls.size() > kVisClasses)
     return fail(c, HC_ERR_UNSUPPORTED, "more than 8 distinct interior viscosity ratios");
   const bool on = cls.size() > 1 || (!cls.empty() && cls[0] != 1.f);
-  if (on && c->L.le)
-    return fail(c, HC_ERR_UNSUPPORTED, "interior viscosity is not combined with Lees-Edwards images");
   if (on && c->adj_ready)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
   std::vector<uint8_t> k((size_t)n_cells);
@@ -940,6 +936,7 @@ hc_status hc_read_interior(hc_ctx* c, uint8_t* host, int64_t n_sites) {
   HC_TRY(need_ws(c));
   if (!host || n_sites != c->L.n) return fail(c, HC_ERR_ARG, "site count mismatch");
   HC_TRY(flush(c));
+  le_update(c);   // the image shift of the step about to run
   Cells C = c->C;
   C.n = c->have_cells ? c->C.n : 0;
   const Lattice& L = c->L;

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
   __shared__ int cnt[kMaxCols];
   __shared__ float zc[kMaxCols][kMaxCross];
   __shared__ float bb[kMarkThreads / kWave][6];
-  __shared__ int box[4];          // lo_x, lo_y, ncx, ncy (cell-local node coordinates)
+  __shared__ int box[6];          // lo_x, lo_y, ncx, ncy, lo_z, hi_z (cell-local nodes)
+  __shared__ float xr[2];         // the cell's x extent (cell-local)
   const int c = blockIdx.x, tid = threadIdx.x;
   if (only_class >= 0 && cls[c] != only_class) return;   // another class's pass
   const int64_t b3 = (int64_t)c * M.nv * 3;
@@ -89,100 +90,123 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
       box[1] = (int)ceilf(l[1]);
       box[2] = (int)floorf(h[0]) - box[0] + 1;
       box[3] = (int)floorf(h[1]) - box[1] + 1;
+      box[4] = (int)ceilf(l[2]);
+      box[5] = (int)floorf(h[2]);
+      xr[0] = l[0];
+      xr[1] = h[0];
     } else {   // non-finite positions (reported by the vertex move) or a cell far too large
       box[2] = box[3] = 0;
       if (sx >= kMaxSpan || sy >= kMaxSpan || sz >= kMaxSpan || !near) atomicOr(&flags[1], 16);
     }
   }
   __syncthreads();
-  const int lx = box[0], ly = box[1], ncx = box[2], ncy = box[3];
-  if (ncx <= 0 || ncy <= 0) return;
-  if (ncx > kMaxCols) {   // a cell wider than the column grid along x
-    if (tid == 0) atomicOr(&flags[1], 16);
-    return;
-  }
+  const int ly = box[1], ncy = box[3];
+  if (ncy <= 0 || (!L.le && box[2] <= 0)) return;
   const int ox = C.origin[3 * c], oy = C.origin[3 * c + 1], oz = C.origin[3 * c + 2];
   const unsigned bit = 1u << (cls ? cls[c] : 0);
-  // the columns in chunks of whole rows that fit the LDS grid (one chunk for
-  // an undeformed cell)
-  const int rows = kMaxCols / ncx;
-  for (int r0 = 0; r0 < ncy; r0 += rows) {
-    const int nr = min(rows, ncy - r0);
-    for (int i = tid; i < nr * ncx; i += kMarkThreads) cnt[i] = 0;
-    __syncthreads();
-    for (int t = tid; t < M.nt; t += kMarkThreads) {
-      const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-      float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
-      float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
-      float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
-      const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-      if (area2 == 0.f) continue;
-      if (area2 < 0.f) {   // orient counter-clockwise in projection
-        float tx = bx, ty = by, tz = bz;
-        bx = cx, by = cy, bz = cz;
-        cx = tx, cy = ty, cz = tz;
-      }
-      const float A = fabsf(area2);
-      const int x0 = max((int)ceilf(fminf(ax, fminf(bx, cx))), lx);
-      const int x1 = min((int)floorf(fmaxf(ax, fmaxf(bx, cx))), lx + ncx - 1);
-      const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly + r0);
-      const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + r0 + nr - 1);
-      for (int iy = y0; iy <= y1; ++iy)
-        for (int ix = x0; ix <= x1; ++ix) {
-          const float x = (float)ix, y = (float)iy;
-          if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
-                edge_in(cx, cy, ax, ay, x, y)))
-            continue;
-          const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
-          const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
-          const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
-          const float z = (wa * az + wb * bz + wc * cz) / A;
-          const int col = (iy - ly - r0) * ncx + (ix - lx);
-          const int slot = atomicAdd(&cnt[col], 1);
-          if (slot < kMaxCross) zc[col][slot] = z;
-          else atomicOr(&flags[1], 32);
-        }
+  // Sheared periodic images (gradient z, flow x): the nodes of image m,
+  // m = floor(unwrapped z / nz), are inside when the cell's copy displaced
+  // by -m Delta along x contains them, so their columns sit at cell-frame
+  // x + m Delta.  Without images there is one pass, m = 0, with integer
+  // columns.
+  int m_lo = 0, m_hi = 0;
+  if (L.le) {
+    m_lo = floor_div(oz + box[4], L.nz);
+    m_hi = floor_div(oz + box[5], L.nz);
+  }
+  for (int m = m_lo; m <= m_hi; ++m) {
+    const float shift = L.le ? (float)m * L.le_delta : 0.f;
+    // with a shift the column range is widened by one: columns outside the
+    // cell's projection cross nothing
+    const int lx = L.le ? (int)floorf(xr[0] - shift) : box[0];
+    const int ncx = L.le ? (int)floorf(xr[1] - shift) - lx + 2 : box[2];
+    if (ncx > kMaxCols) {   // a cell wider than the column grid along x
+      if (tid == 0) atomicOr(&flags[1], 16);
+      return;
     }
-    __syncthreads();
-    for (int col = tid; col < nr * ncx; col += kMarkThreads) {
-      const int n = min(cnt[col], kMaxCross);
-      if (n < 2) continue;
-      float z[kMaxCross];
-      for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
-      for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
-        for (int j = i; j > 0; --j)
-          if (z[j] < z[j - 1]) {
-            const float s = z[j];
-            z[j] = z[j - 1];
-            z[j - 1] = s;
+    // the columns in chunks of whole rows that fit the LDS grid (one chunk for
+    // an undeformed cell)
+    const int rows = kMaxCols / ncx;
+    for (int r0 = 0; r0 < ncy; r0 += rows) {
+      const int nr = min(rows, ncy - r0);
+      for (int i = tid; i < nr * ncx; i += kMarkThreads) cnt[i] = 0;
+      __syncthreads();
+      for (int t = tid; t < M.nt; t += kMarkThreads) {
+        const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+        float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
+        float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
+        float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
+        const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+        if (area2 == 0.f) continue;
+        if (area2 < 0.f) {   // orient counter-clockwise in projection
+          float tx = bx, ty = by, tz = bz;
+          bx = cx, by = cy, bz = cz;
+          cx = tx, cy = ty, cz = tz;
+        }
+        const float A = fabsf(area2);
+        const float tx0 = fminf(ax, fminf(bx, cx)), tx1 = fmaxf(ax, fmaxf(bx, cx));
+        const int x0 = max(L.le ? (int)floorf(tx0 - shift) : (int)ceilf(tx0), lx);
+        const int x1 = min(L.le ? (int)floorf(tx1 - shift) + 1 : (int)floorf(tx1), lx + ncx - 1);
+        const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly + r0);
+        const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + r0 + nr - 1);
+        for (int iy = y0; iy <= y1; ++iy)
+          for (int ix = x0; ix <= x1; ++ix) {
+            const float x = (float)ix + shift, y = (float)iy;
+            if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
+                  edge_in(cx, cy, ax, ay, x, y)))
+              continue;
+            const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
+            const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
+            const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
+            const float z = (wa * az + wb * bz + wc * cz) / A;
+            const int col = (iy - ly - r0) * ncx + (ix - lx);
+            const int slot = atomicAdd(&cnt[col], 1);
+            if (slot < kMaxCross) zc[col][slot] = z;
+            else atomicOr(&flags[1], 32);
           }
-      int xs = ox + lx + col % ncx, ys = oy + ly + r0 + col / ncx;
-      if (L.bc[0] == 1) {
-        if (xs < 0 || xs >= L.nx) continue;
-      } else {
-        xs = wrap(xs, L.nx);
       }
-      if (L.bc[1] == 1) {
-        if (ys < 0 || ys >= L.ny) continue;
-      } else {
-        ys = wrap(ys, L.ny);
-      }
-      for (int k = 0; k + 1 < n; k += 2) {
-        // the heights lie within the cell's bounded z extent
-        const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
-        for (int iz = z0; iz <= z1; ++iz) {
-          int zs = oz + iz;
-          if (L.bc[2] == 1) {
-            if (zs < 0 || zs >= L.nz) continue;
-          } else {
-            zs = wrap(zs, L.nz);
+      __syncthreads();
+      for (int col = tid; col < nr * ncx; col += kMarkThreads) {
+        const int n = min(cnt[col], kMaxCross);
+        if (n < 2) continue;
+        float z[kMaxCross];
+        for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
+        for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
+          for (int j = i; j > 0; --j)
+            if (z[j] < z[j - 1]) {
+              const float s = z[j];
+              z[j] = z[j - 1];
+              z[j - 1] = s;
+            }
+        int xs = ox + lx + col % ncx, ys = oy + ly + r0 + col / ncx;
+        if (L.bc[0] == 1) {
+          if (xs < 0 || xs >= L.nx) continue;
+        } else {
+          xs = wrap(xs, L.nx);
+        }
+        if (L.bc[1] == 1) {
+          if (ys < 0 || ys >= L.ny) continue;
+        } else {
+          ys = wrap(ys, L.ny);
+        }
+        for (int k = 0; k + 1 < n; k += 2) {
+          // the heights lie within the cell's bounded z extent
+          const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
+          for (int iz = z0; iz <= z1; ++iz) {
+            int zs = oz + iz;
+            if (L.le && floor_div(zs, L.nz) != m) continue;   // a node of another image
+            if (L.bc[2] == 1) {
+              if (zs < 0 || zs >= L.nz) continue;
+            } else {
+              zs = wrap(zs, L.nz);
+            }
+            const int64_t h = site_of(L, xs, ys, zs);
+            mask[h] = (unsigned char)bit;
           }
-          const int64_t h = site_of(L, xs, ys, zs);
-          mask[h] = (unsigned char)bit;
         }
       }
+      __syncthreads();   // the grid is reused by the next chunk
     }
-    __syncthreads();   // the grid is reused by the next chunk
   }
 }
 

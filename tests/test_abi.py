@@ -113,7 +113,7 @@ def test_settings_validate_without_a_device(lib, rbc):
     lib.hc_destroy(ctx)
     rc, ctx, _ = _create(lib, Lattice(32, 24, 16, tau=1.0, lees_edwards_u=0.02), rbc)
     assert rc == OK
-    assert lib.hc_set_interior_viscosity(ctx, 5.0) == UNSUPPORTED
+    assert lib.hc_set_interior_viscosity(ctx, 5.0) == OK    # combined with sheared images
     lib.hc_destroy(ctx)
 
 

@@ -181,12 +181,6 @@ def test_ratio_one_and_refusals():
     a.set_cell_viscosity([1.0])   # one ratio for the one cell: accepted (and off)
     with pytest.raises(HemoError, match="HC_ERR_ARG"):
         a.set_cell_viscosity([2.0, 3.0])   # two ratios for one cell
-    le = Lattice(24, 16, 16, tau=1.0, lees_edwards_u=0.01)
-    rest64, tri = rbc_mesh()
-    from paper_2305_02752_amd import Simulation
-    s = Simulation(le, rest64.astype(np.float32), tri, max_cells=1)
-    with pytest.raises(HemoError, match="HC_ERR_UNSUPPORTED"):
-        s.set_interior_viscosity(5.0)
 
 
 def test_too_many_classes_refused():
@@ -256,3 +250,75 @@ def test_marks_of_a_stretched_cell_in_row_chunks():
     ref = interior.inside_sites(off, tri, (40, 64, 24), lat.bc, origin=o)
     assert ref.sum() > 1000
     assert np.array_equal(dev, ref.astype(np.uint8))
+
+
+def _straddling_suspension(lat, seed, n=4):
+    rest64, tri = rbc_mesh()
+    rng = np.random.default_rng(seed)
+    cen = np.column_stack([rng.uniform(0, lat.nx, n), rng.uniform(0, lat.ny, n),
+                           np.where(np.arange(n) % 2 == 0, lat.nz - 0.7, 0.9) + rng.uniform(-0.4, 0.4, n)])
+    rots = np.stack([random_rotation(rng) for _ in range(n)])
+    k = np.ones((n, 4)) * 1e-3
+    cells = jitter_cells(rng, place_cells(rest64, cen, rots, k, traction=np.zeros((n, 3))), 0.04)
+    return rest64, tri, cells
+
+
+def test_marks_with_sheared_images():
+    """Lees-Edwards images: cells straddling z = 0 and z = nz are marked in
+    the image above or below through their copies displaced by the image
+    shift; bit-exact against the oracle's float32 local mode at the shift the
+    device uses (fractional after a few steps)."""
+    U = 0.037
+    lat = Lattice(48, 32, 40, tau=1.0, lees_edwards_u=U)
+    rest64, tri, cells = _straddling_suspension(lat, 54)
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri,
+                                   cells=cells), cells)
+    sim.init_equilibrium()
+    sim.set_interior_viscosity(5.0)
+    dims = (lat.nx, lat.ny, lat.nz)
+    for steps in (0, 7):
+        sim.step(steps)
+        dev = sim.read_interior()
+        o, off, _ = sim.read_vertices()
+        n = sim.steps_taken()
+        # the shift the device uses: U (float32) * n mod nx, in double, then float32
+        d = np.float32(np.fmod(np.fmod(float(np.float32(U)) * n, lat.nx) + lat.nx, lat.nx))
+        ref = interior.inside_sites(off, tri, dims, lat.bc, origin=o, le_delta=d)
+        periodic = interior.inside_sites(off, tri, dims, lat.bc, origin=o)
+        print("steps", n, "shift", d, "inside", int(ref.sum()), "differs from periodic",
+              int((ref != periodic).sum()), flush=True)
+        assert ref.sum() > 1000
+        if n > 0:
+            assert (ref != periodic).sum() > 50       # the images matter
+        assert np.array_equal(dev, ref.astype(np.uint8))
+
+
+def test_coupled_parity_sheared_images_with_interior_viscosity():
+    U = 0.03
+    lat = Lattice(40, 24, 32, tau=1.0, lees_edwards_u=U)
+    rest64, tri, cells = _straddling_suspension(lat, 55, n=3)
+    g0 = random_shifted_populations(np.random.default_rng(56), lat, 1e-3)
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri,
+                                   cells=cells), cells)
+    sim.write_populations(g0)
+    sim.set_interior_viscosity(4.0)
+    n = 6
+    sim.step(n)
+    sim.sync()
+    m = step.make_model(lat, rest64, tri, cells.k.astype(np.float64), cells.traction.astype(np.float64),
+                        le_u=U, interior_ratio=4.0)
+    f0, X0 = oracle_state(g0, cells)
+    f, X = step.run(m, f0, X0, n)
+    plain, _ = step.run(step.make_model(lat, rest64, tri, cells.k.astype(np.float64),
+                                        cells.traction.astype(np.float64), le_u=U), f0, X0, n)
+    o, off, _ = sim.read_vertices()
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    effect = relerr(lattice.shifted(plain), lattice.shifted(f))
+    Xg = o[:, None, :] + off.astype(np.float64)
+    bound = n * 6e-8 * np.abs(off).max() + TOL * np.abs(X - X0).max()
+    e_x = np.abs(Xg - X).max()
+    print("pops", e_g, "effect", effect, "position", e_x, "bound", bound, flush=True)
+    assert effect > 100 * TOL
+    assert e_g <= TOL and e_x <= bound

@@ -131,3 +131,38 @@ def test_refused_combinations():
     sim = _sim(lat, cells)
     with pytest.raises(HemoError):
         sim.adj_bind(10, 5)
+
+
+def test_suspension_across_both_boundaries():
+    """Eight cells, several straddling the sheared boundary at z = 0 and at
+    z = nz and one crossing the x wrap as well, on a box of several tiles per
+    axis: populations and positions after 6 steps, and the vertex velocity
+    of the last step, against the FP64 oracle."""
+    U = -0.025
+    lat = Lattice(48, 32, 40, tau=0.95, lees_edwards_u=U)
+    rest64, tri = rbc_mesh()
+    rng = np.random.default_rng(45)
+    cen = np.array([[10.3, 8.2, 0.6], [30.7, 20.4, 39.1], [47.6, 12.9, 1.4], [21.5, 27.3, 20.2],
+                    [5.2, 25.1, 38.3], [38.9, 5.6, 12.7], [16.4, 15.8, 29.5], [42.1, 28.4, 0.2]])
+    rots = np.stack([small_rotation(rng, 25.0) for _ in range(len(cen))])
+    k = K_REF[None] * 10.0 ** rng.uniform(-0.3, 0.3, (len(cen), 4))
+    cells = jitter_cells(rng, place_cells(rest64, cen, rots, k, traction=np.zeros((len(cen), 3))), 0.04)
+    g0 = random_shifted_populations(rng, lat, 1e-3)
+    sim = _sim(lat, cells)
+    sim.write_populations(g0)
+    n = 6
+    sim.step(n)
+    sim.sync()
+    m = _oracle(lat, rest64, tri, cells, U)
+    f, X = lattice.unshift(g0), cells.positions64()
+    X0 = X.copy()
+    for t in range(n):
+        f, X, info = step.step(m, f, X, t)
+    o, off, _ = sim.read_vertices()
+    Xg = o[:, None, :] + off.astype(np.float64)
+    e_g = relerr(sim.read_populations(), lattice.shifted(f))
+    e_u = relerr(sim.read_vertex_velocity(), info["U"])
+    bound = n * 6e-8 * np.abs(off).max() + 1e-4 * np.abs(X - X0).max()
+    print("8 cells, 6 steps", e_g, e_u, np.abs(Xg - X).max(), bound, flush=True)
+    assert e_g <= n * TOL_STEP and e_u <= n * TOL_STEP
+    assert np.abs(Xg - X).max() <= bound
