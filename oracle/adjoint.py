@@ -31,18 +31,21 @@ def loss_of(X, targets):
     return (da - targets[0]) ** 2 + (dt - targets[1]) ** 2
 
 
-def run_loss(lat, rest_pos, tri, X0, k, traction, tau, n, targets, f0=None):
-    """Loss after n oracle steps for one cell with stiffness k [4] and relaxation time tau."""
+def run_loss(lat, rest_pos, tri, X0, k, traction, tau, n, targets, f0=None, interior_ratio=1.0):
+    """Loss after n oracle steps for one cell with stiffness k [4] and
+    relaxation time tau (interior sites: tau_in = 1/2 + ratio (tau - 1/2))."""
     lat2 = dataclasses.replace(lat, tau=float(tau))
     m = step.make_model(lat2, np.asarray(rest_pos, dtype=np.float64), tri,
                         np.asarray(k, dtype=np.float64)[None],
-                        None if traction is None else np.asarray(traction, dtype=np.float64)[None])
+                        None if traction is None else np.asarray(traction, dtype=np.float64)[None],
+                        interior_ratio=interior_ratio)
     f = lattice.init_equilibrium(lat.shape) if f0 is None else f0
     f, X = step.run(m, f, np.asarray(X0, dtype=np.float64)[None], n)
     return loss_of(X[0], targets), X[0]
 
 
-def fd_gradient(lat, rest_pos, tri, X0, k, traction, tau, n, targets, eps=1e-4, f0=None):
+def fd_gradient(lat, rest_pos, tri, X0, k, traction, tau, n, targets, eps=1e-4, f0=None,
+                interior_ratio=1.0):
     """Central-difference gradient dL/d(k_link, k_bend, k_area, k_volume, tau)."""
     p = np.concatenate([np.asarray(k, dtype=np.float64), [float(tau)]])
     g = np.zeros(5)
@@ -52,6 +55,7 @@ def fd_gradient(lat, rest_pos, tri, X0, k, traction, tau, n, targets, eps=1e-4, 
         for sgn in (+1.0, -1.0):
             q = p.copy()
             q[j] += sgn * h
-            vals.append(run_loss(lat, rest_pos, tri, X0, q[:4], traction, q[4], n, targets, f0=f0)[0])
+            vals.append(run_loss(lat, rest_pos, tri, X0, q[:4], traction, q[4], n, targets, f0=f0,
+                                 interior_ratio=interior_ratio)[0])
         g[j] = (vals[0] - vals[1]) / (2 * h)
     return g

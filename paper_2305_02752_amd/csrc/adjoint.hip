@@ -15,7 +15,8 @@
 // Its transpose, given lam_h^{n+1} and lam_X^{n+1}, is evaluated by:
 //   spread of lam_U = lam_X^{n+1}        -> lam_u(x)        (k_spread, reused)
 //   k_adj_collide: the collision VJP at each node from its own lam_h^{n+1}
-//     -> lam_f, lam_F(x), and d/d omega partial sums; lam_f is then
+//     -> lam_f, lam_F(x), and d/d omega partial sums (kept apart for the
+//     sites inside cells, which relax at the interior rate); lam_f is then
 //     scattered back to the pull sources (a bijection) as lam_h^n;
 //   k_adj_vertex: lam_{F_v} = sum_x lam_F(x) delta, plus the kernel-gradient
 //     terms sum_x (lam_U.u(x) + F_v.lam_F(x)) grad delta for lam_X;
@@ -44,13 +45,27 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
                                                      const float* __restrict__ F,
                                                      const float* __restrict__ lamu,
                                                      float* __restrict__ lamF,
-                                                     double* __restrict__ domega_part, Lattice L) {
-  __shared__ double red[4];
+                                                     double* __restrict__ domega_part,
+                                                     unsigned char* __restrict__ mask,
+                                                     double* __restrict__ domega_in_part, Lattice L) {
+  __shared__ double red[2][4];
   const int64_t N = L.np;   // slots of every (tile-major) lattice field
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double dom = 0.0;
+  double dom = 0.0, dom_in = 0.0;
   int x, y, z;
   if (s < N && node_of(L, s, x, y, z)) {
+    // a site inside a cell relaxes with the interior rate (the marks of
+    // this step's positions, cleared once read)
+    float om = L.omega;
+    bool inside = false;
+    if (mask) {
+      const unsigned b = mask[s];
+      if (b) {
+        om = L.omega_in[31 - __clz(b)];
+        inside = true;
+        mask[s] = 0;
+      }
+    }
     // cotangent of the post-collision values stored at this node; a value
     // stored for a bounce-back carries the wall term c rho
     float ls[kQ];
@@ -80,7 +95,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     }
     const float rho = 1.f + drho, inv = 1.f / rho;
     const float ux = (jx + 0.5f * fx) * inv, uy = (jy + 0.5f * fy) * inv, uz = (jz + 0.5f * fz) * inv;
-    const float om = L.omega, src = 1.f - 0.5f * om;
+    const float src = 1.f - 0.5f * om;
     const float uu = ux * ux + uy * uy + uz * uz, uF = ux * fx + uy * fy + uz * fz;
     float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
 #pragma unroll
@@ -100,7 +115,9 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
       Gz += ls[j] * cs * (3.f * (cz[j] - uz) + 9.f * eu * cz[j]);
       const float geq = wq[j] * (drho + rho * (phi - 1.f));
       const float S = wq[j] * (3.f * (eF - uF) + 9.f * eu * eF);
-      dom += (double)(ls[j] * (-(g[j] - geq) - 0.5f * S));
+      const double d = (double)(ls[j] * (-(g[j] - geq) - 0.5f * S));
+      if (inside) dom_in += d;
+      else dom += d;
     }
     A = om * A + lrho;
     Bx += lamu[s];
@@ -114,13 +131,23 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     lamF[N + s] = Gy + 0.5f * By * inv;
     lamF[2 * N + s] = Gz + 0.5f * Bz * inv;
   }
-  for (int m = kWave / 2; m > 0; m >>= 1) dom += __shfl_xor(dom, m);
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = dom;
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    dom += __shfl_xor(dom, m);
+    dom_in += __shfl_xor(dom_in, m);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[0][threadIdx.x / kWave] = dom;
+    red[1][threadIdx.x / kWave] = dom_in;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
-    domega_part[blockIdx.x] += t;   // each block owns its slot across steps
+    double t = 0.0, ti = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      t += red[0][w];
+      ti += red[1][w];
+    }
+    domega_part[blockIdx.x] += t;   // each block owns its slots across steps
+    domega_in_part[blockIdx.x] += ti;
   }
 }
 
@@ -387,10 +414,10 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 }  // namespace
 
 hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
-                              const float* lamu, float* lamF, double* domega_part, const Lattice& L,
-                              hipStream_t s) {
+                              const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
+                              double* domega_in_part, const Lattice& L, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.np + 255) / 256)), dim3(256), 0, s, lam1, lam0,
-                     g0, F, lamu, lamF, domega_part, L);
+                     g0, F, lamu, lamF, domega_part, mask, domega_in_part, L);
   return hipGetLastError();
 }
 

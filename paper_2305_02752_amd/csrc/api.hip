@@ -91,6 +91,7 @@ struct hc_ctx {
   float *lam_f[2] = {nullptr, nullptr}, *lam_X[2] = {nullptr, nullptr};
   float *lam_Fv = nullptr, *lam_u = nullptr, *lam_F = nullptr, *vel_scratch = nullptr;
   double *dom_part = nullptr, *dk = nullptr, *loss = nullptr, *targets = nullptr, *scal = nullptr;
+  double* dom_in_part = nullptr;   // d/d omega_in partial sums (sites inside cells)
   // workspace offsets
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
@@ -304,7 +305,7 @@ hc_status run_steps(hc_ctx* c, int n) {
 struct AdjPlan {
   size_t total = 0;
   size_t ck_pops, ck_off, sg_pops, sg_off, sg_F, sg_macro, sg_Fv, lf0, lf1, lx0, lx1, lfv, lu, lF, vel,
-      dom, dk, loss, tg, scal;
+      dom, dom_in, dk, loss, tg, scal;
 };
 
 AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
@@ -328,6 +329,7 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   p.lF = L.add(3 * N * 4);
   p.vel = L.add(X * 4);
   p.dom = L.add(((N + 255) / 256) * 8);
+  p.dom_in = L.add(((N + 255) / 256) * 8);
   p.dk = L.add(C * 4 * 8);
   p.loss = L.add(C * 8);
   p.tg = L.add(C * 2 * 8);
@@ -353,8 +355,13 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev, true,
                                    false, c->stream),
                "cell step"));
+  unsigned char* mask = nullptr;
+  if (interior_on(c)) {   // the forward step's marks, from slot i's positions
+    mask = c->mask;
+    HC_TRY(check(c, mark_interior(c, Ci), "interior marking"));
+  }
   HC_TRY(check(c, launch_tile_step(Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
-                                   Fi, Mi, c->partial, true, nullptr, c->stream),
+                                   Fi, Mi, c->partial, true, mask, c->stream),
                "lattice pass"));
   return HC_OK;
 }
@@ -372,8 +379,13 @@ hc_status adj_reverse_step(hc_ctx* c, int i, int a) {
   float* lx0 = c->lam_X[a ^ 1];
   HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
   HC_TRY(check(c, launch_spread_vec(Ci, c->M, c->L, c->B, lx1, 0.f, c->lam_u, c->stream), "spread"));
+  unsigned char* mask = nullptr;
+  if (interior_on(c)) {   // the marks step i relaxed with (read and cleared by the collide VJP)
+    mask = c->mask;
+    HC_TRY(check(c, mark_interior(c, Ci), "interior marking"));
+  }
   HC_TRY(check(c, launch_adj_collide(lf1, lf0, c->sg_pops + i * P, c->sg_F + i * 3 * N, c->lam_u,
-                                     c->lam_F, c->dom_part, c->L, c->stream),
+                                     c->lam_F, c->dom_part, mask, c->dom_in_part, c->L, c->stream),
                "adjoint collide"));
   HC_TRY(check(c, launch_adj_vertex(Ci, c->M, c->L, lx1, c->sg_macro + i * N, c->lam_F, c->lam_Fv, lx0,
                                     c->stream),
@@ -898,8 +910,9 @@ hc_status hc_set_integration(hc_ctx* c, int32_t force_every, int32_t scheme) {
 hc_status hc_set_interior_viscosity(hc_ctx* c, float ratio) {
   if (!c) return HC_ERR_ARG;
   if (!std::isfinite(ratio) || !(ratio > 0.f)) return fail(c, HC_ERR_ARG, "ratio must be positive");
-  if (ratio != 1.f && c->adj_ready)
-    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
+  if (c->adj_ready && (ratio != c->uniform_ratio || c->per_cell_ratio))
+    return fail(c, HC_ERR_STATE, "the interior viscosity cannot change between hc_adj_forward and "
+                                 "hc_adj_backward (bind the adjoint workspace again)");
   c->uniform_ratio = ratio;
   interior_uniform(c);
   return HC_OK;
@@ -919,7 +932,7 @@ hc_status hc_set_cell_viscosity(hc_ctx* c, const float* ratio, int64_t n_cells) 
     return fail(c, HC_ERR_UNSUPPORTED, "more than 8 distinct interior viscosity ratios");
   const bool on = cls.size() > 1 || (!cls.empty() && cls[0] != 1.f);
   if (on && c->adj_ready)
-    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint covers one interior viscosity ratio for all cells");
   std::vector<uint8_t> k((size_t)n_cells);
   for (int64_t i = 0; i < n_cells; ++i)
     k[i] = (uint8_t)(std::lower_bound(cls.begin(), cls.end(), ratio[i]) - cls.begin());
@@ -986,8 +999,8 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   if (c->L.kernel != HC_PHI4)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
   if (c->L.le) return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover Lees-Edwards images");
-  if (interior_on(c))
-    return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover the interior viscosity");
+  if (c->n_vclass > 1)
+    return fail(c, HC_ERR_UNSUPPORTED, "adjoint covers one interior viscosity ratio for all cells");
   if (c->force_every != 1 || c->scheme != HC_EULER)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int ck = std::min(ckpt_every, n_steps);
@@ -1014,6 +1027,7 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   c->lam_F = reinterpret_cast<float*>(w + p.lF);
   c->vel_scratch = reinterpret_cast<float*>(w + p.vel);
   c->dom_part = reinterpret_cast<double*>(w + p.dom);
+  c->dom_in_part = reinterpret_cast<double*>(w + p.dom_in);
   c->dk = reinterpret_cast<double*>(w + p.dk);
   c->loss = reinterpret_cast<double*>(w + p.loss);
   c->targets = reinterpret_cast<double*>(w + p.tg);
@@ -1054,6 +1068,7 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_part, nblk, c->stream), "zero"));
+  HC_TRY(check(c, launch_zero_f64(c->dom_in_part, nblk, c->stream), "zero"));
   int a = 0;   // lam_f[a], lam_X[a] hold the cotangents of the later state
   for (int seg = c->adj_nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * c->adj_ck, len = std::min(c->adj_ck, c->adj_n - s0);
@@ -1066,15 +1081,18 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
     }
   }
   HC_TRY(check(c, launch_sum_parts(c->dom_part, nblk, c->scal, c->stream), "sum"));
+  HC_TRY(check(c, launch_sum_parts(c->dom_in_part, nblk, c->scal + 1, c->stream), "sum"));
   std::vector<double> dk((size_t)c->C.n * 4);
-  double dom = 0.0;
+  double dom[2] = {0.0, 0.0};
   HC_TRY(copy_d2h(c, dk.data(), c->dk, dk.size() * 8));
-  HC_TRY(copy_d2h(c, &dom, c->scal, 8));
+  HC_TRY(copy_d2h(c, dom, c->scal, 16));
   HC_TRY(sync(c, "adjoint backward"));
-  const double om = c->L.omega;
+  // tau = 1/omega outside the cells; inside, tau_in = 1/2 + ratio (tau - 1/2)
+  const double om = c->L.omega, om_in = c->L.omega_in[0], ratio = c->class_ratio[0];
+  const double dtau = -om * om * dom[0] - ratio * om_in * om_in * dom[1];
   for (int i = 0; i < c->C.n; ++i) {
     for (int j = 0; j < 4; ++j) grad[5 * i + j] = dk[4 * i + j];
-    grad[5 * i + 4] = -om * om * dom;   // tau = 1/omega
+    grad[5 * i + 4] = dtau;
   }
   return HC_OK;
 }

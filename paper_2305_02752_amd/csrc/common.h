@@ -148,8 +148,8 @@ hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, co
                              const float* vec, float body, float* F, hipStream_t s);
 // adjoint kernels
 hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
-                              const float* lamu, float* lamF, double* domega_part, const Lattice& L,
-                              hipStream_t s);
+                              const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
+                              double* domega_in_part, const Lattice& L, hipStream_t s);
 hipError_t launch_adj_vertex(const Cells& c, const Mesh& m, const Lattice& L, const float* lamX1,
                              const float4* macro, const float* lamF, float* lamFv, float* lamX0,
                              hipStream_t s);

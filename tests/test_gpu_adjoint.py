@@ -2,8 +2,10 @@
 
 Loss: (D_A - D_A*)^2 + (D_T - D_T*)^2 of one cell after n coupled steps in a
 sheared box with a pole traction.  Parameters p = (k_link, k_bend, k_area,
-k_volume, tau).  Bar: p . dL/dp normwise within 1e-4 of the FP64
-finite-difference gradient.
+k_volume, tau), also with an interior viscosity ratio (tau then also sets
+the interior relaxation time).  Bar: p . dL/dp normwise within 1e-4 of the
+FP64 finite-difference gradient; bit-identical gradients for any checkpoint
+interval.
 """
 import numpy as np
 import pytest
@@ -33,38 +35,43 @@ def _box(seed=0, side=20, walls=True):
     return lat, rest64.astype(np.float32), tri, cells, targets
 
 
-def _device_grad(lat, rest, tri, cells, targets, n, ck):
+def _device_grad(lat, rest, tri, cells, targets, n, ck, ratio=1.0):
     from types import SimpleNamespace
     sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest, tri=tri, cells=cells), cells)
     sim.init_equilibrium()
+    sim.set_interior_viscosity(ratio)
     sim.adj_bind(n, ck)
     loss = sim.adj_forward(targets)
     g = sim.adj_backward()
     return loss[0], g[0], sim
 
 
-@pytest.mark.parametrize("walls", [True, False])
-def test_adjoint_matches_fd(walls):
+@pytest.mark.parametrize("walls,ratio", [(True, 1.0), (False, 1.0), (True, 5.0)])
+def test_adjoint_matches_fd(walls, ratio):
     lat, rest, tri, cells, targets = _box(1 if walls else 2, walls=walls)
     n = 40
-    loss, g, _ = _device_grad(lat, rest, tri, cells, targets, n, 10)
+    loss, g, _ = _device_grad(lat, rest, tri, cells, targets, n, 10, ratio)
     X0 = cells.positions64()[0]
     k = cells.k[0].astype(np.float64)
-    L_ref, _ = oadj.run_loss(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets)
-    g_fd = oadj.fd_gradient(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets, eps=1e-4)
+    L_ref, _ = oadj.run_loss(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets,
+                             interior_ratio=ratio)
+    g_fd = oadj.fd_gradient(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets, eps=1e-4,
+                            interior_ratio=ratio)
     p = np.concatenate([k, [lat.tau]])
     pg, pf = p * g, p * g_fd
     comp = np.abs(pg - pf) / np.maximum(np.abs(pf), 1e-30)
     norm = np.linalg.norm(pg - pf) / np.linalg.norm(pf)
-    print(f"loss {loss:.8f} vs {L_ref:.8f}; p.g {pg}; fd {pf}; comp {comp}; norm {norm:.2e}", flush=True)
+    print(f"ratio {ratio}: loss {loss:.8f} vs {L_ref:.8f}; p.g {pg}; fd {pf}; comp {comp}; norm {norm:.2e}",
+          flush=True)
     assert abs(loss - L_ref) <= 1e-5 * abs(L_ref)
     assert norm <= 1e-4
 
 
-def test_adjoint_checkpoint_interval_is_exact():
+@pytest.mark.parametrize("ratio", [1.0, 5.0])
+def test_adjoint_checkpoint_interval_is_exact(ratio):
     lat, rest, tri, cells, targets = _box(3)
-    _, g1, _ = _device_grad(lat, rest, tri, cells, targets, 24, 24)
-    _, g2, _ = _device_grad(lat, rest, tri, cells, targets, 24, 5)
+    _, g1, _ = _device_grad(lat, rest, tri, cells, targets, 24, 24, ratio)
+    _, g2, _ = _device_grad(lat, rest, tri, cells, targets, 24, 5, ratio)
     assert np.array_equal(g1, g2)
 
 
