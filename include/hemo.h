@@ -216,10 +216,9 @@ hc_status hc_set_integration(hc_ctx* ctx, int32_t force_every, int32_t scheme);
  * and 8 membrane crossings per column (hc_sync reports HC_ERR_UNSUPPORTED
  * beyond).  With Lees-Edwards images, a node in the image above or below
  * is inside when the cell's copy displaced by -/+ the image shift contains
- * it (the reading the IBM stencils follow).  The adjoint calls cover one
- * ratio for all cells (d/d tau includes the interior sites through
- * tau_in); the ratio may not change between hc_adj_forward and
- * hc_adj_backward (HC_ERR_STATE). */
+ * it (the reading the IBM stencils follow).  The adjoint calls include the
+ * interior sites in d/d tau through tau_in; the ratios may not change
+ * between hc_adj_forward and hc_adj_backward (HC_ERR_STATE). */
 hc_status hc_set_interior_viscosity(hc_ctx* ctx, float ratio);
 
 /* One interior viscosity ratio per current cell, ratio [n_cells] (mixtures
@@ -337,8 +336,8 @@ hc_status hc_set_params(hc_ctx* ctx, const float* k, float tau);
  * column 4 dL/dtau, where L is the sum of all cells' losses (tau is shared
  * by the lattice; with an interior viscosity it includes the interior
  * sites through tau_in = 1/2 + ratio (tau - 1/2)).  Needs the 4-point
- * kernel, Euler moves with forces every step, no Lees-Edwards images and at
- * most one interior viscosity ratio (HC_ERR_UNSUPPORTED otherwise).  The
+ * kernel, Euler moves with forces every step and no Lees-Edwards images
+ * (HC_ERR_UNSUPPORTED otherwise).  The
  * adjoint workspace is separate from the main one and sized by
  * hc_adj_query_workspace.
  * ------------------------------------------------------------------------- */

@@ -48,10 +48,11 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
                                                      double* __restrict__ domega_part,
                                                      unsigned char* __restrict__ mask,
                                                      double* __restrict__ domega_in_part, Lattice L) {
-  __shared__ double red[2][4];
+  __shared__ double red[1 + kVisClasses][4];
   const int64_t N = L.np;   // slots of every (tile-major) lattice field
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double dom = 0.0, dom_in = 0.0;
+  int cls = -1;   // viscosity class of an interior site
   int x, y, z;
   if (s < N && node_of(L, s, x, y, z)) {
     // a site inside a cell relaxes with the interior rate (the marks of
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     if (mask) {
       const unsigned b = mask[s];
       if (b) {
-        om = L.omega_in[31 - __clz(b)];
+        cls = 31 - __clz(b);
+        om = L.omega_in[cls];
         inside = true;
         mask[s] = 0;
       }
@@ -131,23 +133,21 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     lamF[N + s] = Gy + 0.5f * By * inv;
     lamF[2 * N + s] = Gz + 0.5f * Bz * inv;
   }
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    dom += __shfl_xor(dom, m);
-    dom_in += __shfl_xor(dom_in, m);
-  }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    red[0][threadIdx.x / kWave] = dom;
-    red[1][threadIdx.x / kWave] = dom_in;
+  // per-block sums for the plasma sites and for each viscosity class, in a
+  // fixed order (each block owns its slots across steps)
+  for (int k = -1; k < kVisClasses; ++k) {
+    double v = k < 0 ? dom : (cls == k ? dom_in : 0.0);
+    for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[k + 1][threadIdx.x / kWave] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0, ti = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-      t += red[0][w];
-      ti += red[1][w];
-    }
-    domega_part[blockIdx.x] += t;   // each block owns its slots across steps
-    domega_in_part[blockIdx.x] += ti;
+  if (threadIdx.x < 1 + kVisClasses) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[threadIdx.x][w];
+    if (threadIdx.x == 0)
+      domega_part[blockIdx.x] += t;
+    else
+      domega_in_part[(int64_t)(threadIdx.x - 1) * gridDim.x + blockIdx.x] += t;
   }
 }
 

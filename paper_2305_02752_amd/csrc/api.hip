@@ -329,11 +329,11 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   p.lF = L.add(3 * N * 4);
   p.vel = L.add(X * 4);
   p.dom = L.add(((N + 255) / 256) * 8);
-  p.dom_in = L.add(((N + 255) / 256) * 8);
+  p.dom_in = L.add(kVisClasses * ((N + 255) / 256) * 8);
   p.dk = L.add(C * 4 * 8);
   p.loss = L.add(C * 8);
   p.tg = L.add(C * 2 * 8);
-  p.scal = L.add(64);
+  p.scal = L.add(128);   // d/d omega sums (plasma + 8 classes) and scalars
   p.total = L.total;
   return p;
 }
@@ -931,8 +931,9 @@ hc_status hc_set_cell_viscosity(hc_ctx* c, const float* ratio, int64_t n_cells) 
   if ((int)cls.size() > kVisClasses)
     return fail(c, HC_ERR_UNSUPPORTED, "more than 8 distinct interior viscosity ratios");
   const bool on = cls.size() > 1 || (!cls.empty() && cls[0] != 1.f);
-  if (on && c->adj_ready)
-    return fail(c, HC_ERR_UNSUPPORTED, "adjoint covers one interior viscosity ratio for all cells");
+  if (c->adj_ready)
+    return fail(c, HC_ERR_STATE, "the interior viscosity cannot change between hc_adj_forward and "
+                                 "hc_adj_backward (bind the adjoint workspace again)");
   std::vector<uint8_t> k((size_t)n_cells);
   for (int64_t i = 0; i < n_cells; ++i)
     k[i] = (uint8_t)(std::lower_bound(cls.begin(), cls.end(), ratio[i]) - cls.begin());
@@ -999,8 +1000,6 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   if (c->L.kernel != HC_PHI4)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint needs the differentiable 4-point kernel");
   if (c->L.le) return fail(c, HC_ERR_UNSUPPORTED, "adjoint does not cover Lees-Edwards images");
-  if (c->n_vclass > 1)
-    return fail(c, HC_ERR_UNSUPPORTED, "adjoint covers one interior viscosity ratio for all cells");
   if (c->force_every != 1 || c->scheme != HC_EULER)
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int ck = std::min(ckpt_every, n_steps);
@@ -1068,7 +1067,7 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_part, nblk, c->stream), "zero"));
-  HC_TRY(check(c, launch_zero_f64(c->dom_in_part, nblk, c->stream), "zero"));
+  HC_TRY(check(c, launch_zero_f64(c->dom_in_part, (int64_t)kVisClasses * nblk, c->stream), "zero"));
   int a = 0;   // lam_f[a], lam_X[a] hold the cotangents of the later state
   for (int seg = c->adj_nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * c->adj_ck, len = std::min(c->adj_ck, c->adj_n - s0);
@@ -1081,15 +1080,22 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
     }
   }
   HC_TRY(check(c, launch_sum_parts(c->dom_part, nblk, c->scal, c->stream), "sum"));
-  HC_TRY(check(c, launch_sum_parts(c->dom_in_part, nblk, c->scal + 1, c->stream), "sum"));
+  for (int k = 0; k < kVisClasses; ++k)
+    HC_TRY(check(c, launch_sum_parts(c->dom_in_part + (int64_t)k * nblk, nblk, c->scal + 1 + k, c->stream),
+                 "sum"));
   std::vector<double> dk((size_t)c->C.n * 4);
-  double dom[2] = {0.0, 0.0};
+  double dom[1 + kVisClasses] = {};
   HC_TRY(copy_d2h(c, dk.data(), c->dk, dk.size() * 8));
-  HC_TRY(copy_d2h(c, dom, c->scal, 16));
+  HC_TRY(copy_d2h(c, dom, c->scal, sizeof(dom)));
   HC_TRY(sync(c, "adjoint backward"));
-  // tau = 1/omega outside the cells; inside, tau_in = 1/2 + ratio (tau - 1/2)
-  const double om = c->L.omega, om_in = c->L.omega_in[0], ratio = c->class_ratio[0];
-  const double dtau = -om * om * dom[0] - ratio * om_in * om_in * dom[1];
+  // tau = 1/omega outside the cells; inside a cell of class k,
+  // tau_k = 1/2 + ratio_k (tau - 1/2)
+  const double om = c->L.omega;
+  double dtau = -om * om * dom[0];
+  for (int k = 0; k < c->n_vclass; ++k) {
+    const double ok = c->L.omega_in[k];
+    dtau -= (double)c->class_ratio[k] * ok * ok * dom[1 + k];
+  }
   for (int i = 0; i < c->C.n; ++i) {
     for (int j = 0; j < 4; ++j) grad[5 * i + j] = dk[4 * i + j];
     grad[5 * i + 4] = dtau;

@@ -89,3 +89,58 @@ def test_coupled_step_fn_autograd():
         _, g, _ = _device_grad(boxes[b][0], boxes[b][1], boxes[b][2], boxes[b][3], boxes[b][4], 20, 5)
         w = [1.0, 2.0, -0.5][b]
         assert np.allclose(params.grad[b].numpy(), w * g, rtol=1e-12, atol=0)
+
+
+def test_adjoint_with_per_cell_interior_ratios():
+    """Two cells with different interior viscosity ratios (two classes):
+    dL/dtau, which reaches the interior sites of each class through its own
+    tau_k, and dL/dk_link of each cell against FP64 central differences of
+    the summed loss."""
+    import dataclasses
+
+    from oracle import lattice as olat, step as ostep
+    rng = np.random.default_rng(60)
+    rest64, tri = rbc_mesh()
+    lat = Lattice(40, 24, 24, bc=(0, 0, 1), tau=0.95, wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
+    k = K_REF * 10.0 ** rng.uniform(-0.3, 0.3, (2, 4))
+    cells = place_cells(rest64, np.array([[10.6, 11.7, 11.4], [29.3, 12.2, 11.6]]),
+                        np.stack([small_rotation(rng, 5.0) for _ in range(2)]), k,
+                        traction=[[3e-3, 0.0, 0.0], [-2e-3, 0.0, 0.0]])
+    targets = np.array([[16.0 * 1.2, 16.0 * 0.9], [16.0 * 1.1, 16.0 * 0.95]])
+    ratios = np.array([3.0, 6.0])
+    n = 24
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri, cells=cells),
+                   cells)
+    sim.init_equilibrium()
+    sim.set_cell_viscosity(ratios)
+    sim.adj_bind(n, 8)
+    loss = sim.adj_forward(targets.reshape(-1))
+    g = sim.adj_backward()
+
+    X0 = cells.positions64()
+    kk = cells.k.astype(np.float64)
+    tr = cells.traction.astype(np.float64)
+
+    def total_loss(tau, kmat):
+        m = ostep.make_model(dataclasses.replace(lat, tau=float(tau)), rest64, tri, kmat, tr,
+                             interior_ratio=ratios)
+        _, X = ostep.run(m, olat.init_equilibrium(lat.shape), X0, n)
+        return sum(oadj.loss_of(X[c], targets[c]) for c in range(2))
+
+    assert abs(loss.sum() - total_loss(lat.tau, kk)) <= 1e-5 * abs(loss.sum())
+    h = 1e-4 * lat.tau
+    fd_tau = (total_loss(lat.tau + h, kk) - total_loss(lat.tau - h, kk)) / (2 * h)
+    fd_k = []
+    for c in range(2):
+        hk = 1e-4 * kk[c, 0]
+        kp, km = kk.copy(), kk.copy()
+        kp[c, 0] += hk
+        km[c, 0] -= hk
+        fd_k.append((total_loss(lat.tau, kp) - total_loss(lat.tau, km)) / (2 * hk))
+    pg = np.array([lat.tau * g[0, 4], kk[0, 0] * g[0, 0], kk[1, 0] * g[1, 0]])
+    pf = np.array([lat.tau * fd_tau, kk[0, 0] * fd_k[0], kk[1, 0] * fd_k[1]])
+    norm = np.linalg.norm(pg - pf) / np.linalg.norm(pf)
+    print("p.g", pg, "fd", pf, "norm", norm, flush=True)
+    assert np.allclose(g[:, 4], g[0, 4])       # tau is shared
+    assert norm <= 1e-4
