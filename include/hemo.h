@@ -378,6 +378,14 @@ hc_status hc_batch_query_workspace(const hc_batch* b, size_t* bytes);
 hc_status hc_batch_bind_workspace(hc_batch* b, void* dev_ptr, size_t bytes);
 hc_status hc_batch_set_cells(hc_batch* b, const int32_t* origin, const float* offsets,
                              const float* k, const float* traction);
+/* Interior viscosity per box (Sec. 1: cytosol five times more viscous than
+ * plasma; Sec. 3.4: the internal ratio of stiffened cells): ratio [n_boxes]
+ * host floats, finite and > 0; nodes inside box i's cell relax with
+ * tau_in = 1/2 + ratio[i] (tau_i - 1/2), as hc_set_interior_viscosity does
+ * for a single lattice (same inside test and limits; a cell beyond them
+ * surfaces at hc_batch_sync as HC_ERR_UNSUPPORTED).  A ratio of 1 switches
+ * the box's marking off.  HC_ERR_STATE before a workspace is bound. */
+hc_status hc_batch_set_interior_viscosity(hc_batch* b, const float* ratio);
 hc_status hc_batch_set_tiling(hc_batch* b, int32_t ty, int32_t tz, int32_t block);
 hc_status hc_batch_get_tiling(const hc_batch* b, int32_t* ty, int32_t* tz, int32_t* block,
                               int32_t* grid);

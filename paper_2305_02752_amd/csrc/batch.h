@@ -10,8 +10,10 @@ struct BoxDesc {
   int bc[3];
   int ty, tz, nty, ntz;     // tile = all x, ty rows in y, tz rows in z
   float omega;
+  float omega_in;           // relaxation rate inside the cell (omega when the ratio is 1)
   float g[3], ulo[3], uhi[3];
   long long pop_off;        // float offset of the box in a population buffer
+  long long site_off;       // offset of the box's first node among all boxes' nodes
   long long n;              // nodes
 };
 
@@ -35,7 +37,9 @@ struct Batch {
   const int4* wg;           // per work-group: box (-1 idle), rank, members
   int* bar;                 // [nbox] barrier counters, zeroed before a launch
   int* box_step;            // [nbox] steps taken
-  int* flags;               // [0] non-finite position, [1] barrier abort
+  unsigned char* mask;      // [all nodes] 1 inside the box's cell (set and cleared each step)
+  int interior;             // some box has omega_in != omega
+  int* flags;               // [0] non-finite position, [1] barrier abort, [2] marking limits
   int spin_limit;
   int tile_cap;             // largest tile in nodes
 };

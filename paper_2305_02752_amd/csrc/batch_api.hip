@@ -54,7 +54,7 @@ struct hc_batch {
   std::string err;
   size_t o_pop0, o_pop1, o_snap_pop, o_box, o_tri, o_edge, o_L0, o_hv, o_th0, o_pole, o_origin,
       o_off, o_force, o_vel, o_snap_off, o_k, o_trac, o_area, o_vol, o_uacc, o_bbox, o_wg, o_bar,
-      o_step, o_snap_step, o_flags;
+      o_step, o_snap_step, o_flags, o_mask;
 };
 
 namespace {
@@ -108,6 +108,7 @@ void plan(hc_batch* b, Lay& L) {
   b->o_step = L.add(B * 4);
   b->o_snap_step = L.add(B * 4);
   b->o_flags = L.add(16);
+  b->o_mask = L.add(b->sites);
 }
 
 hc_status bsync(hc_batch* b) { return bcheck(b, hipStreamSynchronize(b->stream), "sync"); }
@@ -300,8 +301,10 @@ hc_status hc_batch_create(int32_t n_boxes, const hc_lattice_desc* boxes, const h
       B.uhi[a] = d.wall_u_hi[a];
     }
     B.omega = 1.0f / d.tau;
+    B.omega_in = B.omega;
     B.n = (int64_t)d.nx * d.ny * d.nz;
     B.pop_off = 19 * b->sites;
+    B.site_off = b->sites;
     b->sites += B.n;
     b->box.push_back(B);
     b->lat.push_back(d);
@@ -374,6 +377,9 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   V.bar = bat<int>(b, b->o_bar);
   V.box_step = bat<int>(b, b->o_step);
   V.flags = bat<int>(b, b->o_flags);
+  V.mask = bat<unsigned char>(b, b->o_mask);
+  V.interior = 0;
+  for (auto& B : b->box) V.interior |= B.omega_in != B.omega;
   V.spin_limit = kSpinLimit;
   HB_TRY(h2d(b, (void*)V.M.tri, m.tri.data(), m.tri.size() * 4));
   HB_TRY(h2d(b, (void*)V.M.edge, m.edge.data(), m.edge.size() * 4));
@@ -383,6 +389,8 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   HB_TRY(h2d(b, (void*)V.M.pole, m.pole.data(), m.pole.size() * 4));
   HB_TRY(bcheck(b, launch_fill_i32(V.box_step, 0, b->nbox, b->stream), "clear"));
   HB_TRY(bcheck(b, launch_fill_i32(V.flags, 0, 4, b->stream), "clear"));
+  HB_TRY(bcheck(b, launch_fill_i32(reinterpret_cast<int*>(V.mask), 0, (b->sites + 3) / 4, b->stream),
+                "clear"));
   HB_TRY(bcheck(b, launch_fill_i32(reinterpret_cast<int*>(V.uacc), 0,
                                    (int64_t)b->nbox * m.nv * 6, b->stream),
                 "clear"));
@@ -409,6 +417,25 @@ hc_status hc_batch_set_cells(hc_batch* b, const int32_t* origin, const float* of
     b->V.trac = nullptr;
   }
   b->V.has_cells = 1;
+  drop_graph(b);
+  return bsync(b);
+}
+
+hc_status hc_batch_set_interior_viscosity(hc_batch* b, const float* ratio) {
+  if (!b || !b->ws) return bfail(b, HC_ERR_STATE, "no workspace bound");
+  if (!ratio) return bfail(b, HC_ERR_ARG, "null ratio array");
+  for (int i = 0; i < b->nbox; ++i)
+    if (!(ratio[i] > 0.f) || !std::isfinite(ratio[i]))
+      return bfail(b, HC_ERR_ARG, "box " + std::to_string(i) + ": ratio must be finite and > 0");
+  int any = 0;
+  for (int i = 0; i < b->nbox; ++i) {
+    BoxDesc& B = b->box[i];
+    const double tau = b->lat[i].tau;
+    B.omega_in = (float)(1.0 / (0.5 + (double)ratio[i] * (tau - 0.5)));
+    any |= B.omega_in != B.omega;
+  }
+  b->V.interior = any;
+  HB_TRY(h2d(b, bat<void>(b, b->o_box), b->box.data(), b->box.size() * sizeof(BoxDesc)));
   drop_graph(b);
   return bsync(b);
 }
@@ -457,10 +484,14 @@ hc_status hc_batch_sync(hc_batch* b) {
   int f[4];
   HB_TRY(d2h(b, f, b->V.flags, 16));
   HB_TRY(bsync(b));
-  if (f[0] || f[1]) {
+  if (f[0] || f[1] || f[2]) {
     HB_TRY(bcheck(b, launch_fill_i32(b->V.flags, 0, 4, b->stream), "clear"));
     HB_TRY(bsync(b));
     if (f[1]) return bfail(b, HC_ERR_DEVICE, "group barrier timed out (work-groups not co-resident)");
+    if (f[2] & 16)
+      return bfail(b, HC_ERR_UNSUPPORTED, "interior marking: a cell wider than 320 columns or 1024 nodes");
+    if (f[2] & 32)
+      return bfail(b, HC_ERR_UNSUPPORTED, "interior marking: more than 8 membrane crossings on a column");
     return bfail(b, HC_ERR_NONFINITE, "non-finite vertex position");
   }
   return HC_OK;

@@ -5,12 +5,14 @@
 // work-groups sized in proportion to its lattice; all members of a group
 // sit on the same XCD (block ids congruent modulo 8), so their data shares
 // one L2.  Per step, inside the group:
-//   rank 0:      membrane forces of the box's cell (Sec. 2.3 force sum) and
-//                the node range its IBM stencil can reach;
+//   rank 0:      membrane forces of the box's cell (Sec. 2.3 force sum),
+//                the node range its IBM stencil can reach and, with an
+//                interior viscosity, the marks of the nodes inside the cell;
 //   -- group barrier --
 //   all ranks:   for each of their tiles (full x rows, ty x tz rows):
 //                spread the vertex forces onto the tile in LDS (2^-40 fixed
-//                point), BGK+Guo collide and stream every node (Sec. 2.2),
+//                point), BGK+Guo collide (the interior rate at marked
+//                nodes, clearing the mark) and stream every node (Sec. 2.2),
 //                and add the tile's share of every vertex velocity
 //                (Sec. 2.3 interpolation) to a fixed-point accumulator;
 //   -- group barrier --
@@ -21,6 +23,7 @@
 // Each box carries its own step counter, which fixes the parity of its
 // population buffers; the launch therefore replays unchanged from a graph.
 #include "batch.h"
+#include "interior_dev.h"
 #include "lbm_dev.h"
 #include "membrane_dev.h"
 #include "stencil.h"
@@ -121,6 +124,24 @@ __device__ inline void cell_reach(const Batch& V, int box, int K, const float* o
   __syncthreads();
 }
 
+// Marks the nodes inside the box's cell (positions staged in sp by the
+// membrane phase) for the interior relaxation rate.
+__device__ inline void box_mark(const Batch& V, const BoxDesc& B, const float* sp, const int (&o3)[3],
+                                inside::Lds& S, int tid, int nthr) {
+  if (!V.interior || B.omega_in == B.omega) return;
+  inside::Grid G;
+  G.n[0] = B.nx;
+  G.n[1] = B.ny;
+  G.n[2] = B.nz;
+  for (int d = 0; d < 3; ++d) G.bc[d] = B.bc[d];
+  G.le = 0;
+  G.le_delta = 0.f;
+  const long long nx = B.nx, ny = B.ny;
+  inside::mark_cell(sp, V.M.nv, V.M.tri, V.M.nt, o3, G,
+                    [=](int x, int y, int z) { return ((int64_t)z * ny + y) * nx + x; },
+                    V.mask + B.site_off, (unsigned char)1, V.flags + 2, S, tid, nthr);
+}
+
 // Integer test: does the K-node stencil starting at node `base` meet rows [a, a + h)?
 template <int K>
 __device__ inline bool stencil_meets(int base, int a, int h, int n, bool wall) {
@@ -198,8 +219,16 @@ __device__ void box_tile(const Batch& V, const BoxDesc& B, int box, int t, const
       fy += (float)((double)facc[3 * i + 1] * kFixInv);
       fz += (float)((double)facc[3 * i + 2] * kFixInv);
     }
+    float om = B.omega;
+    if (V.interior) {
+      unsigned char* mk = V.mask + B.site_off + s;
+      if (*mk) {
+        om = B.omega_in;
+        *mk = 0;
+      }
+    }
     float rho, ux, uy, uz;
-    lbm::collide(g, fx, fy, fz, B.omega, rho, ux, uy, uz);
+    lbm::collide(g, fx, fy, fz, om, rho, ux, uy, uz);
     if (near) su[i] = make_float4(ux, uy, uz, rho);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -317,6 +346,10 @@ __global__ void k_batch(Batch V, int nsteps) {
   float* sp = reinterpret_cast<float*>(lds + (size_t)nv * 3 * 8);
   long long* facc = reinterpret_cast<long long*>(lds);
   float4* su = reinterpret_cast<float4*>(lds + (size_t)V.tile_cap * 24);
+  // marking scratch: over acc (free once the forces are out) when it fits,
+  // else after sp
+  inside::Lds& ms = *reinterpret_cast<inside::Lds*>(
+      lds + ((size_t)nv * 24 >= sizeof(inside::Lds) ? 0 : (size_t)nv * 36));
   int epoch = 0;
   const int parity0 = V.box_step[box] & 1;
   int* ctr = V.bar + box;
@@ -325,6 +358,7 @@ __global__ void k_batch(Batch V, int nsteps) {
     mem::membrane_cell(V.M, off, V.k + 4 * box, V.trac ? V.trac + 3 * box : nullptr, force,
                        V.area + box, V.volume + box, acc, sp, red, tid, nthr);
     cell_reach(V, box, K, off, o3, fred, tid, nthr);
+    box_mark(V, B, sp, o3, ms, tid, nthr);
   }
   if (!group_barrier(ctr, members, epoch, V.flags + 1, V.spin_limit, &s_ok)) return;
   const int ntiles = B.nty * B.ntz;
@@ -341,6 +375,7 @@ __global__ void k_batch(Batch V, int nsteps) {
         mem::membrane_cell(V.M, off, V.k + 4 * box, V.trac ? V.trac + 3 * box : nullptr, force,
                            V.area + box, V.volume + box, acc, sp, red, tid, nthr);
         cell_reach(V, box, K, off, o3, fred, tid, nthr);
+        box_mark(V, B, sp, o3, ms, tid, nthr);
       }
     }
     if (!group_barrier(ctr, members, epoch, V.flags + 1, V.spin_limit, &s_ok)) return;
@@ -351,7 +386,8 @@ __global__ void k_batch(Batch V, int nsteps) {
 }  // namespace
 
 size_t batch_lds_bytes(int nv, int tile_cap) {
-  const size_t mem = (size_t)nv * 3 * (8 + 4);
+  size_t mem = (size_t)nv * 3 * (8 + 4);
+  if ((size_t)nv * 24 < sizeof(inside::Lds)) mem += sizeof(inside::Lds);
   const size_t tile = (size_t)tile_cap * (24 + 16);
   return mem > tile ? mem : tile;
 }

@@ -1,213 +1,38 @@
-// Lattice sites inside the cells, for the interior viscosity (Sec. 1: the
-// cytosol is five times more viscous than plasma; Sec. 3.4: stiffened cells
-// scale the internal viscosity ratio).  A site is inside a cell by ray
-// parity along z: the vertical line through the site's (x, y) crosses the
-// closed membrane at heights z_1 < z_2 < ..., and the site is inside when
-// it lies strictly between z_(2k-1) and z_(2k).
-//
-// One work-group per cell.  The cell's (x, y) node columns within its
-// bounding box form a small grid, held in LDS in chunks of whole rows of at
-// most kMaxCols columns (one chunk for an undeformed cell); every triangle
-// adds its crossing height to each column its projection covers (edge points are
-// kept by exactly one of the two triangles sharing the edge: after orienting
-// the triangle counter-clockwise in projection, edge P -> Q keeps them when
-// Q.y > P.y, or Q.y == P.y and Q.x < P.x); each column then sorts its
-// crossings and marks the nodes between pairs.  The marks are bytes in the
-// site-ordered mask as one bit for the viscosity class (cells of different
+// Marking of the lattice sites inside the cells for the interior viscosity
+// (Sec. 1, Sec. 3.4): one work-group per cell runs inside::mark_cell, which
+// states the ray-parity rule.  The marks are bytes in the site-ordered
+// mask: 1 << k for a cell of viscosity class k (cells of different
 // stiffness may carry different interior viscosities, Sec. 3.4), which the
 // lattice pass reads (and clears) to pick the relaxation time.
-#include "common.h"
-#include "stencil.h"
+#include "interior_dev.h"
 
 namespace hc {
 namespace {
 
 constexpr int kMarkThreads = 256;
-constexpr int kMaxCols = 320;    // (x, y) columns held in LDS at once (whole rows)
-constexpr int kMaxCross = 8;     // crossings per column
-constexpr float kMaxSpan = 1024.f;   // bounding-box side beyond which a cell is refused
-constexpr float kMaxOff = 16777216.f;   // offsets from the cell origin beyond which it is refused
-
-// The edge tests and crossing heights are evaluated without contraction to
-// fused multiply-adds, so every decision is the one plain float32 arithmetic
-// (each product and sum rounded) takes.
-#pragma clang fp contract(off)
-
-__device__ inline bool edge_in(float px, float py, float qx, float qy, float x, float y) {
-  const float w = (qx - px) * (y - py) - (qy - py) * (x - px);
-  const bool keep = qy > py || (qy == py && qx < px);
-  return w > 0.f || (w == 0.f && keep);
-}
 
 __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M, Lattice L,
                                                                 unsigned char* __restrict__ mask,
                                                                 const unsigned char* __restrict__ cls,
                                                                 int only_class, int* __restrict__ flags) {
   extern __shared__ float sp[];   // [nv][3] offsets
-  __shared__ int cnt[kMaxCols];
-  __shared__ float zc[kMaxCols][kMaxCross];
-  __shared__ float bb[kMarkThreads / kWave][6];
-  __shared__ int box[6];          // lo_x, lo_y, ncx, ncy, lo_z, hi_z (cell-local nodes)
-  __shared__ float xr[2];         // the cell's x extent (cell-local)
+  __shared__ inside::Lds S;
   const int c = blockIdx.x, tid = threadIdx.x;
   if (only_class >= 0 && cls[c] != only_class) return;   // another class's pass
   const int64_t b3 = (int64_t)c * M.nv * 3;
-  float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
-  for (int v = tid; v < M.nv; v += kMarkThreads) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float p = C.off[b3 + 3 * v + d];
-      sp[3 * v + d] = p;
-      lo[d] = fminf(lo[d], p);
-      hi[d] = fmaxf(hi[d], p);
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    for (int m = kWave / 2; m > 0; m >>= 1) {
-      lo[d] = fminf(lo[d], __shfl_xor(lo[d], m));
-      hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], m));
-    }
-  if ((tid & (kWave - 1)) == 0)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      bb[tid / kWave][d] = lo[d];
-      bb[tid / kWave][3 + d] = hi[d];
-    }
+  for (int i = tid; i < 3 * M.nv; i += kMarkThreads) sp[i] = C.off[b3 + i];
   __syncthreads();
-  if (tid == 0) {
-    float l[3] = {bb[0][0], bb[0][1], bb[0][2]}, h[3] = {bb[0][3], bb[0][4], bb[0][5]};
-    for (int w = 1; w < kMarkThreads / kWave; ++w)
-      for (int d = 0; d < 3; ++d) {
-        l[d] = fminf(l[d], bb[w][d]);
-        h[d] = fmaxf(h[d], bb[w][3 + d]);
-      }
-    const float sx = h[0] - l[0], sy = h[1] - l[1], sz = h[2] - l[2];
-    bool near = true;   // offsets small enough for exact integer conversion
-    for (int d = 0; d < 3; ++d) near = near && fabsf(l[d]) < kMaxOff && fabsf(h[d]) < kMaxOff;
-    if (near && sx < kMaxSpan && sy < kMaxSpan && sz < kMaxSpan) {
-      box[0] = (int)ceilf(l[0]);
-      box[1] = (int)ceilf(l[1]);
-      box[2] = (int)floorf(h[0]) - box[0] + 1;
-      box[3] = (int)floorf(h[1]) - box[1] + 1;
-      box[4] = (int)ceilf(l[2]);
-      box[5] = (int)floorf(h[2]);
-      xr[0] = l[0];
-      xr[1] = h[0];
-    } else {   // non-finite positions (reported by the vertex move) or a cell far too large
-      box[2] = box[3] = 0;
-      if (sx >= kMaxSpan || sy >= kMaxSpan || sz >= kMaxSpan || !near) atomicOr(&flags[1], 16);
-    }
-  }
-  __syncthreads();
-  const int ly = box[1], ncy = box[3];
-  if (ncy <= 0 || (!L.le && box[2] <= 0)) return;
-  const int ox = C.origin[3 * c], oy = C.origin[3 * c + 1], oz = C.origin[3 * c + 2];
-  const unsigned bit = 1u << (cls ? cls[c] : 0);
-  // Sheared periodic images (gradient z, flow x): the nodes of image m,
-  // m = floor(unwrapped z / nz), are inside when the cell's copy displaced
-  // by -m Delta along x contains them, so their columns sit at cell-frame
-  // x + m Delta.  Without images there is one pass, m = 0, with integer
-  // columns.
-  int m_lo = 0, m_hi = 0;
-  if (L.le) {
-    m_lo = floor_div(oz + box[4], L.nz);
-    m_hi = floor_div(oz + box[5], L.nz);
-  }
-  for (int m = m_lo; m <= m_hi; ++m) {
-    const float shift = L.le ? (float)m * L.le_delta : 0.f;
-    // with a shift the column range is widened by one: columns outside the
-    // cell's projection cross nothing
-    const int lx = L.le ? (int)floorf(xr[0] - shift) : box[0];
-    const int ncx = L.le ? (int)floorf(xr[1] - shift) - lx + 2 : box[2];
-    if (ncx > kMaxCols) {   // a cell wider than the column grid along x
-      if (tid == 0) atomicOr(&flags[1], 16);
-      return;
-    }
-    // the columns in chunks of whole rows that fit the LDS grid (one chunk for
-    // an undeformed cell)
-    const int rows = kMaxCols / ncx;
-    for (int r0 = 0; r0 < ncy; r0 += rows) {
-      const int nr = min(rows, ncy - r0);
-      for (int i = tid; i < nr * ncx; i += kMarkThreads) cnt[i] = 0;
-      __syncthreads();
-      for (int t = tid; t < M.nt; t += kMarkThreads) {
-        const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-        float ax = sp[3 * ia], ay = sp[3 * ia + 1], az = sp[3 * ia + 2];
-        float bx = sp[3 * ib], by = sp[3 * ib + 1], bz = sp[3 * ib + 2];
-        float cx = sp[3 * ic], cy = sp[3 * ic + 1], cz = sp[3 * ic + 2];
-        const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-        if (area2 == 0.f) continue;
-        if (area2 < 0.f) {   // orient counter-clockwise in projection
-          float tx = bx, ty = by, tz = bz;
-          bx = cx, by = cy, bz = cz;
-          cx = tx, cy = ty, cz = tz;
-        }
-        const float A = fabsf(area2);
-        const float tx0 = fminf(ax, fminf(bx, cx)), tx1 = fmaxf(ax, fmaxf(bx, cx));
-        const int x0 = max(L.le ? (int)floorf(tx0 - shift) : (int)ceilf(tx0), lx);
-        const int x1 = min(L.le ? (int)floorf(tx1 - shift) + 1 : (int)floorf(tx1), lx + ncx - 1);
-        const int y0 = max((int)ceilf(fminf(ay, fminf(by, cy))), ly + r0);
-        const int y1 = min((int)floorf(fmaxf(ay, fmaxf(by, cy))), ly + r0 + nr - 1);
-        for (int iy = y0; iy <= y1; ++iy)
-          for (int ix = x0; ix <= x1; ++ix) {
-            const float x = (float)ix + shift, y = (float)iy;
-            if (!(edge_in(ax, ay, bx, by, x, y) && edge_in(bx, by, cx, cy, x, y) &&
-                  edge_in(cx, cy, ax, ay, x, y)))
-              continue;
-            const float wa = (bx - x) * (cy - y) - (by - y) * (cx - x);
-            const float wb = (cx - x) * (ay - y) - (cy - y) * (ax - x);
-            const float wc = (ax - x) * (by - y) - (ay - y) * (bx - x);
-            const float z = (wa * az + wb * bz + wc * cz) / A;
-            const int col = (iy - ly - r0) * ncx + (ix - lx);
-            const int slot = atomicAdd(&cnt[col], 1);
-            if (slot < kMaxCross) zc[col][slot] = z;
-            else atomicOr(&flags[1], 32);
-          }
-      }
-      __syncthreads();
-      for (int col = tid; col < nr * ncx; col += kMarkThreads) {
-        const int n = min(cnt[col], kMaxCross);
-        if (n < 2) continue;
-        float z[kMaxCross];
-        for (int k = 0; k < kMaxCross; ++k) z[k] = k < n ? zc[col][k] : 3e38f;
-        for (int i = 1; i < kMaxCross; ++i)   // insertion sort, fixed trip counts
-          for (int j = i; j > 0; --j)
-            if (z[j] < z[j - 1]) {
-              const float s = z[j];
-              z[j] = z[j - 1];
-              z[j - 1] = s;
-            }
-        int xs = ox + lx + col % ncx, ys = oy + ly + r0 + col / ncx;
-        if (L.bc[0] == 1) {
-          if (xs < 0 || xs >= L.nx) continue;
-        } else {
-          xs = wrap(xs, L.nx);
-        }
-        if (L.bc[1] == 1) {
-          if (ys < 0 || ys >= L.ny) continue;
-        } else {
-          ys = wrap(ys, L.ny);
-        }
-        for (int k = 0; k + 1 < n; k += 2) {
-          // the heights lie within the cell's bounded z extent
-          const int z0 = (int)floorf(z[k]) + 1, z1 = (int)ceilf(z[k + 1]) - 1;
-          for (int iz = z0; iz <= z1; ++iz) {
-            int zs = oz + iz;
-            if (L.le && floor_div(zs, L.nz) != m) continue;   // a node of another image
-            if (L.bc[2] == 1) {
-              if (zs < 0 || zs >= L.nz) continue;
-            } else {
-              zs = wrap(zs, L.nz);
-            }
-            const int64_t h = site_of(L, xs, ys, zs);
-            mask[h] = (unsigned char)bit;
-          }
-        }
-      }
-      __syncthreads();   // the grid is reused by the next chunk
-    }
-  }
+  const int o[3] = {C.origin[3 * c], C.origin[3 * c + 1], C.origin[3 * c + 2]};
+  inside::Grid G;
+  for (int d = 0; d < 3; ++d) G.bc[d] = L.bc[d];
+  G.n[0] = L.nx;
+  G.n[1] = L.ny;
+  G.n[2] = L.nz;
+  G.le = L.le;
+  G.le_delta = L.le_delta;
+  const unsigned char bit = (unsigned char)(1u << (cls ? cls[c] : 0));
+  inside::mark_cell(sp, M.nv, M.tri, M.nt, o, G, [&](int x, int y, int z) { return site_of(L, x, y, z); },
+                    mask, bit, flags + 1, S, tid, kMarkThreads);
 }
 
 }  // namespace

@@ -439,6 +439,7 @@ def _declare_batch(lib):
         "hc_batch_bind_workspace": [_P, _P, sz],
         "hc_batch_set_cells": [_P, _P, _P, _P, _P],
         "hc_batch_set_tiling": [_P, i32, i32, i32],
+        "hc_batch_set_interior_viscosity": [_P, _P],
         "hc_batch_get_tiling": [_P, _P, _P, _P, _P],
         "hc_batch_autotune": [_P, C.c_char_p, i32, _P, _P, _P],
         "hc_batch_run": [_P, i32],
@@ -516,6 +517,11 @@ class Batch:
         tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float32).reshape(self.n_boxes, 3)
         self._check(self.lib.hc_batch_set_cells(self.h, _ptr(origin), _ptr(offsets), _ptr(k),
                                                 None if tr is None else _ptr(tr)))
+
+    def set_interior_viscosity(self, ratios):
+        """Viscosity ratio inside each box's cell (one float per box)."""
+        r = np.ascontiguousarray(np.broadcast_to(np.asarray(ratios, dtype=np.float32), (self.n_boxes,)))
+        self._check(self.lib.hc_batch_set_interior_viscosity(self.h, _ptr(r)))
 
     def set_tiling(self, ty, tz, block=256):
         self._check(self.lib.hc_batch_set_tiling(self.h, int(ty), int(tz), int(block)))

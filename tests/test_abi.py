@@ -137,3 +137,20 @@ def test_packing_plan_validation(lib):
         assert why in lib.hc_last_error(None)
     # run-time checks that precede any device work
     assert lib.hc_pack_run(C.byref(_pack()), None, None, None, 10, 1, None, 0, None, None) == ARG
+
+
+def test_batch_settings_need_a_workspace(lib, rbc):
+    from paper_2305_02752_amd import hemo
+    from workloads.configs import Lattice
+    hemo._declare_batch(lib)
+    lats = (hemo.LatticeDesc * 2)(hemo.lattice_desc(Lattice(16, 16, 16, tau=0.9)),
+                                  hemo.lattice_desc(Lattice(20, 16, 12, tau=1.1)))
+    m, keep = _mesh(rbc)
+    b = C.c_void_p()
+    assert lib.hc_batch_create(2, lats, C.byref(m), C.byref(b)) == OK
+    r = (C.c_float * 2)(2.0, 5.0)
+    assert lib.hc_batch_set_interior_viscosity(b, r) == 2    # HC_ERR_STATE: no workspace bound
+    assert b"workspace" in lib.hc_batch_last_error(b)
+    n = C.c_size_t()
+    assert lib.hc_batch_query_workspace(b, C.byref(n)) == OK and n.value > 19 * (16 ** 3 + 20 * 16 * 12) * 12
+    lib.hc_batch_destroy(b)

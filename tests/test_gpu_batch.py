@@ -114,3 +114,78 @@ def test_batch_tilings_agree_bitwise_and_autotune_preserves_state(tmp_path):
         assert np.array_equal(after[b], outs[0][b][0])
     again = bt.autotune(tmp_path / "tune.txt", trial_steps=3)   # served from the cache
     assert again == choice
+
+
+RATIOS = [5.0, 1.0, 3.0, 5.0, 2.0]   # per box; 1 leaves the box without marks
+
+
+def test_batch_interior_viscosity_one_step_parity():
+    # each box's cell carries its own interior ratio (Sec. 1, Sec. 3.4)
+    lats, rest, tri, cells = _boxes(4)
+    bt = _make(lats, rest, tri, cells)
+    bt.set_interior_viscosity(RATIOS)
+    rng = np.random.default_rng(6)
+    g0 = [random_shifted_populations(rng, l, 1e-3) for l in lats]
+    for b, g in enumerate(g0):
+        bt.write_populations(b, g)
+    bt.run(1)
+    bt.sync()
+    for b, l in enumerate(lats):
+        m = step.make_model(l, rest.astype(np.float64), tri, cells[b].k, cells[b].traction,
+                            interior_ratio=RATIOS[b])
+        f1, _, info = step.step(m, lattice.unshift(g0[b]), cells[b].positions64())
+        _, _, fv, vel = bt.read_vertices(b)
+        errs = {"g": relerr(bt.read_populations(b), lattice.shifted(f1)),
+                "Fv": relerr(fv, info["Fv"][0]), "U": relerr(vel, info["U"][0])}
+        print(b, RATIOS[b], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-5, (b, k, e)
+
+
+def test_batch_interior_viscosity_multistep_parity_and_effect():
+    lats, rest, tri, cells = _boxes(5)
+    n = 60
+    plain = _make(lats, rest, tri, cells)
+    plain.run(n)
+    plain.sync()
+    bt = _make(lats, rest, tri, cells)
+    bt.set_interior_viscosity(RATIOS)
+    bt.run(25)
+    bt.run(n - 25)   # marks are set and cleared within each launch
+    bt.sync()
+    for b, l in enumerate(lats):
+        m = step.make_model(l, rest.astype(np.float64), tri, cells[b].k, cells[b].traction,
+                            interior_ratio=RATIOS[b])
+        X0 = cells[b].positions64()
+        f, X = step.run(m, lattice.init_equilibrium(l.shape), X0, n)
+        o, off, _, _ = bt.read_vertices(b)
+        g = bt.read_populations(b)
+        e_g = relerr(g, lattice.shifted(f))
+        # the stiffer interior keeps the displacement small, so positions are
+        # held to float32 storage of the offsets (one rounding per step) plus
+        # the multi-step bar on the displacement
+        e_x = np.abs(o[None, :] + off.astype(np.float64) - X[0]).max()
+        bound = n * 6e-8 * np.abs(off).max() + 1e-3 * np.abs(X[0] - X0[0]).max()
+        effect = relerr(plain.read_populations(b), g)
+        print(b, RATIOS[b], f"{e_g:.2e} {e_x:.2e} (bound {bound:.2e}) effect {effect:.2e}", flush=True)
+        assert e_g <= 1e-3 and e_x <= bound
+        if RATIOS[b] == 1.0:   # marking off: the plain step, bit for bit
+            assert np.array_equal(g, plain.read_populations(b))
+        else:   # well above the parity error: the interior rate changes the flow
+            assert effect > 100 * e_g and effect > 1e-3
+
+
+def test_batch_interior_ratio_one_is_the_plain_step_and_bad_ratios_refused():
+    lats, rest, tri, cells = _boxes(6)
+    a = _make(lats, rest, tri, cells)
+    b = _make(lats, rest, tri, cells)
+    b.set_interior_viscosity([1.0] * len(lats))
+    a.run(9)
+    b.run(9)
+    a.sync()
+    b.sync()
+    for i in range(len(lats)):
+        assert np.array_equal(a.read_populations(i), b.read_populations(i))
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError):
+            a.set_interior_viscosity([2.0, bad, 2.0, 2.0, 2.0])
