@@ -61,16 +61,19 @@ __device__ inline void axis_local(int origin, float x, int n, bool wall, int t0,
   }
 }
 
+// The wait polls with relaxed loads and takes one acquire fence when it
+// ends: an acquire on every poll would invalidate the XCD's L2 each time,
+// which the other work-groups of the XCD, still streaming, pay for.
 __device__ inline bool group_barrier(int* ctr, int members, int& epoch, int* abort_flag,
                                      int spin_limit, int* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(ctr, 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++epoch;
     const int target = epoch * members;
     int ok = 1, spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           ++spins > spin_limit) {
         atomicOr(abort_flag, 1);
@@ -79,7 +82,7 @@ __device__ inline bool group_barrier(int* ctr, int members, int& epoch, int* abo
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *s_ok = ok;
   }
   __syncthreads();
