@@ -129,7 +129,7 @@ __device__ inline void cell_reach(const Batch& V, int box, int K, const float* o
 
 // Marks the nodes inside the box's cell (positions staged in sp by the
 // membrane phase) for the interior relaxation rate.
-__device__ inline void box_mark(const Batch& V, const BoxDesc& B, const float* sp, const int (&o3)[3],
+__device__ inline void box_mark(const Batch& V, const BoxDesc& B, float* sp, const int (&o3)[3],
                                 inside::Lds& S, int tid, int nthr) {
   if (!V.interior || B.omega_in == B.omega) return;
   inside::Grid G;
@@ -140,7 +140,7 @@ __device__ inline void box_mark(const Batch& V, const BoxDesc& B, const float* s
   G.le = 0;
   G.le_delta = 0.f;
   const long long nx = B.nx, ny = B.ny;
-  inside::mark_cell(sp, V.M.nv, V.M.tri, V.M.nt, o3, G,
+  inside::mark_cell(nullptr, sp, V.M.nv, V.M.tri, V.M.nt, o3, G,
                     [=](int x, int y, int z) { return ((int64_t)z * ny + y) * nx + x; },
                     V.mask + B.site_off, (unsigned char)1, V.flags + 2, S, tid, nthr);
 }

@@ -20,8 +20,6 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
   const int c = blockIdx.x, tid = threadIdx.x;
   if (only_class >= 0 && cls[c] != only_class) return;   // another class's pass
   const int64_t b3 = (int64_t)c * M.nv * 3;
-  for (int i = tid; i < 3 * M.nv; i += kMarkThreads) sp[i] = C.off[b3 + i];
-  __syncthreads();
   const int o[3] = {C.origin[3 * c], C.origin[3 * c + 1], C.origin[3 * c + 2]};
   inside::Grid G;
   for (int d = 0; d < 3; ++d) G.bc[d] = L.bc[d];
@@ -31,7 +29,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark_interior(Cells C, Mesh M,
   G.le = L.le;
   G.le_delta = L.le_delta;
   const unsigned char bit = (unsigned char)(1u << (cls ? cls[c] : 0));
-  inside::mark_cell(sp, M.nv, M.tri, M.nt, o, G, [&](int x, int y, int z) { return site_of(L, x, y, z); },
+  inside::mark_cell(C.off + b3, sp, M.nv, M.tri, M.nt, o, G, [&](int x, int y, int z) { return site_of(L, x, y, z); },
                     mask, bit, flags + 1, S, tid, kMarkThreads);
 }
 

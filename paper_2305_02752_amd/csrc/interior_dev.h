@@ -56,13 +56,15 @@ __device__ inline bool edge_in(float px, float py, float qx, float qy, float x, 
 }
 
 // Writes `bit` to mask[site(x, y, z)] for every lattice site inside the
-// cell whose vertex offsets (from its integer origin o) are staged in sp
-// [nv][3] in LDS.  All nthr threads of the work-group call it (nthr a
+// cell whose vertex offsets (from its integer origin o) are in sp [nv][3]
+// in LDS; with src non-null they are first copied there from src (global),
+// in the same pass that finds the cell's extent.  All nthr threads of the work-group call it (nthr a
 // multiple of 64, at most 1024); it synchronises the work-group.  A cell
 // too large for the column grid raises bit 4 of *err; more than kMaxCross
 // crossings on a column raise bit 5.
 template <class Site>
-__device__ void mark_cell(const float* sp, int nv, const int* __restrict__ tri, int nt, const int (&o)[3],
+__device__ void mark_cell(const float* __restrict__ src, float* sp, int nv, const int* __restrict__ tri,
+                          int nt, const int (&o)[3],
                           const Grid& G, Site site, unsigned char* __restrict__ mask, unsigned char bit,
                           int* err, Lds& S, int tid, int nthr) {
 #pragma clang fp contract(off)
@@ -70,7 +72,13 @@ __device__ void mark_cell(const float* sp, int nv, const int* __restrict__ tri, 
   for (int v = tid; v < nv; v += nthr) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float p = sp[3 * v + d];
+      float p;
+      if (src) {
+        p = src[3 * v + d];
+        sp[3 * v + d] = p;
+      } else {
+        p = sp[3 * v + d];
+      }
       lo[d] = fminf(lo[d], p);
       hi[d] = fmaxf(hi[d], p);
     }
