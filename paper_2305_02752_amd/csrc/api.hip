@@ -51,7 +51,7 @@ struct hc_ctx {
   int cur = 0;
   float* F = nullptr;
   float4* macro = nullptr;     // (ux, uy, uz, rho) per site of the last step
-  float4* partial = nullptr;   // interpolation partial sums per (vertex, touch slot)
+  float4* partial = nullptr;   // interpolation partial sums [touch slot][cells x V]
   int *cell_cnt = nullptr, *cell_ptr = nullptr, *cell_tiles = nullptr, *cell_rank = nullptr,
       *cell_list = nullptr;
   int64_t step = 0;

@@ -204,7 +204,9 @@ __device__ inline void spread_tile(const Cells& C, const Mesh& M, const Lattice&
 
 // Interpolation phase of one tile: one thread per (vertex, tile) entry sums
 // w * u over its stencil nodes inside the tile (velocities staged in su) and
-// stores the partial sum in the vertex's slot.
+// stores the partial sum in the vertex's slot.  Partials are slot-major,
+// [max_touch][cells x V]: entries of neighbouring vertices with the same
+// slot, which one tile mostly holds together, share cache lines.
 template <int K, bool LE = false>
 __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                    const float4* su, int t, int x0, int y0, int z0,
@@ -255,7 +257,7 @@ __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice&
         }
       }
     }
-    partial[(int64_t)v * L.max_touch + j] = make_float4(ux, uy, uz, 0.f);
+    partial[(int64_t)j * C.n * M.nv + v] = make_float4(ux, uy, uz, 0.f);
   }
 }
 

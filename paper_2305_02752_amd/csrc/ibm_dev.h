@@ -25,7 +25,7 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
   const int nt = B.ntouch[v];
   for (int j = 0; j < nt; ++j) {
-    const float4 q = partial[v * L.max_touch + j];
+    const float4 q = partial[(int64_t)j * C.n * M.nv + v];
     Ux += q.x;
     Uy += q.y;
     Uz += q.z;
