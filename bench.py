@@ -399,6 +399,9 @@ def main():
     ap.add_argument("--adjoint-boxes", type=int, default=8)
     ap.add_argument("--packing-only", action="store_true",
                     help="time only the force-bias packing of a million ellipsoids (one JSON line)")
+    ap.add_argument("--fluid-only", action="store_true",
+                    help="time only the lattice pass of the large suspension's lattice without cells "
+                         "(one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no "
@@ -409,6 +412,16 @@ def main():
 
     if args.packing_only:
         print(json.dumps({"force_bias_packing": bench_packing(torch)}), flush=True)
+        return
+    if args.fluid_only:
+        from workloads import rbc_mesh
+        from workloads.configs import Lattice, Workload
+        rest, tri = rbc_mesh(3, 16.0)   # the suspension's cell mesh (unused: no cells)
+        lat = Lattice(256, 256, 512, tau=1.0, body_force=(0.0, 0.0, 1e-6))
+        w = Workload("large_suspension_256x256x512_without_cells", lat, rest.astype(np.float32), tri,
+                     None, args.steps)
+        print(json.dumps({"fluid_only_lattice_pass": bench_fluid_only(torch, w, args.warmup, args.steps)}),
+              flush=True)
         return
 
     from paper_2305_02752_amd import Simulation
