@@ -189,3 +189,44 @@ def test_batch_interior_ratio_one_is_the_plain_step_and_bad_ratios_refused():
     for bad in (0.0, -1.0, float("nan"), float("inf")):
         with pytest.raises(RuntimeError):
             a.set_interior_viscosity([2.0, bad, 2.0, 2.0, 2.0])
+
+
+def test_batch_full_size_sampled_boxes(tmp_path):
+    # the batched calibration workload at full size (256 boxes, sides
+    # U{24..48}, 13.5M nodes) in the launch configuration the benchmark
+    # times (autotuned tiling, one persistent launch); one step from random
+    # shifted populations in the sampled boxes, each checked against the
+    # oracle stepping that box alone.  The cells are jittered so that every
+    # membrane term is active (at the rest shape the internal forces cancel
+    # and the force error would be measured against little more than the
+    # traction).
+    from paper_2305_02752_amd import Batch
+    from workloads import batched_calibration
+    w = batched_calibration(seed=3)
+    jrng = np.random.default_rng(12)
+    cells = [jitter_cells(jrng, c, 0.04) for c in w.cells]
+    bt = Batch(w.lattice, w.rest_pos, w.tri)
+    bt.set_cells(np.concatenate([c.origin for c in cells]), np.concatenate([c.offsets for c in cells]),
+                 np.concatenate([c.k for c in cells]), np.concatenate([c.traction for c in cells]))
+    bt.autotune(tmp_path / "tiling.txt", trial_steps=3)
+    sizes = np.array([l.n_sites for l in w.lattice])
+    rng = np.random.default_rng(11)
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), *rng.choice(len(cells), 2, replace=False)})
+    g0 = {}
+    for b in sample:
+        g0[b] = random_shifted_populations(rng, w.lattice[b], 1e-3)
+        bt.write_populations(b, g0[b])
+    bt.run(1)
+    bt.sync()
+    rest = w.rest_pos.astype(np.float64)
+    for b in sample:
+        l = w.lattice[b]
+        m = step.make_model(l, rest, w.tri, cells[b].k, cells[b].traction)
+        f1, _, info = step.step(m, lattice.unshift(g0[b]), cells[b].positions64())
+        _, _, fv, vel = bt.read_vertices(b)
+        errs = {"g": relerr(bt.read_populations(b), lattice.shifted(f1)),
+                "Fv": relerr(fv, info["Fv"][0]), "U": relerr(vel, info["U"][0])}
+        print(b, l.nx, {k: f"{v:.2e}" for k, v in errs.items()}, bt.tiling(), flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-5, (b, k, e)
+    bt.close()
