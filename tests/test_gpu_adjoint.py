@@ -144,3 +144,44 @@ def test_adjoint_with_per_cell_interior_ratios():
     print("p.g", pg, "fd", pf, "norm", norm, flush=True)
     assert np.allclose(g[:, 4], g[0, 4])       # tau is shared
     assert norm <= 1e-4
+
+
+def test_adjoint_full_size_properties():
+    # one box of the adjoint workload at its full configuration (48^3,
+    # moving walls, pole traction, 2000 steps, checkpoint every 100), as the
+    # benchmark runs it.  The FP64 oracle cannot take 2000 steps of 48^3 in
+    # test time, so the checks are properties that hold at any size: the
+    # checkpointed forward is the plain run bit for bit, its loss is the loss
+    # of its final vertices, and the gradient is finite and does not depend
+    # on the checkpoint interval.
+    from paper_2305_02752_amd import Simulation
+    from workloads import adjoint_boxes
+    w = adjoint_boxes(seed=4, n_boxes=1)   # box 0 of the 64-box workload
+    n, ck = w.steps, w.extra["ckpt_every"]
+    c, tg = w.cells[0], w.extra["targets"][0]
+
+    def make():
+        sim = Simulation(w.lattice[0], w.rest_pos, w.tri, max_cells=1)
+        sim.set_cells(c.origin, c.offsets, c.k, c.traction)
+        sim.init_equilibrium()
+        return sim
+
+    plain = make()
+    plain.step(n)
+    plain.sync()
+    a = make()
+    a.adj_bind(n, ck)
+    loss = a.adj_forward(tg)[0]
+    assert np.array_equal(a.read_populations(), plain.read_populations())
+    o, off = a.read_vertices()[:2]
+    assert np.array_equal(off, plain.read_vertices()[1])
+    L_host = oadj.loss_of(o[0][None, :] + off[0].astype(np.float64), tg)
+    g1 = a.adj_backward()[0]
+    b = make()
+    b.adj_bind(n, 40)
+    assert b.adj_forward(tg)[0] == loss
+    g2 = b.adj_backward()[0]
+    print(f"loss {loss:.8f} (host {L_host:.8f}), grad {g1}", flush=True)
+    assert abs(loss - L_host) <= 1e-5 * abs(L_host)
+    assert np.all(np.isfinite(g1)) and np.any(g1 != 0.0)
+    assert np.array_equal(g1, g2)
