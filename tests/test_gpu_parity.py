@@ -71,6 +71,33 @@ def test_one_step_parity(name):
         assert e <= TOL_STEP, (k, e)
 
 
+def test_one_step_parity_dense_channel():
+    # the dense channel suspension at its full size (128 x 64 x 64, walls at
+    # the y bounds, body force, 220 cells), one step from random shifted
+    # populations and jittered cells, every field against the oracle
+    from workloads import dense_channel
+    w = dense_channel()
+    rng = np.random.default_rng(101)
+    cells = jitter_cells(rng, w.cells, 0.05)
+    g0 = random_shifted_populations(rng, w.lattice, 1e-3)
+    sim = make_sim(w, cells)
+    sim.write_populations(g0)
+    sim.step(1)
+    sim.sync()
+    rho, u = sim.read_macro()
+    o1, off1, fv = sim.read_vertices()
+    m = oracle_model(w, cells)
+    f0, X0 = oracle_state(g0, cells)
+    f1r, X1r, info = step.step(m, f0, X0)
+    _check_positions(o1[:, None, :].astype(np.float64) + off1.astype(np.float64), X1r, off1, info["U"])
+    errs = {"g": relerr(sim.read_populations(), lattice.shifted(f1r)), "rho": relerr(rho, info["rho"]),
+            "u": relerr(u, info["u"]), "F": relerr(sim.read_force_field(), info["F"]),
+            "Fv": relerr(fv, info["Fv"]), "U": relerr(sim.read_vertex_velocity(), info["U"])}
+    print("dense channel", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= TOL_STEP, (k, e)
+
+
 def test_zero_cells_fluid_only():
     lat = Lattice(20, 12, 16, bc=(0, 1, 0), tau=0.8, body_force=(1e-5, 0, 0))
     from workloads import rbc_mesh
