@@ -24,7 +24,7 @@ namespace inside {
 
 constexpr int kMaxCols = 320;        // (x, y) columns held in LDS at once (whole rows)
 constexpr int kMaxCross = 8;         // crossings per column
-constexpr int kMaxWaves = 16;        // work-groups of up to 1024 threads
+constexpr int kMaxWaves = 16;        // wavefronts per work-group (up to 1024 threads)
 constexpr float kMaxSpan = 1024.f;   // bounding-box side beyond which a cell is refused
 constexpr float kMaxOff = 16777216.f;   // offsets from the cell origin beyond which it is refused
 
