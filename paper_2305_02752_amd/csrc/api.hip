@@ -463,17 +463,19 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   L.np = (int64_t)L.ntiles * kTile * kTile * kTile;
   // a K-node stencil window meets 3 tiles along a periodic axis only when the
   // last tile is at most K-2 nodes wide; otherwise 2 (1 for a 1-tile axis)
-  L.max_touch = 1;
   const int sides[3] = {L.nx, L.ny, L.nz};
+  int reach[3];
   for (int d = 0; d < 3; ++d) {
     const int last = sides[d] - (sides[d] - 1) / kTile * kTile;
     int per_axis = sides[d] <= kTile ? 1 : 2;
     if (L.bc[d] == HC_PERIODIC && sides[d] > kTile && last <= L.kernel - 2) per_axis = 3;
-    int reach = std::min(per_axis, (sides[d] + kTile - 1) / kTile);
-    // with sheared images a stencil spans the x tiles of two displaced copies
-    if (le && d == 0) reach = std::min(2 * reach, (sides[d] + kTile - 1) / kTile);
-    L.max_touch *= reach;
+    reach[d] = std::min(per_axis, (sides[d] + kTile - 1) / kTile);
   }
+  L.max_touch = reach[0] * reach[1] * reach[2];
+  // with sheared images the (z tile, x tile) pairs: one z tile per image
+  // when the stencil crosses the boundary (sides are multiples of 8), each
+  // with the x tiles of its own displaced copy; at most 4
+  if (le) L.max_touch = reach[1] * std::min(4, std::max(reach[2], 2) * reach[0]);
   c->max_cells = max_cells;
   // tile-list capacity: 4 entries per tile node (about 4x the densest
   // suspension's mean), capped by what all vertices could ever need

@@ -27,9 +27,13 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out, int c
 }
 
 // Tiles reached by the stencil of a vertex of cell c at offset o, per axis,
-// and its owner tile.  With sheared periodic images the x tiles are those
-// of the vertex's displaced copies in every image its z stencil reaches
-// (two at most), so up to 4 along x.
+// and its owner tile.  The reached tiles are the products T[2] x T[1] x T[0].
+// With sheared periodic images the z stencil may reach two images, and each
+// image's nodes sit at the vertex's x displaced by that image's shift; the
+// reached tiles are then the (z tile, x tile) pairs of each image's own
+// nodes times the y tiles.  Those pairs (at most 4: one z tile per image
+// when the stencil crosses the boundary, with at most 2 x tiles each) are
+// stored as T[2][p], T[0][p] with nT[0] = pairs and nT[2] = 1.
 __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, const float* o,
                                    int (&T)[3][4], int (&nT)[3]) {
   const int K = L.kernel;
@@ -44,17 +48,43 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
   }
   if (L.le) {
     const int pz = C.origin[3 * c + 2] + (int)floorf(o[2]);
-    const int ma = floor_div(pz + b, L.nz), mb = floor_div(pz + b + K - 1, L.nz);
-    const float xa = o[0] - (float)ma * L.le_delta, xb = o[0] - (float)mb * L.le_delta;
-    nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xa) + b, K, L.nx, 0, T[0], 0, 4);
-    if (mb != ma) nT[0] = axis_tiles(C.origin[3 * c] + (int)floorf(xb) + b, K, L.nx, 0, T[0], nT[0], 4);
+    const int ma = floor_div(pz + b, L.nz);
+    int xt[2][4], nxt[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float xi = o[0] - (float)(ma + i) * L.le_delta;
+      nxt[i] = axis_tiles(C.origin[3 * c] + (int)floorf(xi) + b, K, L.nx, 0, xt[i], 0, 4);
+    }
+    int np = 0;
+    for (int k = 0; k < K; ++k) {
+      const int p = pz + b + k;
+      const int i = floor_div(p, L.nz) - ma;   // 0 or 1: the image of this z node
+      const int zt = wrap(p, L.nz) / kTile;
+      for (int q = 0; q < nxt[i]; ++q) {
+        bool seen = false;
+        for (int r = 0; r < np; ++r) seen = seen || (T[2][r] == zt && T[0][r] == xt[i][q]);
+        if (!seen && np < 4) {
+          T[0][np] = xt[i][q];
+          T[2][np] = zt;
+          ++np;
+        }
+      }
+    }
+    nT[0] = np;
+    nT[2] = 1;
     const float xo = o[0] - (float)floor_div(pz, L.nz) * L.le_delta;
     own[0] = wrap(C.origin[3 * c] + (int)floorf(xo), L.nx) / kTile;
   }
   return (own[2] * L.ty + own[1]) * L.tx + own[0];
 }
 
+// Tile of slot j of a vertex: j runs over x fastest, then y, then z (over
+// the (z, x) pairs, then y, with sheared images).
 __device__ inline int slot_tile(const Lattice& L, const int (&T)[3][4], const int (&nT)[3], int j) {
+  if (L.le) {
+    const int p = j % nT[0], r = j / nT[0];
+    return (T[2][p] * L.ty + T[1][r]) * L.tx + T[0][p];
+  }
   const int a = j / (nT[0] * nT[1]), r = j % (nT[0] * nT[1]);
   return (T[2][a] * L.ty + T[1][r / nT[0]]) * L.tx + T[0][r % nT[0]];
 }
