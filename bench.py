@@ -401,6 +401,8 @@ def main():
     ap.add_argument("--adjoint-boxes", type=int, default=64)
     ap.add_argument("--packing-only", action="store_true",
                     help="time only the force-bias packing of a million ellipsoids (one JSON line)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched calibration form (one JSON line)")
     ap.add_argument("--fluid-only", action="store_true",
                     help="time only the lattice pass of the large suspension's lattice without cells "
                          "(one JSON line)")
@@ -414,6 +416,9 @@ def main():
 
     if args.packing_only:
         print(json.dumps({"force_bias_packing": bench_packing(torch)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_calibration": bench_batched(torch)}), flush=True)
         return
     if args.fluid_only:
         from workloads import rbc_mesh
