@@ -17,6 +17,12 @@ device the same bookkeeping becomes binning to cubic lattice tiles of side
     (floor(X)-1 .. floor(X)+2 for the 4-point kernel, floor(X) ..
     floor(X)+1 for the 2-point one; walls drop outside nodes) lie in it;
   * CSR lists sorted by (tile, cell) and (tile, cell, vertex).
+  * with Lees-Edwards images (Sec. 2.5 reading; periodic axes, shift Delta
+    along x per image across z): a z stencil node p lies in image
+    m = floor(p / N_z), and its x nodes are those of the vertex displaced
+    to x - m Delta.  The displaced coordinate decides integer tiles, so it
+    is taken as the device takes it: offset - m Delta in float32 with one
+    rounding (a fused multiply-add).
 """
 from __future__ import annotations
 
@@ -83,8 +89,17 @@ def bins(origin, offsets, dims, bc):
     return owner, vert_ptr, gidx[order], cell_ptr, pairs[:, 1]
 
 
-def touch_lists(origin, offsets, dims, bc, kernel=4):
-    """CSR (ptr [NT+1], vertex ids) of the tiles each vertex's stencil reaches."""
+def _sheared_x(off_x, m, delta):
+    """float32(off_x - m * delta) rounded once, as a fused multiply-add:
+    the product of a small integer and a float32 and the difference are
+    exact in float64, so one rounding to float32 follows."""
+    return np.float32(np.float64(np.float32(off_x)) - np.float64(m) * np.float64(np.float32(delta)))
+
+
+def touch_lists(origin, offsets, dims, bc, kernel=4, le_delta=None):
+    """CSR (ptr [NT+1], vertex ids) of the tiles each vertex's stencil
+    reaches; le_delta: the image shift with Lees-Edwards images (None: no
+    images)."""
     off = np.asarray(offsets, dtype=np.float32)
     C, V = off.shape[:2]
     T = tiles_per_axis(dims)
@@ -92,6 +107,20 @@ def touch_lists(origin, offsets, dims, bc, kernel=4):
     pairs = set()
     for c in range(C):
         for v in range(V):
+            if le_delta is not None:   # node by node: x depends on the z node's image
+                yb = int(origin[c, 1]) + int(np.floor(off[c, v, 1]))
+                zb = int(origin[c, 2]) + int(np.floor(off[c, v, 2]))
+                for kz in ks:
+                    p = zb + kz
+                    m = p // dims[2]
+                    xm = _sheared_x(off[c, v, 0], m, le_delta)
+                    xb = int(origin[c, 0]) + int(np.floor(xm))
+                    for ky in ks:
+                        for kx in ks:
+                            t = (((p % dims[2]) // TILE) * T[1] + ((yb + ky) % dims[1]) // TILE) * T[0] \
+                                + ((xb + kx) % dims[0]) // TILE
+                            pairs.add((t, c * V + v))
+                continue
             axes = []
             for d in range(3):
                 base = int(origin[c, d]) + int(np.floor(off[c, v, d]))

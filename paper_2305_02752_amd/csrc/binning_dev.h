@@ -52,7 +52,8 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
     int xt[2][4], nxt[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const float xi = o[0] - (float)(ma + i) * L.le_delta;
+      // one rounding, as the lattice pass forms the same displaced x
+      const float xi = fmaf(-(float)(ma + i), L.le_delta, o[0]);
       nxt[i] = axis_tiles(C.origin[3 * c] + (int)floorf(xi) + b, K, L.nx, 0, xt[i], 0, 4);
     }
     int np = 0;

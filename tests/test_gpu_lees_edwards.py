@@ -166,3 +166,28 @@ def test_suspension_across_both_boundaries():
     print("8 cells, 6 steps", e_g, e_u, np.abs(Xg - X).max(), bound, flush=True)
     assert e_g <= n * TOL_STEP and e_u <= n * TOL_STEP
     assert np.abs(Xg - X).max() <= bound
+
+
+def test_sheared_touch_lists_bit_exact():
+    # the device's tile lists with sheared images are the tiles holding at
+    # least one of each vertex's stencil nodes, each node's x taken in its
+    # own image (oracle binning), after several steps of a growing shift
+    from oracle import binning
+    U = 0.37   # a shift that is not a whole number of nodes
+    lat = Lattice(32, 24, 32, tau=0.9, lees_edwards_u=U)
+    _, _, cells = _straddling_cell(lat, 71)
+    sim = _sim(lat, cells)
+    sim.init_equilibrium()
+    n = 9
+    sim.step(n)
+    sim.sync()
+    sim.read_populations()   # brings the context's image shift to step n
+    o, off, _ = sim.read_vertices()
+    owner, tptr, touch, _, _ = sim.read_bins()
+    t = n
+    delta = np.float32(np.fmod(np.fmod(np.float64(np.float32(U)) * t, lat.nx) + lat.nx, lat.nx))
+    ptr_r, vid_r = binning.touch_lists(o, off, (lat.nx, lat.ny, lat.nz), lat.bc, 4, le_delta=delta)
+    # the cell straddles the boundary: some vertices reach two images
+    assert np.any(np.floor(off[0, :, 2] + o[0, 2] - 1) < lat.nz) and np.any(off[0, :, 2] + o[0, 2] + 2 >= lat.nz)
+    assert np.array_equal(tptr, ptr_r)
+    assert np.array_equal(touch, vid_r)

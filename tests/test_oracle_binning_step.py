@@ -104,3 +104,27 @@ def test_coupled_momentum_and_mass_conservation():
     p1 = np.tensordot(E, f, 1).sum(axis=(1, 2, 3))
     assert np.abs(p1 - p0).max() < 1e-13
     assert abs(f.sum() - m0) < 1e-10
+
+
+def test_sheared_touch_lists_special_cases():
+    # Lees-Edwards touch lists: no shift, and a shift of whole periods, are
+    # the plain periodic lists; a shift of one tile moves the x tiles of the
+    # nodes beyond the top z boundary by one tile (worked by hand)
+    rng = np.random.default_rng(3)
+    dims = (32, 24, 40)
+    o = rng.integers(0, 40, (3, 3))
+    off = rng.uniform(-8.0, 8.0, (3, 30, 3)).astype(np.float32)
+    plain = binning.touch_lists(o, off, dims, (0, 0, 0), 4)
+    for delta in (0.0, 32.0, 64.0):
+        got = binning.touch_lists(o, off, dims, (0, 0, 0), 4, le_delta=delta)
+        assert np.array_equal(got[0], plain[0]) and np.array_equal(got[1], plain[1]), delta
+    # one vertex at x = 12.5, y = 4.5, z = 39.5: z nodes 38, 39 (image 0:
+    # tile 4) and 40, 41 (image 1: wrapped 0, 1, tile 0, x displaced by -8)
+    o1 = np.zeros((1, 3), dtype=np.int64)
+    off1 = np.array([[[12.5, 4.5, 39.5]]], dtype=np.float32)
+    ptr, vid = binning.touch_lists(o1, off1, dims, (0, 0, 0), 4, le_delta=8.0)
+    T = binning.tiles_per_axis(dims)
+    tiles = {t for t in range(T[0] * T[1] * T[2]) if ptr[t + 1] > ptr[t]}
+    # x nodes 11..14 (tile 1) in image 0, 3..6 (tile 0) in image 1; y nodes 3..6 (tile 0)
+    expect = {(4 * T[1] + 0) * T[0] + 1, (0 * T[1] + 0) * T[0] + 0}
+    assert tiles == expect
