@@ -234,7 +234,7 @@ __device__ inline double dotf(mem::f3 f, const float* lam, int v) {
 
 // Sum of 4 doubles over the kAdjThreads threads of a work-group: within each
 // wave by shuffles, then across waves in a fixed order (reproducible).
-constexpr int kAdjThreads = 256;
+template <int kAdjThreads>
 __device__ inline void block_sum4(double (&v)[4], double* red) {
   for (int m = kWave / 2; m > 0; m >>= 1)
 #pragma unroll
@@ -252,8 +252,10 @@ __device__ inline void block_sum4(double (&v)[4], double* red) {
   }
 }
 
-// One work-group of kAdjThreads per cell.  LDS: positions, tangents
+// One work-group of kAdjThreads per cell (wider when the cells are few, as
+// for the forward per-cell kernel).  LDS: positions, tangents
 // (= lam_{F_v}), int64 accumulator of the Jacobian-vector product.
+template <int kAdjThreads>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
                                                               const float* __restrict__ lamFv,
                                                               float* __restrict__ lamX,
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
     dV += (trip(dx[0], x[1], x[2]) + trip(x[0], dx[1], x[2]) + trip(x[0], x[1], dx[2])) / 6.0;
   }
   double av[4] = {A, V, dA, dV};
-  block_sum4(av, red);
+  block_sum4<kAdjThreads>(av, red);
   A = av[0];
   V = av[1];
   dA = av[2];
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
     sb += (dotv(fi, st, i) + dotv(fj, st, j) + dotv(fk, st, k) + dotv(fl, st, l)) / kb;
   }
   double sk[4] = {sl, sb, sa, sv};
-  block_sum4(sk, red);
+  block_sum4<kAdjThreads>(sk, red);
   sl = sk[0];
   sb = sk[1];
   sa = sk[2];
@@ -435,7 +437,12 @@ hipError_t launch_adj_membrane(const Cells& c, const Mesh& m, const float* lamFv
                                hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * 3 * (8 + 4 + 4);
-  hipLaunchKernelGGL(k_adj_membrane, dim3(c.n), dim3(kAdjThreads), lds, s, c, m, lamFv, lamX, dk);
+  if (c.n <= 64)
+    hipLaunchKernelGGL(k_adj_membrane<1024>, dim3(c.n), dim3(1024), lds, s, c, m, lamFv, lamX, dk);
+  else if (c.n <= 1024)
+    hipLaunchKernelGGL(k_adj_membrane<512>, dim3(c.n), dim3(512), lds, s, c, m, lamFv, lamX, dk);
+  else
+    hipLaunchKernelGGL(k_adj_membrane<256>, dim3(c.n), dim3(256), lds, s, c, m, lamFv, lamX, dk);
   return hipGetLastError();
 }
 

@@ -15,14 +15,15 @@
 namespace hc {
 namespace {
 
-__global__ __launch_bounds__(256) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
+template <bool LE, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
   extern __shared__ unsigned short slots[];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
   const int c = blockIdx.x;
   unsigned short* srank = slots;
   unsigned char* shash = reinterpret_cast<unsigned char*>(slots + (size_t)M.nv * L.max_touch);
-  bin::bin_cell(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, srank, shash,
-                threadIdx.x, blockDim.x);
+  bin::bin_cell<LE>(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, srank, shash,
+                    threadIdx.x, blockDim.x);
 }
 
 // Copy the fixed-capacity tile lists into CSR form (read-out path).
@@ -213,7 +214,13 @@ hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, 
                                hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const size_t lds = (size_t)m.nv * bin::slot_lds_per_vertex(L.max_touch);
-  hipLaunchKernelGGL(k_bin_vertices, dim3(c.n), dim3(256), lds, s, c, m, L, b);
+  // wider work-groups when the cells are few (one work-group per cell)
+  if (L.le)
+    hipLaunchKernelGGL((k_bin_vertices<true, 256>), dim3(c.n), dim3(256), lds, s, c, m, L, b);
+  else if (c.n <= 64)
+    hipLaunchKernelGGL((k_bin_vertices<false, 1024>), dim3(c.n), dim3(1024), lds, s, c, m, L, b);
+  else
+    hipLaunchKernelGGL((k_bin_vertices<false, 256>), dim3(c.n), dim3(256), lds, s, c, m, L, b);
   return hipGetLastError();
 }
 

@@ -34,6 +34,10 @@ __device__ inline int axis_tiles(int p0, int K, int n, int wall, int* out, int c
 // nodes times the y tiles.  Those pairs (at most 4: one z tile per image
 // when the stencil crosses the boundary, with at most 2 x tiles each) are
 // stored as T[2][p], T[0][p] with nT[0] = pairs and nT[2] = 1.
+// LE = false compiles the enumeration without the sheared-image branch (its
+// dynamically indexed arrays would otherwise move the arrays of every
+// lattice into scratch memory); such a caller must not be given images.
+template <bool LE = true>
 __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, const float* o,
                                    int (&T)[3][4], int (&nT)[3]) {
   const int K = L.kernel;
@@ -46,7 +50,7 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
     nT[d] = axis_tiles(p + b, K, n[d], L.bc[d] == 1, T[d]);
     own[d] = (L.bc[d] == 1 ? min(max(p, 0), n[d] - 1) : wrap(p, n[d])) / kTile;
   }
-  if (L.le) {
+  if (LE && L.le) {
     const int pz = C.origin[3 * c + 2] + (int)floorf(o[2]);
     const int ma = floor_div(pz + b, L.nz);
     int xt[2][4], nxt[2];
@@ -81,8 +85,9 @@ __device__ inline int vertex_tiles(const Cells& C, const Lattice& L, int c, cons
 
 // Tile of slot j of a vertex: j runs over x fastest, then y, then z (over
 // the (z, x) pairs, then y, with sheared images).
+template <bool LE = true>
 __device__ inline int slot_tile(const Lattice& L, const int (&T)[3][4], const int (&nT)[3], int j) {
-  if (L.le) {
+  if (LE && L.le) {
     const int p = j % nT[0], r = j / nT[0];
     return (T[2][p] * L.ty + T[1][r]) * L.tx + T[0][p];
   }
@@ -103,6 +108,7 @@ __host__ __device__ inline int slot_lds_per_vertex(int max_touch) { return 3 * m
 // pos: the cell's vertex offsets [nv][3] (global or LDS); keys, count and
 // base: LDS arrays of kHash ints; srank / shash: LDS [nv * max_touch]
 // records of each pair's rank and hash slot (rank 0xffff: no slot).
+template <bool LE = true>
 __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B, int c,
                                 const float* pos, int* keys, int* count, int* base,
                                 unsigned short* srank, unsigned char* shash, int tid, int nthr) {
@@ -114,7 +120,7 @@ __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L,
   for (int vl = tid; vl < M.nv; vl += nthr) {
     const int64_t v = (int64_t)c * M.nv + vl;
     int T[3][4], nT[3];
-    B.owner[v] = vertex_tiles(C, L, c, pos + 3 * vl, T, nT);
+    B.owner[v] = vertex_tiles<LE>(C, L, c, pos + 3 * vl, T, nT);
     int ntouch = nT[0] * nT[1] * nT[2];
     if (ntouch > L.max_touch) {  // excluded by the per-axis bound set at create
       atomicOr(&B.flags[1], 2);
@@ -122,7 +128,7 @@ __device__ inline void bin_cell(const Cells& C, const Mesh& M, const Lattice& L,
     }
     B.ntouch[v] = ntouch;
     for (int j = 0; j < ntouch; ++j) {
-      const int tile = slot_tile(L, T, nT, j);
+      const int tile = slot_tile<LE>(L, T, nT, j);
       int h = (int)(((unsigned)tile * 2654435761u) >> 24);
       int probe = 0;
       for (; probe < kHash; ++probe) {

@@ -16,9 +16,10 @@
 namespace hc {
 namespace {
 
-constexpr int kCellThreads = 256;
-
-template <int K>
+// Work-group size: 256 threads when the cells fill the chip; with fewer
+// cells than a few per CU each cell's work-group is widened so that its
+// latency-bound loops take fewer rounds.
+template <int K, int kCellThreads, bool LE>
 __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
                                                            const float4* __restrict__ partial,
                                                            int* __restrict__ flags, int advect,
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
     __syncthreads();   // forces held from the last refresh; sp complete for the binning
   }
   __syncthreads();   // the accumulator is free: its space takes the slot records
-  bin::bin_cell(C, M, L, B, c, sp, keys, count, base, srank, shash, tid, kCellThreads);
+  bin::bin_cell<LE>(C, M, L, B, c, sp, keys, count, base, srank, shash, tid, kCellThreads);
 }
 
 }  // namespace
@@ -66,12 +67,24 @@ hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, con
   if (c.n == 0) return hipSuccess;
   const int region = std::max(24, bin::slot_lds_per_vertex(L.max_touch)) * m.nv;
   const size_t lds = (size_t)((region + 7) & ~7) + (size_t)m.nv * 3 * sizeof(float);
-  if (L.kernel == 4)
-    hipLaunchKernelGGL(k_cell_step<4>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0, src, refresh ? 1 : 0, ab2 ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_cell_step<2>, dim3(c.n), dim3(kCellThreads), lds, s, c, m, L, b, partial,
-                       flags, advect ? 1 : 0, src, refresh ? 1 : 0, ab2 ? 1 : 0);
+  const int adv = advect ? 1 : 0, ref = refresh ? 1 : 0, a2 = ab2 ? 1 : 0;
+  auto go = [&](auto kern, int threads) {
+    hipLaunchKernelGGL(kern, dim3(c.n), dim3(threads), lds, s, c, m, L, b, partial, flags, adv, src, ref, a2);
+  };
+  // sheared images: one 256-thread form
+  if (L.le) {
+    if (L.kernel == 4) go(k_cell_step<4, 256, true>, 256);
+    else go(k_cell_step<2, 256, true>, 256);
+  } else if (c.n <= 64) {
+    if (L.kernel == 4) go(k_cell_step<4, 1024, false>, 1024);
+    else go(k_cell_step<2, 1024, false>, 1024);
+  } else if (c.n <= 1024) {
+    if (L.kernel == 4) go(k_cell_step<4, 512, false>, 512);
+    else go(k_cell_step<2, 512, false>, 512);
+  } else {
+    if (L.kernel == 4) go(k_cell_step<4, 256, false>, 256);
+    else go(k_cell_step<2, 256, false>, 256);
+  }
   return hipGetLastError();
 }
 
