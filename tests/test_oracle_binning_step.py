@@ -128,3 +128,78 @@ def test_sheared_touch_lists_special_cases():
     # x nodes 11..14 (tile 1) in image 0, 3..6 (tile 0) in image 1; y nodes 3..6 (tile 0)
     expect = {(4 * T[1] + 0) * T[0] + 1, (0 * T[1] + 0) * T[0] + 0}
     assert tiles == expect
+
+
+def _brute_touch(origin, off, dims, bc, kernel):
+    """(tile, vertex) pairs by enumeration: for every tile, every node in it,
+    and for every vertex the nodes of its stencil (walls drop the nodes past
+    them): the vertex is listed for the tile when one of its stencil nodes is
+    one of the tile's nodes."""
+    K = kernel
+    T = [(n + 7) // 8 for n in dims]
+    off = np.asarray(off, dtype=np.float32)
+    C, V = off.shape[:2]
+    first = -1 if K == 4 else 0
+    base = (origin[:, None, :].astype(np.int64) + np.floor(off).astype(np.int64) + first).reshape(-1, 3)
+    # stencil node sets, one boolean row per vertex and per axis over the nodes of that axis
+    reach = []
+    for d in range(3):
+        n = dims[d]
+        hit = np.zeros((C * V, n), dtype=bool)
+        for k in range(K):
+            p = base[:, d] + k
+            if bc[d] == 1:
+                ok = (p >= 0) & (p < n)
+                hit[np.nonzero(ok)[0], p[ok]] = True
+            else:
+                hit[np.arange(C * V), np.mod(p, n)] = True
+        reach.append(hit)
+    out = {}
+    for tz in range(T[2]):
+        for ty in range(T[1]):
+            for tx in range(T[0]):
+                t = (tz * T[1] + ty) * T[0] + tx
+                xs = np.arange(tx * 8, min(tx * 8 + 8, dims[0]))
+                ys = np.arange(ty * 8, min(ty * 8 + 8, dims[1]))
+                zs = np.arange(tz * 8, min(tz * 8 + 8, dims[2]))
+                # every node (x, y, z) of the tile against every vertex
+                node_hit = (reach[0][:, xs][:, None, None, :] & reach[1][:, ys][:, None, :, None]
+                            & reach[2][:, zs][:, :, None, None])
+                out[t] = np.nonzero(node_hit.reshape(C * V, -1).any(axis=1))[0]
+    return out
+
+
+@pytest.mark.parametrize("kernel", [4, 2])
+@pytest.mark.parametrize("dims,bc", [
+    ((16, 16, 16), (0, 0, 0)),
+    ((33, 20, 25), (0, 1, 0)),     # ragged tiles, y walls
+    ((17, 18, 26), (0, 0, 0)),     # last tiles 1-2 nodes wide: a stencil meets 3 tiles
+    ((6, 20, 5), (0, 0, 0)),       # sides below 8
+    ((6, 20, 5), (0, 0, 1)),       # sides below 8, a wall on the 5-node axis
+    ((25, 19, 18), (1, 0, 0)),     # x walls, ragged
+])
+def test_touch_lists_brute_force(dims, bc, kernel):
+    rng = np.random.default_rng(sum(dims) + kernel)
+    rest64, _ = rbc_mesh()
+    C = 3
+    cen = rng.uniform(0, 1, (C, 3)) * np.array(dims)
+    for d in range(3):
+        if bc[d] == 1:   # keep the cells inside the walls, near them
+            cen[:, d] = np.array([2.5, dims[d] / 2, dims[d] - 3.0])
+    cen[0, 0] = dims[0] - 0.7 if bc[0] == 0 else cen[0, 0]   # straddle the periodic x boundary
+    cells = place_cells(0.35 * rest64, cen, np.stack([random_rotation(rng) for _ in range(C)]),
+                        np.repeat(K_REF[None], C, 0))
+    off = cells.offsets.copy()
+    # some vertices exactly on nodes and just below them
+    off[1, :40] = np.round(off[1, :40])
+    off[2, :40] = np.nextafter(np.round(off[2, :40]), np.float32(-np.inf))
+    ptr, vid = binning.touch_lists(cells.origin, off, dims, bc, kernel)
+    want = _brute_touch(cells.origin, off, dims, bc, kernel)
+    nt = len(ptr) - 1
+    assert nt == len(want)
+    total = 0
+    for t in range(nt):
+        got = vid[ptr[t]:ptr[t + 1]]
+        assert np.array_equal(got, want[t]), t
+        total += len(got)
+    assert total > C * off.shape[1] // 2
