@@ -20,17 +20,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, `jobs` at a time; 0: one per CPU,
+    at most 16) and link libhemo.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    os.makedirs(os.path.join(CSRC, "_build"), exist_ok=True)
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
-        os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [hipcc, "-c", os.path.join(CSRC, src), "-o", obj] + [f for f in FLAGS if f != "-shared"]
+        cmds.append([hipcc, "-c", os.path.join(CSRC, src), "-o", obj] + [f for f in FLAGS if f != "-shared"])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    n = jobs or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        list(ex.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-o", tmp] + objs + ["-shared", "-fPIC", "--offload-arch=gfx950"]
     subprocess.run(cmd, check=True)

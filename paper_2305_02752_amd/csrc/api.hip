@@ -410,6 +410,7 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
   if (lat->ibm_kernel != HC_PHI4 && lat->ibm_kernel != HC_PHI2)
     return fail(nullptr, HC_ERR_ARG, "ibm_kernel must be HC_PHI4 or HC_PHI2");
   if (max_cells < 0) return fail(nullptr, HC_ERR_ARG, "max_cells < 0");
+  if (max_cells >= (1 << 20)) return fail(nullptr, HC_ERR_UNSUPPORTED, "2^20 cells or more");
   if (mesh && (int64_t)max_cells * mesh->n_vert >= ((int64_t)1 << 26))
     return fail(nullptr, HC_ERR_UNSUPPORTED, "more than 2^26 vertices");
   int walls = 0, wall_axis = -1;
@@ -447,6 +448,17 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     L.uhi[d] = lat->wall_u_hi[d];
   }
   L.wall_axis = wall_axis;
+  {
+    static const int ex[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static const int ey[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static const int ez[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    for (int q = 0; q < kQ; ++q) {
+      const double w = q == 0 ? 1.0 / 3 : (q < 7 ? 1.0 / 18 : 1.0 / 36);
+      const bool on = wall_axis >= 0;
+      L.wc_lo[q] = on ? (float)(-6.0 * w * (ex[q] * L.ulo[0] + ey[q] * L.ulo[1] + ez[q] * L.ulo[2])) : 0.f;
+      L.wc_hi[q] = on ? (float)(-6.0 * w * (ex[q] * L.uhi[0] + ey[q] * L.uhi[1] + ez[q] * L.uhi[2])) : 0.f;
+    }
+  }
   L.tau = lat->tau;
   L.omega = 1.0f / lat->tau;
   L.kernel = lat->ibm_kernel;

@@ -57,6 +57,8 @@ struct Lattice {
   float tau, omega;
   float g[3];               // body force density
   float ulo[3], uhi[3];     // wall velocities (wall axis only)
+  float wc_lo[kQ], wc_hi[kQ];   // Ladd's moving-wall coefficients -6 w_q (e_q . u_wall) of the
+                                // lower and upper wall (0 without a wall)
   int kernel;               // 4 or 2
   int le;                   // Lees-Edwards images across z (flow along x)
   float le_u;               // image velocity U

@@ -22,30 +22,43 @@ __device__ constexpr float wq[kQ] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f
 __device__ constexpr int opp[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 // g: shifted populations in, post-collision shifted populations out.
+//
+// Directions come in opposite pairs (a, a + 1) for odd a, e_{a+1} = -e_a.
+// Within a pair the equilibrium and the Guo source split into a part even
+// in e (the same for both) and a part odd in e (opposite signs):
+//   f_eq = w [drho - 3/2 rho u.u + 9/2 rho (e.u)^2] +- 3 w rho (e.u),
+//   S    = (1 - omega/2) w [9 (e.u)(e.F) - 3 u.F] +- 3 (1 - omega/2) w (e.F),
+// so each pair is relaxed from one even and one odd term.
 __device__ inline void collide(float (&g)[kQ], float fx, float fy, float fz, float omega,
                                float& rho, float& ux, float& uy, float& uz) {
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  float drho = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    drho += g[i];
-    jx += cx[i] * g[i];
-    jy += cy[i] * g[i];
-    jz += cz[i] * g[i];
+  for (int a = 1; a < kQ; a += 2) {
+    const float d = g[a] - g[a + 1];
+    drho += g[a] + g[a + 1];
+    jx += cx[a] * d;
+    jy += cy[a] * d;
+    jz += cz[a] * d;
   }
   rho = 1.f + drho;
   const float inv = 1.f / rho;
   ux = (jx + 0.5f * fx) * inv;
   uy = (jy + 0.5f * fy) * inv;
   uz = (jz + 0.5f * fz) * inv;
-  const float src = 1.f - 0.5f * omega;
+  const float src = 1.f - 0.5f * omega, keep = 1.f - omega;
   const float uu = ux * ux + uy * uy + uz * uz;
   const float uF = ux * fx + uy * fy + uz * fz;
+  const float c0 = drho - 1.5f * rho * uu;   // f_eq / w at e = 0
+  g[0] = keep * g[0] + wq[0] * (omega * c0 - 3.f * src * uF);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const float eu = cx[i] * ux + cy[i] * uy + cz[i] * uz;
-    const float eF = cx[i] * fx + cy[i] * fy + cz[i] * fz;
-    const float geq = wq[i] * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
-    g[i] = g[i] - omega * (g[i] - geq) + src * wq[i] * (3.f * (eF - uF) + 9.f * eu * eF);
+  for (int a = 1; a < kQ; a += 2) {
+    const float w = wq[a];
+    const float eu = cx[a] * ux + cy[a] * uy + cz[a] * uz;
+    const float eF = cx[a] * fx + cy[a] * fy + cz[a] * fz;
+    const float even = omega * w * (c0 + 4.5f * rho * eu * eu) + src * w * (9.f * eu * eF - 3.f * uF);
+    const float odd = 3.f * w * (omega * rho * eu + src * eF);
+    g[a] = keep * g[a] + (even + odd);
+    g[a + 1] = keep * g[a + 1] + (even - odd);
   }
 }
 

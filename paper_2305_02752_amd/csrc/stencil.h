@@ -9,9 +9,27 @@
 
 namespace hc {
 
+// p mod n in [0, n).  Positions within one period of the range, which is
+// every stencil position of a vertex near the lattice, take one compare and
+// add; others the exact remainder.
 __host__ __device__ inline int wrap(int p, int n) {
-  p %= n;
-  return p < 0 ? p + n : p;
+  int q = p < 0 ? p + n : (p >= n ? p - n : p);
+  if (q < 0 || q >= n) {
+    q = p % n;
+    q = q < 0 ? q + n : q;
+  }
+  return q;
+}
+
+// floor(a / n) for 0 <= a < 2^31 and a quotient below 2^20, from a float
+// reciprocal r of n (within one ulp): the float quotient is then within a
+// quarter unit, so one exact correction makes it right.
+__device__ inline int div_small(int a, int n, float r) {
+  int q = (int)((float)a * r);
+  const int m = a - q * n;
+  q += m >= n ? 1 : 0;
+  q -= m < 0 ? 1 : 0;
+  return q;
 }
 
 __device__ inline float phi4(float r) {
