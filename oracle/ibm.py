@@ -21,12 +21,20 @@ import numpy as np
 WALL = 1
 
 
+def _abs(r):
+    """|r| for real arrays; for complex ones (the complex-step gradient) the
+    sign is decided by the real part, which continues |r| analytically."""
+    r = np.asarray(r)
+    r = r if np.iscomplexobj(r) else r.astype(np.float64)
+    return np.where(r.real < 0.0, -r, r)
+
+
 def phi4(r):
     """Peskin's 4-point regularised delta function (Peskin 2002)."""
-    r = np.abs(np.asarray(r, dtype=np.float64))
+    r = _abs(r)
     out = np.zeros_like(r)
-    a = r <= 1.0
-    b = (r > 1.0) & (r < 2.0)
+    a = r.real <= 1.0
+    b = (r.real > 1.0) & (r.real < 2.0)
     out[a] = (3.0 - 2.0 * r[a] + np.sqrt(1.0 + 4.0 * r[a] - 4.0 * r[a] ** 2)) / 8.0
     out[b] = (5.0 - 2.0 * r[b] - np.sqrt(-7.0 + 12.0 * r[b] - 4.0 * r[b] ** 2)) / 8.0
     return out
@@ -34,8 +42,21 @@ def phi4(r):
 
 def phi2(r):
     """Linear hat max(0, 1 - |r|)."""
-    r = np.abs(np.asarray(r, dtype=np.float64))
-    return np.maximum(0.0, 1.0 - r)
+    r = _abs(r)
+    return np.where(r.real < 1.0, 1.0 - r, 0.0)
+
+
+def _array(a):
+    """float64 array, or complex128 for the complex-step gradient."""
+    a = np.asarray(a)
+    return a.astype(np.complex128 if np.iscomplexobj(a) else np.float64)
+
+
+def _scatter_add(idx, val, n):
+    """Sums of val over equal idx, length n (real and imaginary parts apart)."""
+    if np.iscomplexobj(val):
+        return np.bincount(idx, weights=val.real, minlength=n) + 1j * np.bincount(idx, weights=val.imag, minlength=n)
+    return np.bincount(idx, weights=val, minlength=n)
 
 
 def _stencil(kernel: int):
@@ -48,7 +69,7 @@ def _stencil(kernel: int):
 
 def _axis_nodes(x, k, n, bc):
     """Node index along one axis for offset k, and whether it is inside the fluid."""
-    node = np.floor(x).astype(np.int64) + k
+    node = np.floor(np.real(x)).astype(np.int64) + k
     if bc == WALL:
         inside = (node >= 0) & (node < n)
         return node, inside
@@ -62,23 +83,23 @@ def spread(X: np.ndarray, Fv: np.ndarray, dims, bc, kernel: int = 4) -> np.ndarr
     """
     phi, ks = _stencil(kernel)
     nx, ny, nz = dims
-    out = np.zeros((3, nz * ny * nx))
-    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
-    Fv = np.asarray(Fv, dtype=np.float64).reshape(-1, 3)
+    X = _array(X).reshape(-1, 3)
+    Fv = _array(Fv).reshape(-1, 3)
+    out = np.zeros((3, nz * ny * nx), dtype=np.result_type(X, Fv))
     for kz in ks:
         iz, okz = _axis_nodes(X[:, 2], kz, nz, bc[2])
-        wz = phi(X[:, 2] - (np.floor(X[:, 2]) + kz))
+        wz = phi(X[:, 2] - (np.floor(X[:, 2].real) + kz))
         for ky in ks:
             iy, oky = _axis_nodes(X[:, 1], ky, ny, bc[1])
-            wy = phi(X[:, 1] - (np.floor(X[:, 1]) + ky))
+            wy = phi(X[:, 1] - (np.floor(X[:, 1].real) + ky))
             for kx in ks:
                 ix, okx = _axis_nodes(X[:, 0], kx, nx, bc[0])
-                wx = phi(X[:, 0] - (np.floor(X[:, 0]) + kx))
+                wx = phi(X[:, 0] - (np.floor(X[:, 0].real) + kx))
                 ok = okx & oky & okz
                 w = (wx * wy * wz)[ok]
                 s = ((iz * ny + iy) * nx + ix)[ok]
                 for d in range(3):
-                    out[d] += np.bincount(s, weights=w * Fv[ok, d], minlength=out.shape[1])
+                    out[d] += _scatter_add(s, w * Fv[ok, d], out.shape[1])
     return out.reshape(3, nz, ny, nx)
 
 
@@ -92,11 +113,11 @@ def interpolate(u: np.ndarray, X: np.ndarray, dims, bc, wall_u_lo, wall_u_hi,
     phi, ks = _stencil(kernel)
     nx, ny, nz = dims
     n = (nx, ny, nz)
-    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    X = _array(X).reshape(-1, 3)
     uf = u.reshape(3, -1)
     lo = np.asarray(wall_u_lo, dtype=np.float64)
     hi = np.asarray(wall_u_hi, dtype=np.float64)
-    U = np.zeros_like(X)
+    U = np.zeros(X.shape, dtype=np.result_type(X, uf))
     for kz in ks:
         for ky in ks:
             for kx in ks:
@@ -107,7 +128,7 @@ def interpolate(u: np.ndarray, X: np.ndarray, dims, bc, wall_u_lo, wall_u_hi,
                 below = np.zeros(X.shape[0], dtype=bool)
                 above = np.zeros(X.shape[0], dtype=bool)
                 for d in range(3):
-                    node = np.floor(X[:, d]).astype(np.int64) + kk[d]
+                    node = np.floor(X[:, d].real).astype(np.int64) + kk[d]
                     w = w * phi(X[:, d] - node)
                     if bc[d] == WALL:
                         below |= node < 0

@@ -60,6 +60,27 @@ class Topology:
         self.hinges = np.array(hinges, dtype=np.int64)[order]   # (i, j, k, l)
 
 
+def _norm(v):
+    """Euclidean norm over the last axis, sqrt(v . v) (for complex input, the
+    complex-step gradient, its analytic continuation)."""
+    return np.sqrt((v * v).sum(axis=-1))
+
+
+def _atan2(s, c):
+    """atan2 of real arrays; for complex ones (the complex-step gradient) the
+    real angle plus its first-order change, (c ds - s dc) / (s^2 + c^2),
+    carried in the imaginary part."""
+    if not (np.iscomplexobj(s) or np.iscomplexobj(c)):
+        return np.arctan2(s, c)
+    s, c = np.asarray(s, dtype=np.complex128), np.asarray(c, dtype=np.complex128)
+    return np.arctan2(s.real, c.real) + 1j * (c.real * s.imag - s.real * c.imag) / (s.real ** 2 + c.real ** 2)
+
+
+def _as_array(X):
+    X = np.asarray(X)
+    return X.astype(np.complex128 if np.iscomplexobj(X) else np.float64)
+
+
 def triangle_normals(X, tri):
     """Unnormalised normals (x_j - x_i) x (x_k - x_i), per triangle."""
     a, b, c = X[..., tri[:, 0], :], X[..., tri[:, 1], :], X[..., tri[:, 2], :]
@@ -72,7 +93,7 @@ def area_volume(X, tri):
     X: [..., V, 3].  Volume uses the first vertex of each cell as origin.
     """
     N = triangle_normals(X, tri)
-    A = 0.5 * np.linalg.norm(N, axis=-1).sum(axis=-1)
+    A = 0.5 * _norm(N).sum(axis=-1)
     o = X[..., :1, :]
     a, b, c = X[..., tri[:, 0], :] - o, X[..., tri[:, 1], :] - o, X[..., tri[:, 2], :] - o
     V = (a * np.cross(b, c)).sum(axis=-1).sum(axis=-1) / 6.0
@@ -85,16 +106,16 @@ def dihedral(X, hinges):
     e = xj - xi
     n1 = np.cross(xj - xi, xk - xi)
     n2 = np.cross(xi - xj, xl - xj)
-    n1h = n1 / np.linalg.norm(n1, axis=-1, keepdims=True)
-    n2h = n2 / np.linalg.norm(n2, axis=-1, keepdims=True)
-    eh = e / np.linalg.norm(e, axis=-1, keepdims=True)
+    n1h = n1 / _norm(n1)[..., None]
+    n2h = n2 / _norm(n2)[..., None]
+    eh = e / _norm(e)[..., None]
     s = (np.cross(n1h, n2h) * eh).sum(axis=-1)
     c = (n1h * n2h).sum(axis=-1)
-    return np.arctan2(s, c)
+    return _atan2(s, c)
 
 
 def edge_lengths(X, edges):
-    return np.linalg.norm(X[..., edges[:, 1], :] - X[..., edges[:, 0], :], axis=-1)
+    return _norm(X[..., edges[:, 1], :] - X[..., edges[:, 0], :])
 
 
 class RestState:
@@ -112,7 +133,8 @@ class RestState:
 
 
 def _g(x, lim):
-    x = np.clip(x, -CLAMP * lim, CLAMP * lim)
+    c = CLAMP * lim   # clamped on the real part (a clamped argument has zero derivative)
+    x = np.where(np.real(x) > c, c, np.where(np.real(x) < -c, -c, x))
     return x + x / (lim * lim - x * x)
 
 
@@ -120,7 +142,7 @@ def link_forces(X, topo, rest):
     """F_link: -dE_link/dx, per vertex.  X [..., V, 3]."""
     i, j = topo.edges[:, 0], topo.edges[:, 1]
     d = X[..., j, :] - X[..., i, :]
-    L = np.linalg.norm(d, axis=-1)
+    L = _norm(d)
     s = (L - rest.L0) / rest.L0
     f = (_g(s, TAU_LINK) / L)[..., None] * d          # force on i
     F = np.zeros_like(X)
@@ -162,7 +184,7 @@ def area_gradient(X, tri):
     """dA/dx per vertex: for triangle (v, j, k), 1/2 n_hat x (x_k - x_j)."""
     G = np.zeros_like(X)
     N = triangle_normals(X, tri)
-    nh = N / np.linalg.norm(N, axis=-1, keepdims=True)
+    nh = N / _norm(N)[..., None]
     for r in range(3):
         v, j, k = tri[:, r], tri[:, (r + 1) % 3], tri[:, (r + 2) % 3]
         _scatter(G, v, 0.5 * np.cross(nh, X[..., k, :] - X[..., j, :]))
@@ -182,9 +204,9 @@ def volume_gradient(X, tri):
 def forces(X, k, topo, rest, traction=None, terms=("link", "bend", "area", "volume")):
     """Total membrane force per vertex for cells X [C, V, 3] with stiffness
     k [C, 4] = (link, bend, area, volume) and optional traction [C, 3]."""
-    X = np.asarray(X, dtype=np.float64)
-    k = np.asarray(k, dtype=np.float64)
-    F = np.zeros_like(X)
+    X = _as_array(X)
+    k = _as_array(k)
+    F = np.zeros(X.shape, dtype=np.result_type(X, k))
     if "link" in terms:
         F += k[:, 0, None, None] * link_forces(X, topo, rest)
     if "bend" in terms:

@@ -43,11 +43,15 @@ def make_model(lat, rest_pos, tri, k, traction=None, le_u: float = 0.0,
                interior_ratio=1.0) -> Model:
     topo = membrane.Topology(tri, rest_pos.shape[0])
     rest = membrane.RestState(np.asarray(rest_pos, dtype=np.float64), topo)
-    return Model(dims=(lat.nx, lat.ny, lat.nz), bc=tuple(lat.bc), tau=float(lat.tau),
+    # tau and k stay complex when the complex-step gradient perturbs them
+    tau = complex(lat.tau) if np.iscomplexobj(lat.tau) else float(lat.tau)
+    k = np.asarray(k)
+    k = k.astype(np.complex128 if np.iscomplexobj(k) else np.float64)
+    return Model(dims=(lat.nx, lat.ny, lat.nz), bc=tuple(lat.bc), tau=tau,
                  body_force=tuple(float(b) for b in lat.body_force),
                  wall_u_lo=tuple(lat.wall_u_lo), wall_u_hi=tuple(lat.wall_u_hi),
                  kernel=int(lat.ibm_kernel), topo=topo, rest=rest,
-                 k=np.asarray(k, dtype=np.float64),
+                 k=k,
                  traction=None if traction is None else np.asarray(traction, dtype=np.float64),
                  le_u=float(le_u),
                  interior_ratio=(float(interior_ratio) if np.ndim(interior_ratio) == 0
@@ -67,7 +71,7 @@ def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 
     elif C:
         F = ibm.spread(X.reshape(-1, 3), Fv.reshape(-1, 3), m.dims, m.bc, m.kernel)
     else:
-        F = np.zeros((3, nz, ny, nx))
+        F = np.zeros((3, nz, ny, nx), dtype=f.dtype)
     for d in range(3):
         F[d] += m.body_force[d]
     rho, u = lattice.moments(f, F)
@@ -81,8 +85,8 @@ def fluid_step(m: Model, f: np.ndarray, X: np.ndarray, Fv: np.ndarray, t: int = 
         U = np.zeros_like(X)
     tau = m.tau
     ratios = np.broadcast_to(np.asarray(m.interior_ratio, dtype=np.float64), (C,))
-    if C and np.any(ratios != 1.0):
-        tau = interior.tau_field(interior.ratio_field(X, m.topo.tri, m.dims, m.bc, ratios,
+    if C and np.any(ratios != 1.0):   # inside/outside is decided on the real positions
+        tau = interior.tau_field(interior.ratio_field(np.real(X), m.topo.tri, m.dims, m.bc, ratios,
                                                       le_delta=delta if le else 0.0), m.tau)
     post = lattice.collide(f, rho, u, F, tau)
     if le:
