@@ -20,6 +20,7 @@ class AdjointBoxes:
 
     def __init__(self, lattices, rest_pos, tri, cells, targets, n_steps, ckpt_every, device="cuda:0"):
         self.n_steps, self.ckpt_every = int(n_steps), int(ckpt_every)
+        self.generation = 0   # forward evaluations so far; a backward belongs to the latest
         self.targets = np.asarray(targets, dtype=np.float64).reshape(len(lattices), 2)
         self.sims, self.streams, self.start = [], [], []
         for b, lat in enumerate(lattices):
@@ -35,6 +36,7 @@ class AdjointBoxes:
             self.streams.append(s)
 
     def forward(self, params: np.ndarray) -> np.ndarray:
+        self.generation += 1
         loss = np.empty(len(self.sims))
         for b, sim in enumerate(self.sims):
             with torch.cuda.stream(self.streams[b]):
@@ -56,10 +58,16 @@ class CoupledStepFn(torch.autograd.Function):
     def forward(ctx, params: torch.Tensor, runner: AdjointBoxes):
         loss = runner.forward(params.detach().cpu().numpy().astype(np.float64))
         ctx.runner = runner
+        ctx.generation = runner.generation
         return torch.as_tensor(loss, dtype=params.dtype, device=params.device)
 
     @staticmethod
     def backward(ctx, grad_loss: torch.Tensor):
+        # the runner's contexts hold the checkpoints of its latest forward only
+        if ctx.runner.generation != ctx.generation:
+            raise RuntimeError("CoupledStepFn: the runner has evaluated another forward since this one; "
+                               "its reverse sweep would belong to that forward (call backward first, or "
+                               "use one runner per graph)")
         g = ctx.runner.backward()
         gl = grad_loss.detach().cpu().numpy()[:, None]
         return torch.as_tensor(gl * g, dtype=grad_loss.dtype, device=grad_loss.device), None

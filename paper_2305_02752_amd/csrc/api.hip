@@ -643,6 +643,7 @@ static hc_status cells_changed(hc_ctx* c, int32_t n, const float* k, const float
   c->have_cells = n > 0;
   c->advect_pending = false;
   c->have_prev = false;
+  c->adj_ready = false;   // a reverse sweep would recompute with the new cells
   if (c->per_cell_ratio) interior_uniform(c);   // per-cell ratios belong to the old cells
   HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
@@ -916,6 +917,7 @@ hc_status hc_set_integration(hc_ctx* c, int32_t force_every, int32_t scheme) {
   if (force_every < 1) return fail(c, HC_ERR_ARG, "force_every must be >= 1");
   if (scheme != HC_EULER && scheme != HC_AB2) return fail(c, HC_ERR_ARG, "scheme must be HC_EULER or HC_AB2");
   HC_TRY(flush(c));
+  if (force_every != c->force_every || scheme != c->scheme) c->adj_ready = false;
   c->force_every = force_every;
   c->scheme = scheme;
   return HC_OK;
@@ -994,6 +996,7 @@ hc_status hc_set_params(hc_ctx* c, const float* k, float tau) {
   HC_TRY(need_ws(c));
   if (!(tau > 0.5f)) return fail(c, HC_ERR_ARG, "tau must exceed 1/2");
   if (k) HC_TRY(copy_h2d(c, (void*)c->C.k, k, (size_t)c->C.n * 16));
+  c->adj_ready = false;   // the forward's checkpoints were taken under the old parameters
   c->L.tau = tau;
   c->L.omega = 1.0f / tau;
   interior_update(c);

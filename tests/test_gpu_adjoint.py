@@ -65,6 +65,52 @@ def test_adjoint_matches_fd(walls, ratio):
           flush=True)
     assert abs(loss - L_ref) <= 1e-5 * abs(L_ref)
     assert norm <= 1e-4
+    # the oracle's second, difference-free gradient (complex step)
+    g_cs = oadj.cs_gradient(lat, rest, tri, X0, k, cells.traction[0], lat.tau, n, targets,
+                            interior_ratio=ratio)
+    pc = p * g_cs
+    norm_cs = np.linalg.norm(pg - pc) / np.linalg.norm(pc)
+    print(f"  vs complex step: {pc}; norm {norm_cs:.2e}", flush=True)
+    assert norm_cs <= 1e-4
+
+
+def test_adjoint_backward_refers_to_latest_forward():
+    """A parameter change between hc_adj_forward and hc_adj_backward
+    discards the forward (its reverse sweep would recompute under other
+    parameters): the backward is refused until the next forward."""
+    from paper_2305_02752_amd import HemoError
+    lat, rest, tri, cells, targets = _box(4)
+    loss, g, sim = _device_grad(lat, rest, tri, cells, targets, 12, 4)
+    sim.set_params(k=cells.k * 1.1, tau=lat.tau)
+    with pytest.raises(HemoError) as e:
+        sim.adj_backward()
+    assert e.value.code == 2   # HC_ERR_STATE
+    sim.set_params(k=cells.k, tau=lat.tau)
+    with pytest.raises(HemoError):
+        sim.adj_backward()
+
+
+def test_coupled_step_fn_two_forwards_then_backward():
+    """Two applies on one runner, then backward of the first: refused (the
+    contexts hold the second forward's checkpoints); the second's backward
+    is the second's gradient."""
+    import torch
+    from paper_2305_02752_amd.autograd import AdjointBoxes, CoupledStepFn
+    boxes = [_box(20 + b) for b in range(2)]
+    runner = AdjointBoxes([b[0] for b in boxes], boxes[0][1], boxes[0][2], [b[3] for b in boxes],
+                          [b[4] for b in boxes], n_steps=12, ckpt_every=4)
+    p0 = np.array([np.concatenate([b[3].k[0], [b[0].tau]]) for b in boxes])
+    pa = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    pb = torch.tensor(p0 * np.array([1.2, 1.0, 1.0, 1.0, 1.0]), dtype=torch.float64, requires_grad=True)
+    la = CoupledStepFn.apply(pa, runner)
+    lb = CoupledStepFn.apply(pb, runner)
+    with pytest.raises(RuntimeError):
+        la.sum().backward()
+    lb.sum().backward()
+    ref = AdjointBoxes([b[0] for b in boxes], boxes[0][1], boxes[0][2], [b[3] for b in boxes],
+                       [b[4] for b in boxes], n_steps=12, ckpt_every=4)
+    ref.forward(pb.detach().numpy())
+    assert np.array_equal(pb.grad.numpy(), ref.backward())
 
 
 @pytest.mark.parametrize("ratio", [1.0, 5.0])
