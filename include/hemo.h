@@ -304,6 +304,20 @@ hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot
                       int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* hip_stream,
                       double* overlap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * iterations as hc_pack_run, with the packing's scratch (bin lists, counters,
+ * the second centre buffer, overlap sums) in a static array of the library,
+ * 32 MiB per device, held until the process ends; nothing is allocated.
+ * Sizes needing more scratch than that (about 200,000 ellipsoids at the
+ * density of the RBC surrogate suspension) return HC_ERR_UNSUPPORTED, as
+ * hc_pack_query_workspace reports the need.  Every call on one device shares
+ * that device's array and leaves its contents behind (the call clears what
+ * must start at zero): calls that overlap on one device race.  Results are
+ * those of hc_pack_run, bit for bit. */
+hc_status hc_pack_run_static(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
+                             int32_t n, int32_t n_iter, void* hip_stream, double* overlap);
+
 /* Cells from packed ellipsoids without a host round trip (Sec. 2.4: each
  * ellipsoid encloses one cell): the context's rest mesh, rotated by rot
  * (device [n][9], as for hc_pack_run) and translated to centres (device

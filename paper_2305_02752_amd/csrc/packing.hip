@@ -26,6 +26,7 @@
 //      each other, so they cancel exactly.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/hemo.h"
@@ -493,9 +494,66 @@ hc_status hc_pack_query_workspace(const hc_pack_desc* desc, int32_t n, size_t* b
   return HC_OK;
 }
 
+// Scratch memory of hc_pack_run_static, for callers that cannot allocate:
+// one array per device that the library runs on, held until the process
+// ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there, not a device address).
+constexpr size_t kPackStaticBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kPackStaticBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};   // device address of scratch, per device index
+
+// Device address of this device's scratch, resolved once per device with
+// that device current.
+static hc_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return pack_fail(HC_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= 64) return pack_fail(HC_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return pack_fail(HC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HC_OK;
+}
+
+static hc_status pack_run(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
+                          int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* stream,
+                          double* overlap);
+
 hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
                       int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* stream,
                       double* overlap) {
+  return pack_run(desc, centres, rot, semi, n, n_iter, workspace, ws_bytes, stream, overlap);
+}
+
+hc_status hc_pack_run_static(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
+                             int32_t n, int32_t n_iter, void* stream, double* overlap) {
+  PackPlan P;
+  const std::string e = plan_pack(desc, n, P);
+  if (!e.empty()) return pack_fail(HC_ERR_ARG, e);
+  if (P.total > kPackStaticBytes)
+    return pack_fail(HC_ERR_UNSUPPORTED, "hc_pack_run_static: this packing needs " + std::to_string(P.total) +
+                                             " bytes of scratch, above the library's static " +
+                                             std::to_string(kPackStaticBytes) + " (use hc_pack_run)");
+  void* ws = nullptr;
+  const hc_status st = static_scratch(&ws);
+  if (st != HC_OK) return st;
+  return pack_run(desc, centres, rot, semi, n, n_iter, ws, kPackStaticBytes, stream, overlap);
+}
+
+}  // extern "C"
+
+static hc_status pack_run(const hc_pack_desc* desc, float* centres, const float* rot, const float* semi,
+                          int32_t n, int32_t n_iter, void* workspace, size_t ws_bytes, void* stream,
+                          double* overlap) {
   PackPlan P;
   const std::string e = plan_pack(desc, n, P);
   if (!e.empty()) return pack_fail(HC_ERR_ARG, e);
@@ -563,5 +621,3 @@ hc_status hc_pack_run(const hc_pack_desc* desc, float* centres, const float* rot
   }
   return HC_OK;
 }
-
-}  // extern "C"

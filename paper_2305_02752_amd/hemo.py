@@ -83,6 +83,7 @@ def _declare(lib):
         "hc_adj_backward": [_P, _P],
         "hc_pack_query_workspace": [_P, i32, _P],
         "hc_pack_run": [_P, _P, _P, _P, i32, i32, _P, sz, _P, _P],
+        "hc_pack_run_static": [_P, _P, _P, _P, i32, i32, _P, _P],
         "hc_place_cells": [_P, i32, _P, _P, _P, _P],
     }
     for name, args in sig.items():
@@ -418,6 +419,17 @@ class Packer:
                                          C.c_void_p(rot.data_ptr()), C.c_void_p(semi.data_ptr()), n,
                                          int(n_iter), C.c_void_p(ws), nbytes, C.c_void_p(stream),
                                          _ptr(out) if measure else None))
+        return tuple(out) if measure else None
+
+    def run_device_static(self, centres, rot, semi, n_iter: int, measure: bool = True):
+        """As run_device, through hc_pack_run_static: the library's static
+        per-device scratch instead of a workspace (nothing allocated)."""
+        n = int(centres.shape[0])
+        out = np.zeros(4, dtype=np.float64)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.hc_pack_run_static(C.byref(self.desc), C.c_void_p(centres.data_ptr()),
+                                                C.c_void_p(rot.data_ptr()), C.c_void_p(semi.data_ptr()), n,
+                                                int(n_iter), C.c_void_p(stream), _ptr(out) if measure else None))
         return tuple(out) if measure else None
 
     def run(self, centres, rot, semi, n_iter: int):
