@@ -318,7 +318,7 @@ __host__ __device__ inline int tile_grid(const Lattice& L) { return ((L.ntiles +
 // distances 1 + f, f, 1 - f, 2 - f).
 //
 // Spreading accumulates in LDS as int32 fixed point (node contributions
-// rounded to nearest) at a power-of-two scale chosen per tile from a bound
+// truncated) at a power-of-two scale chosen per tile from a bound
 // on every node sum: the sum over the tile's entries of their largest force
 // component times the largest weight one entry puts on one node.  The bound
 // is summed in integers (each term rounded up on a 2^-19 grid of the tile's
@@ -602,9 +602,9 @@ __device__ __forceinline__ void spread(int m, float scale, Smem& S) {
         for (int ix = 0; ix < K; ++ix) {
           if (ix >= X.n) continue;
           const int li = row + X.l[ix];
-          atomicAdd(&S.acc[0][li], __float2int_rn(wzy * gx[ix]));
-          atomicAdd(&S.acc[1][li], __float2int_rn(wzy * gy[ix]));
-          atomicAdd(&S.acc[2][li], __float2int_rn(wzy * gz[ix]));
+          atomicAdd(&S.acc[0][li], (int)(wzy * gx[ix]));
+          atomicAdd(&S.acc[1][li], (int)(wzy * gy[ix]));
+          atomicAdd(&S.acc[2][li], (int)(wzy * gz[ix]));
         }
       }
     }
