@@ -20,7 +20,7 @@ using namespace hc;
 
 namespace {
 
-constexpr int kMaxCellTiles = 216;   // 6 tiles per axis per cell
+constexpr int kMaxCellTiles = 512;   // cell cover read-out: 8 tiles per axis per cell
 thread_local std::string g_create_error;
 
 struct Layout {

@@ -304,7 +304,7 @@ class Simulation:
         tptr = np.empty(nt + 1, dtype=np.int32)
         cptr = np.empty(nt + 1, dtype=np.int32)
         cap_t = self.n_cells * self.nv * 27
-        cap_c = self.n_cells * 216
+        cap_c = self.n_cells * 512   # a cell covers at most 8 tiles per axis in the read-out
         touch = np.empty(max(cap_t, 1), dtype=np.int32)
         cells = np.empty(max(cap_c, 1), dtype=np.int32)
         self._check(self.lib.hc_read_bins(self.ctx, _ptr(owner), _ptr(tptr), _ptr(touch), touch.size,

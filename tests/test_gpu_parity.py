@@ -174,6 +174,38 @@ def test_binning_bit_exact(kernel, walls):
     assert np.array_equal(tptr, tptr_r) and np.array_equal(touch, touch_r)
 
 
+@pytest.mark.parametrize("scale,n", [(2.8, (72, 64, 56)), (1.0, (24, 24, 24))])
+def test_binning_bit_exact_cell_sizes(scale, n):
+    """A cell reaching more than 6 tiles per axis (its pairs are ranked in
+    the LDS hash), and a cell reaching every tile of a 3-tile lattice (the
+    direct table over the whole cyclic axis)."""
+    from workloads import rbc_mesh
+    from workloads.configs import random_rotation
+    rng = np.random.default_rng(31)
+    rest64, tri = rbc_mesh()
+    lat = Lattice(*n)
+    rot = np.eye(3) if scale > 2 else random_rotation(rng)   # the large cell's diameter along x
+    cells = place_cells(scale * rest64, np.array(n, dtype=float)[None] / 2 + rng.uniform(-1, 1, (1, 3)),
+                        rot[None], K_REF[None])
+    cells = jitter_cells(rng, cells, 0.05)
+    from types import SimpleNamespace
+    sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=(scale * rest64).astype(np.float32), tri=tri,
+                                   cells=cells), cells)
+    sim.step(2)
+    sim.sync()
+    owner, tptr, touch, cptr, clist = sim.read_bins()
+    o, off, _ = sim.read_vertices()
+    dims = (lat.nx, lat.ny, lat.nz)
+    ow, _, _, cptr_r, clist_r = binning.bins(o, off, dims, lat.bc)
+    tptr_r, touch_r = binning.touch_lists(o, off, dims, lat.bc, 4)
+    assert np.array_equal(owner, ow)
+    assert np.array_equal(cptr, cptr_r) and np.array_equal(clist, clist_r)
+    assert np.array_equal(tptr, tptr_r) and np.array_equal(touch, touch_r)
+    if scale > 2:
+        x = o[0, 0] + off[0, :, 0]
+        assert x.max() - x.min() > 5 * 8   # beyond the direct table's 6 tiles
+
+
 def test_deterministic_bitwise():
     w = tiny_periodic(seed=15, n=(32, 24, 24), n_cells=3, body=(1e-5, 0, 0))
     rng = np.random.default_rng(7)
