@@ -153,7 +153,11 @@ hc_status hc_set_field_output(hc_ctx* ctx, int32_t enable);
 hc_status hc_read_force_field(hc_ctx* ctx, float* f, int64_t n_sites);
 
 /* Current cells; vertex_force = membrane forces of the last evaluation
- * (may be NULL).  Counts: origin 3C, offsets and force 3CV. */
+ * (may be NULL).  Counts: origin 3C, offsets and force 3CV.  Each offset
+ * coordinate is kept as a float plus a float low part that carries the
+ * rounding of every move (so that a slowly moving vertex does not drift by
+ * up to half an ulp per step); the offsets read here are the high parts, and
+ * hc_write_vertices, hc_set_cells and hc_place_cells clear the low parts. */
 hc_status hc_read_vertices(hc_ctx* ctx, int32_t* origin, float* offsets, float* vertex_force,
                            int64_t n_cells);
 hc_status hc_write_vertices(hc_ctx* ctx, const int32_t* origin, const float* offsets,
@@ -184,7 +188,7 @@ hc_status hc_num_tiles(const hc_ctx* ctx, int32_t* n_tiles);
 
 /* Checkpoint (Sec. 2.6: pause, save, continue): the step counter and
  * integration settings, the stored lattice state (the library's own
- * layout), cell origins and offsets, the last vertex velocities and the
+ * layout), cell origins and offsets (with their low parts), the last vertex velocities and the
  * held vertex forces -- everything a resumed run needs to continue bit for
  * bit, also in the middle of a force-refresh interval.  The buffer is
  * opaque to the caller; restore checks the cell count. */

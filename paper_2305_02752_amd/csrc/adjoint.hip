@@ -39,8 +39,18 @@ using lbm::cz;
 using lbm::opp;
 using lbm::wq;
 
-__global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ lam1,
-                                                     float* __restrict__ lam0,
+// Lattice weight of direction j, exact in FP64.
+__device__ __forceinline__ double wq64(int j) { return j == 0 ? 1.0 / 3 : (j < 7 ? 1.0 / 18 : 1.0 / 36); }
+
+// The collision VJP in FP64 from FP32 inputs (stored populations, force
+// density, lam_u), with FP64 population cotangents.  The part of lam_f that
+// d/d omega sees is its non-hydrodynamic (second-moment) part, which arises
+// from differences between neighbouring sites' projections; an FP32 lam_f
+// stores those projections to 7 digits and loses most of the differences in
+// smooth regions, and an FP32 f_eq repeats the same rounding across a smooth
+// flow, so both would bias the sum over every site and step.
+__global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ lam1,
+                                                     double* __restrict__ lam0,
                                                      const float* __restrict__ h0,
                                                      const float* __restrict__ F,
                                                      const float* __restrict__ lamu,
@@ -57,7 +67,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
   if (s < N && node_of(L, s, x, y, z)) {
     // a site inside a cell relaxes with the interior rate (the marks of
     // this step's positions, cleared once read)
-    float om = L.omega;
+    double om = L.omega;
     bool inside = false;
     if (mask) {
       const unsigned b = mask[s];
@@ -70,12 +80,12 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
     }
     // cotangent of the post-collision values stored at this node; a value
     // stored for a bounce-back carries the wall term c rho
-    float ls[kQ];
-    float lrho = 0.f;
+    double ls[kQ];
+    double lrho = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       ls[i] = lam1[i * N + s];
-      lrho += lbm::wall_coeff(L, i, x, y, z) * ls[i];
+      lrho += (double)lbm::wall_coeff(L, i, x, y, z) * ls[i];
     }
     // pre-collision populations, pulled as in the forward step
     float g[kQ];
@@ -86,52 +96,54 @@ __global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ l
       from[i] = lbm::pull_source(L, i, x, y, z, &qs[i]);
       g[i] = h0[qs[i] * N + from[i]];
     }
-    const float fx = F[s], fy = F[N + s], fz = F[2 * N + s];
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    const double fx = F[s], fy = F[N + s], fz = F[2 * N + s];
+    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       drho += g[i];
-      jx += cx[i] * g[i];
-      jy += cy[i] * g[i];
-      jz += cz[i] * g[i];
+      jx += cx[i] * (double)g[i];
+      jy += cy[i] * (double)g[i];
+      jz += cz[i] * (double)g[i];
     }
-    const float rho = 1.f + drho, inv = 1.f / rho;
-    const float ux = (jx + 0.5f * fx) * inv, uy = (jy + 0.5f * fy) * inv, uz = (jz + 0.5f * fz) * inv;
-    const float src = 1.f - 0.5f * om;
-    const float uu = ux * ux + uy * uy + uz * uz, uF = ux * fx + uy * fy + uz * fz;
-    float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
+    const double rho = 1.0 + drho, inv = 1.0 / rho;
+    const double ux = (jx + 0.5 * fx) * inv, uy = (jy + 0.5 * fy) * inv, uz = (jz + 0.5 * fz) * inv;
+    const double src = 1.0 - 0.5 * om;
+    const double uu = ux * ux + uy * uy + uz * uz, uF = ux * fx + uy * fy + uz * fz;
+    double A = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0, t = 0.0;
 #pragma unroll
     for (int j = 0; j < kQ; ++j) {
-      const float eu = cx[j] * ux + cy[j] * uy + cz[j] * uz;
-      const float eF = cx[j] * fx + cy[j] * fy + cz[j] * fz;
-      const float phi = 1.f + 3.f * eu + 4.5f * eu * eu - 1.5f * uu;
-      A += ls[j] * wq[j] * phi;                       // d f_eq / d rho at fixed u
-      const float cu = om * wq[j] * rho, cs = src * wq[j];
+      const double w = wq64(j);
+      const double eu = cx[j] * ux + cy[j] * uy + cz[j] * uz;
+      const double eF = cx[j] * fx + cy[j] * fy + cz[j] * fz;
+      const double phi = 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+      A += ls[j] * w * phi;                            // d f_eq / d rho at fixed u
+      const double cu = om * w * rho, cs = src * w;
       // omega d f_eq/du + (1 - omega/2) dS/du
-      Bx += ls[j] * (cu * (3.f * cx[j] + 9.f * eu * cx[j] - 3.f * ux) + cs * (-3.f * fx + 9.f * eF * cx[j]));
-      By += ls[j] * (cu * (3.f * cy[j] + 9.f * eu * cy[j] - 3.f * uy) + cs * (-3.f * fy + 9.f * eF * cy[j]));
-      Bz += ls[j] * (cu * (3.f * cz[j] + 9.f * eu * cz[j] - 3.f * uz) + cs * (-3.f * fz + 9.f * eF * cz[j]));
+      Bx += ls[j] * (cu * (3.0 * cx[j] + 9.0 * eu * cx[j] - 3.0 * ux) + cs * (-3.0 * fx + 9.0 * eF * cx[j]));
+      By += ls[j] * (cu * (3.0 * cy[j] + 9.0 * eu * cy[j] - 3.0 * uy) + cs * (-3.0 * fy + 9.0 * eF * cy[j]));
+      Bz += ls[j] * (cu * (3.0 * cz[j] + 9.0 * eu * cz[j] - 3.0 * uz) + cs * (-3.0 * fz + 9.0 * eF * cz[j]));
       // (1 - omega/2) dS/dF at fixed u
-      Gx += ls[j] * cs * (3.f * (cx[j] - ux) + 9.f * eu * cx[j]);
-      Gy += ls[j] * cs * (3.f * (cy[j] - uy) + 9.f * eu * cy[j]);
-      Gz += ls[j] * cs * (3.f * (cz[j] - uz) + 9.f * eu * cz[j]);
-      const float geq = wq[j] * (drho + rho * (phi - 1.f));
-      const float S = wq[j] * (3.f * (eF - uF) + 9.f * eu * eF);
-      const double d = (double)(ls[j] * (-(g[j] - geq) - 0.5f * S));
-      if (inside) dom_in += d;
-      else dom += d;
+      Gx += ls[j] * cs * (3.0 * (cx[j] - ux) + 9.0 * eu * cx[j]);
+      Gy += ls[j] * cs * (3.0 * (cy[j] - uy) + 9.0 * eu * cy[j]);
+      Gz += ls[j] * cs * (3.0 * (cz[j] - uz) + 9.0 * eu * cz[j]);
+      // d h / d omega = -(f - f_eq) - S / 2
+      const double geq = w * (drho + rho * (phi - 1.0));
+      const double S = w * (3.0 * (eF - uF) + 9.0 * eu * eF);
+      t += ls[j] * (-((double)g[j] - geq) - 0.5 * S);
     }
+    if (inside) dom_in = t;
+    else dom = t;
     A = om * A + lrho;
     Bx += lamu[s];
     By += lamu[N + s];
     Bz += lamu[2 * N + s];
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      lam0[qs[i] * N + from[i]] = (1.f - om) * ls[i] + A +
+      lam0[qs[i] * N + from[i]] = (1.0 - om) * ls[i] + A +
                                  (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
-    lamF[s] = Gx + 0.5f * Bx * inv;
-    lamF[N + s] = Gy + 0.5f * By * inv;
-    lamF[2 * N + s] = Gz + 0.5f * Bz * inv;
+    lamF[s] = (float)(Gx + 0.5 * Bx * inv);
+    lamF[N + s] = (float)(Gy + 0.5 * By * inv);
+    lamF[2 * N + s] = (float)(Gz + 0.5 * Bz * inv);
   }
   // per-block sums for the plasma sites and for each viscosity class, in a
   // fixed order (each block owns its slots across steps)
@@ -415,7 +427,7 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 
 }  // namespace
 
-hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
+hipError_t launch_adj_collide(const double* lam1, double* lam0, const float* g0, const float* F,
                               const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
                               double* domega_in_part, const Lattice& L, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.np + 255) / 256)), dim3(256), 0, s, lam1, lam0,

@@ -85,15 +85,16 @@ struct hc_ctx {
   char* adj_ws = nullptr;
   int adj_n = 0, adj_ck = 0, adj_nseg = 0;
   bool adj_ready = false;
-  float *ck_pops = nullptr, *ck_off = nullptr;
+  float *ck_pops = nullptr, *ck_off = nullptr, *ck_lo = nullptr, *sg_lo = nullptr;
   float *sg_pops = nullptr, *sg_off = nullptr, *sg_F = nullptr, *sg_Fv = nullptr;
   float4* sg_macro = nullptr;
-  float *lam_f[2] = {nullptr, nullptr}, *lam_X[2] = {nullptr, nullptr};
+  double* lam_f[2] = {nullptr, nullptr};   // population cotangents (FP64)
+  float* lam_X[2] = {nullptr, nullptr};
   float *lam_Fv = nullptr, *lam_u = nullptr, *lam_F = nullptr, *vel_scratch = nullptr;
   double *dom_part = nullptr, *dk = nullptr, *loss = nullptr, *targets = nullptr, *scal = nullptr;
   double* dom_in_part = nullptr;   // d/d omega_in partial sums (sites inside cells)
   // workspace offsets
-  size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_force, o_vel, o_k, o_trac, o_area, o_vol;
+  size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_lo, o_force, o_vel, o_k, o_trac, o_area, o_vol;
   size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
   size_t o_owner, o_ntouch, o_scan, o_slot, o_tcnt, o_tptr, o_touch, o_csr, o_flags;
   size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist, o_mask, o_cclass, o_rest;
@@ -133,6 +134,7 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_macro = lay.add(N * 16);
   c->o_origin = lay.add(C * 3 * 4);
   c->o_off = lay.add(C * nv * 3 * 4);
+  c->o_lo = lay.add(C * nv * 3 * 4);
   c->o_force = lay.add(C * nv * 3 * 4);
   c->o_vel = lay.add(C * nv * 3 * 4);
   c->o_k = lay.add(C * 4 * 4);
@@ -304,7 +306,7 @@ hc_status run_steps(hc_ctx* c, int n) {
 
 struct AdjPlan {
   size_t total = 0;
-  size_t ck_pops, ck_off, sg_pops, sg_off, sg_F, sg_macro, sg_Fv, lf0, lf1, lx0, lx1, lfv, lu, lF, vel,
+  size_t ck_pops, ck_off, ck_lo, sg_lo, sg_pops, sg_off, sg_F, sg_macro, sg_Fv, lf0, lf1, lx0, lx1, lfv, lu, lF, vel,
       dom, dom_in, dk, loss, tg, scal;
 };
 
@@ -315,13 +317,15 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   const int64_t nck = (n + ck - 1) / ck, C = c->max_cells;
   p.ck_pops = L.add(nck * P * 4);
   p.ck_off = L.add(nck * X * 4);
+  p.ck_lo = L.add(nck * X * 4);
+  p.sg_lo = L.add(X * 4);
   p.sg_pops = L.add((ck + 1) * P * 4);
   p.sg_off = L.add((ck + 1) * X * 4);
   p.sg_F = L.add(ck * 3 * N * 4);
   p.sg_macro = L.add(ck * N * 16);
   p.sg_Fv = L.add(ck * X * 4);
-  p.lf0 = L.add(P * 4);
-  p.lf1 = L.add(P * 4);
+  p.lf0 = L.add(P * 8);
+  p.lf1 = L.add(P * 8);
   p.lx0 = L.add(X * 4);
   p.lx1 = L.add(X * 4);
   p.lfv = L.add(X * 4);
@@ -347,6 +351,7 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   Cells Ci = c->C;
   Ci.off = c->sg_off + i * X;
+  Ci.lo = c->sg_lo;   // carried in place through the segment, from its checkpoint
   Ci.force = c->sg_Fv + i * X;
   Ci.vel = c->vel_scratch;
   float* Fi = c->sg_F + i * 3 * N;
@@ -371,10 +376,11 @@ hc_status adj_reverse_step(hc_ctx* c, int i, int a) {
   const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   Cells Ci = c->C;
   Ci.off = c->sg_off + i * X;
+  Ci.lo = c->sg_lo;   // carried in place through the segment, from its checkpoint
   Ci.force = c->sg_Fv + i * X;
   Ci.vel = c->vel_scratch;
-  float* lf1 = c->lam_f[a];
-  float* lf0 = c->lam_f[a ^ 1];
+  double* lf1 = c->lam_f[a];
+  double* lf0 = c->lam_f[a ^ 1];
   float* lx1 = c->lam_X[a];
   float* lx0 = c->lam_X[a ^ 1];
   HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
@@ -453,10 +459,11 @@ hc_status hc_create(const hc_lattice_desc* lat, const hc_mesh_desc* mesh, int32_
     static const int ey[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
     static const int ez[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
     for (int q = 0; q < kQ; ++q) {
-      const double w = q == 0 ? 1.0 / 3 : (q < 7 ? 1.0 / 18 : 1.0 / 36);
+      // -6 w = -2 k with the collision's FP32 odd coefficients k
+      const double k = q == 0 ? 0.0 : (q < 7 ? (double)HC_K1 : (double)HC_K2);
       const bool on = wall_axis >= 0;
-      L.wc_lo[q] = on ? (float)(-6.0 * w * (ex[q] * L.ulo[0] + ey[q] * L.ulo[1] + ez[q] * L.ulo[2])) : 0.f;
-      L.wc_hi[q] = on ? (float)(-6.0 * w * (ex[q] * L.uhi[0] + ey[q] * L.uhi[1] + ez[q] * L.uhi[2])) : 0.f;
+      L.wc_lo[q] = on ? (float)(-2.0 * k * (ex[q] * L.ulo[0] + ey[q] * L.ulo[1] + ez[q] * L.ulo[2])) : 0.f;
+      L.wc_hi[q] = on ? (float)(-2.0 * k * (ex[q] * L.uhi[0] + ey[q] * L.uhi[1] + ez[q] * L.uhi[2])) : 0.f;
     }
   }
   L.tau = lat->tau;
@@ -589,6 +596,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   C.n = 0;
   C.origin = at<int>(c, c->o_origin);
   C.off = at<float>(c, c->o_off);
+  C.lo = at<float>(c, c->o_lo);
   C.force = at<float>(c, c->o_force);
   C.vel = at<float>(c, c->o_vel);
   C.k = at<float>(c, c->o_k);
@@ -641,6 +649,8 @@ static hc_status cells_changed(hc_ctx* c, int32_t n, const float* k, const float
   }
   c->C.n = n;
   c->have_cells = n > 0;
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->C.lo), 0, (int64_t)n * c->hm.nv * 3, c->stream),
+               "clear position low parts"));
   c->advect_pending = false;
   c->have_prev = false;
   c->adj_ready = false;   // a reverse sweep would recompute with the new cells
@@ -785,6 +795,8 @@ hc_status hc_write_vertices(hc_ctx* c, const int32_t* origin, const float* offse
   if (n_cells != c->C.n || !origin || !offsets) return fail(c, HC_ERR_ARG, "cell count mismatch");
   HC_TRY(copy_h2d(c, c->C.origin, origin, (size_t)n_cells * 12));
   HC_TRY(copy_h2d(c, c->C.off, offsets, (size_t)n_cells * c->hm.nv * 12));
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->C.lo), 0, n_cells * c->hm.nv * 3, c->stream),
+               "clear position low parts"));
   c->have_prev = false;   // new positions: an Adams-Bashforth run restarts with Euler
   return sync(c, "write vertices");
 }
@@ -850,7 +862,7 @@ constexpr size_t kCkHeader = 32;
 hc_status hc_checkpoint_size(const hc_ctx* c, size_t* bytes) {
   if (!c || !bytes) return HC_ERR_ARG;
   const size_t X = (size_t)c->C.n * c->hm.nv * 12;
-  *bytes = kCkHeader + (size_t)19 * c->L.np * 4 + (size_t)c->C.n * 12 + 3 * X;
+  *bytes = kCkHeader + (size_t)19 * c->L.np * 4 + (size_t)c->C.n * 12 + 4 * X;
   return HC_OK;
 }
 
@@ -872,6 +884,8 @@ hc_status hc_checkpoint_save(hc_ctx* c, void* host, size_t bytes) {
   HC_TRY(copy_d2h(c, p, c->C.origin, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
   HC_TRY(copy_d2h(c, p, c->C.off, X));
+  p += X;
+  HC_TRY(copy_d2h(c, p, c->C.lo, X));
   p += X;
   HC_TRY(copy_d2h(c, p, c->C.vel, X));
   p += X;
@@ -899,6 +913,8 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   HC_TRY(copy_h2d(c, c->C.origin, p, (size_t)c->C.n * 12));
   p += (size_t)c->C.n * 12;
   HC_TRY(copy_h2d(c, c->C.off, p, X));
+  p += X;
+  HC_TRY(copy_h2d(c, c->C.lo, p, X));
   p += X;
   HC_TRY(copy_h2d(c, c->C.vel, p, X));
   p += X;
@@ -1029,13 +1045,15 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   c->adj_nseg = (n_steps + ck - 1) / ck;
   c->ck_pops = reinterpret_cast<float*>(w + p.ck_pops);
   c->ck_off = reinterpret_cast<float*>(w + p.ck_off);
+  c->ck_lo = reinterpret_cast<float*>(w + p.ck_lo);
+  c->sg_lo = reinterpret_cast<float*>(w + p.sg_lo);
   c->sg_pops = reinterpret_cast<float*>(w + p.sg_pops);
   c->sg_off = reinterpret_cast<float*>(w + p.sg_off);
   c->sg_F = reinterpret_cast<float*>(w + p.sg_F);
   c->sg_macro = reinterpret_cast<float4*>(w + p.sg_macro);
   c->sg_Fv = reinterpret_cast<float*>(w + p.sg_Fv);
-  c->lam_f[0] = reinterpret_cast<float*>(w + p.lf0);
-  c->lam_f[1] = reinterpret_cast<float*>(w + p.lf1);
+  c->lam_f[0] = reinterpret_cast<double*>(w + p.lf0);
+  c->lam_f[1] = reinterpret_cast<double*>(w + p.lf1);
   c->lam_X[0] = reinterpret_cast<float*>(w + p.lx0);
   c->lam_X[1] = reinterpret_cast<float*>(w + p.lx1);
   c->lam_Fv = reinterpret_cast<float*>(w + p.lfv);
@@ -1065,6 +1083,7 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
       const int k = s / c->adj_ck;
       HC_TRY(copy_d2d(c, c->ck_pops + k * P, c->pops[c->cur], (size_t)P * 4));
       HC_TRY(copy_d2d(c, c->ck_off + k * X, c->C.off, (size_t)X * 4));
+      HC_TRY(copy_d2d(c, c->ck_lo + k * X, c->C.lo, (size_t)X * 4));
     }
     HC_TRY(one_step(c));
     if ((s + 1) % c->adj_ck == 0 || s + 1 == c->adj_n) HC_TRY(flush(c));
@@ -1081,7 +1100,7 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   if (!c->adj_ready || !grad) return fail(c, HC_ERR_STATE, "hc_adj_forward must run first");
   const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   const int nblk = (int)((N + 255) / 256);
-  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));
+  HC_TRY(check(c, launch_zero_f64(c->lam_f[0], P, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_part, nblk, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_in_part, (int64_t)kVisClasses * nblk, c->stream), "zero"));
@@ -1090,6 +1109,7 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
     const int s0 = seg * c->adj_ck, len = std::min(c->adj_ck, c->adj_n - s0);
     HC_TRY(copy_d2d(c, c->sg_pops, c->ck_pops + seg * P, (size_t)P * 4));
     HC_TRY(copy_d2d(c, c->sg_off, c->ck_off + seg * X, (size_t)X * 4));
+    HC_TRY(copy_d2d(c, c->sg_lo, c->ck_lo + seg * X, (size_t)X * 4));
     for (int i = 0; i < len; ++i) HC_TRY(adj_forward_into(c, i));
     for (int i = len - 1; i >= 0; --i) {
       HC_TRY(adj_reverse_step(c, i, a));

@@ -26,6 +26,7 @@ struct Batch {
   Mesh M;
   int* origin;              // [nbox][3]
   float* off;               // [nbox][nv][3]
+  float* lo;                // [nbox][nv][3] low parts of the positions (see move_compensated)
   float* force;             // [nbox][nv][3]
   float* vel;               // [nbox][nv][3]
   const float* k;           // [nbox][4]

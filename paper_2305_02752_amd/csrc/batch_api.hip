@@ -53,7 +53,7 @@ struct hc_batch {
   bool have_cells = false;
   std::string err;
   size_t o_pop0, o_pop1, o_snap_pop, o_box, o_tri, o_edge, o_L0, o_hv, o_th0, o_pole, o_origin,
-      o_off, o_force, o_vel, o_snap_off, o_k, o_trac, o_area, o_vol, o_uacc, o_bbox, o_wg, o_bar,
+      o_off, o_lo, o_force, o_vel, o_snap_off, o_snap_lo, o_k, o_trac, o_area, o_vol, o_uacc, o_bbox, o_wg, o_bar,
       o_step, o_snap_step, o_flags, o_mask;
 };
 
@@ -94,9 +94,11 @@ void plan(hc_batch* b, Lay& L) {
   b->o_pole = L.add(m.pole.size() * 4);
   b->o_origin = L.add(B * 12);
   b->o_off = L.add(B * nv * 12);
+  b->o_lo = L.add(B * nv * 12);
   b->o_force = L.add(B * nv * 12);
   b->o_vel = L.add(B * nv * 12);
   b->o_snap_off = L.add(B * nv * 12);
+  b->o_snap_lo = L.add(B * nv * 12);
   b->o_k = L.add(B * 16);
   b->o_trac = L.add(B * 12);
   b->o_area = L.add(B * 8);
@@ -223,6 +225,7 @@ hc_status snapshot(hc_batch* b, bool save) {
   if (save) {
     HB_TRY(d2d(b, bat<void>(b, b->o_snap_pop), cur, P));
     HB_TRY(d2d(b, bat<void>(b, b->o_snap_off), b->V.off, X));
+    HB_TRY(d2d(b, bat<void>(b, b->o_snap_lo), b->V.lo, X));
     HB_TRY(d2d(b, bat<void>(b, b->o_snap_step), b->V.box_step, (size_t)b->nbox * 4));
   } else {
     int snap_step = 0;
@@ -231,6 +234,7 @@ hc_status snapshot(hc_batch* b, bool save) {
     float* dst = (snap_step & 1) ? b->V.pops1 : b->V.pops0;
     HB_TRY(d2d(b, dst, bat<void>(b, b->o_snap_pop), P));
     HB_TRY(d2d(b, b->V.off, bat<void>(b, b->o_snap_off), X));
+    HB_TRY(d2d(b, b->V.lo, bat<void>(b, b->o_snap_lo), X));
     HB_TRY(d2d(b, b->V.box_step, bat<void>(b, b->o_snap_step), (size_t)b->nbox * 4));
   }
   return bsync(b);
@@ -365,6 +369,7 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   V.M.V0 = m.V0;
   V.origin = bat<int>(b, b->o_origin);
   V.off = bat<float>(b, b->o_off);
+  V.lo = bat<float>(b, b->o_lo);
   V.force = bat<float>(b, b->o_force);
   V.vel = bat<float>(b, b->o_vel);
   V.k = bat<float>(b, b->o_k);
@@ -409,6 +414,8 @@ hc_status hc_batch_set_cells(hc_batch* b, const int32_t* origin, const float* of
   const size_t nv = b->hm.nv, B = b->nbox;
   HB_TRY(h2d(b, b->V.origin, origin, B * 12));
   HB_TRY(h2d(b, b->V.off, offsets, B * nv * 12));
+  HB_TRY(bcheck(b, launch_fill_i32(reinterpret_cast<int*>(b->V.lo), 0, (int64_t)(B * nv * 3), b->stream),
+                "clear position low parts"));
   HB_TRY(h2d(b, (void*)b->V.k, k, B * 16));
   if (traction) {
     HB_TRY(h2d(b, bat<void>(b, b->o_trac), traction, B * 12));

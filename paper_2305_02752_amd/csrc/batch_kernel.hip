@@ -285,13 +285,15 @@ __device__ void box_tile(const Batch& V, const BoxDesc& B, int box, int t, const
   }
 }
 
-// Vertex velocity = fixed-point sum of tile shares + wall layers; Euler move.
+// Vertex velocity = fixed-point sum of tile shares + wall layers; Euler move
+// with the rounding carried in the low parts (move_compensated).
 template <int K>
 __device__ void box_advect(const Batch& V, const BoxDesc& B, int box, const int* o3, int tid,
                            int nthr) {
   const int nv = V.M.nv;
   long long* U = V.uacc + (int64_t)box * nv * 3;
   float* off = V.off + (int64_t)box * nv * 3;
+  float* lo = V.lo + (int64_t)box * nv * 3;
   float* vel = V.vel + (int64_t)box * nv * 3;
   for (int v = tid; v < nv; v += nthr) {
     float u[3];
@@ -318,9 +320,11 @@ __device__ void box_advect(const Batch& V, const BoxDesc& B, int box, const int*
     bool finite = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float x = off[3 * v + d] + u[d];
+      float x = off[3 * v + d], l = lo[3 * v + d];
+      move_compensated(x, l, u[d]);
       finite = finite && isfinite(x);
       off[3 * v + d] = x;
+      lo[3 * v + d] = l;
       vel[3 * v + d] = u[d];
     }
     if (!finite) atomicOr(&V.flags[0], 1);

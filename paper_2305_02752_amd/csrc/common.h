@@ -7,6 +7,14 @@
 
 #include <cstdint>
 
+// D3Q19 weights and odd coefficients k = 3 w as FP32 constants whose
+// mass and momentum identities hold exactly (the collision explains the choice).
+#define HC_W0 0x1.555558p-2f
+#define HC_W1 0x1.c71c7p-5f
+#define HC_W2 0x1.c71c7p-6f
+#define HC_K1 0x1.555554p-3f
+#define HC_K2 0x1.555556p-4f
+
 namespace hc {
 
 constexpr int kQ = 19;          // D3Q19
@@ -114,6 +122,7 @@ struct Cells {
   int n;
   int* origin;              // [n][3]
   float* off;               // [n][nv][3]
+  float* lo;                // [n][nv][3] low parts of the positions (see move_compensated)
   float* force;             // [n][nv][3]
   float* vel;               // [n][nv][3] interpolated velocity of the last step
   const float* k;           // [n][4]
@@ -149,7 +158,7 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                              const float* vec, float body, float* F, hipStream_t s);
 // adjoint kernels
-hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
+hipError_t launch_adj_collide(const double* lam1, double* lam0, const float* g0, const float* F,
                               const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
                               double* domega_in_part, const Lattice& L, hipStream_t s);
 hipError_t launch_adj_vertex(const Cells& c, const Mesh& m, const Lattice& L, const float* lamX1,

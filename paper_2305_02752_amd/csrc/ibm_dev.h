@@ -14,7 +14,8 @@ namespace ibmd {
 // is reproducible) + stencil nodes beyond a wall at the wall velocity; then
 // X += U (Euler) or X += 3/2 U - 1/2 U_prev (second-order Adams-Bashforth,
 // U_prev = the velocity stored by the previous move), reading X from src
-// when given (else in place) and writing C.off.  The new offset is also
+// when given (else in place) and writing C.off; the low parts C.lo are
+// carried in place (move_compensated).  The new offset is also
 // returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
 // the wall contributes its axis weight times the wall velocity.
 template <int K>
@@ -58,8 +59,15 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
     dy = 1.5f * Uy - 0.5f * vo[1];
     dz = 1.5f * Uz - 0.5f * vo[2];
   }
-  const float nx = ox + dx, ny = oy + dy, nz = oz + dz;
+  float* lo = C.lo + v * 3;
+  float nx = ox, ny = oy, nz = oz, lx = lo[0], ly = lo[1], lz = lo[2];
+  hc::move_compensated(nx, lx, dx);
+  hc::move_compensated(ny, ly, dy);
+  hc::move_compensated(nz, lz, dz);
   if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(&flags[0], 1);
+  lo[0] = lx;
+  lo[1] = ly;
+  lo[2] = lz;
   vo[0] = Ux;
   vo[1] = Uy;
   vo[2] = Uz;

@@ -15,10 +15,23 @@ namespace lbm {
 __device__ constexpr int cx[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 __device__ constexpr int cy[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __device__ constexpr int cz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-__device__ constexpr float wq[kQ] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18,
-                                     1.f / 18, 1.f / 18, 1.f / 36, 1.f / 36, 1.f / 36,
-                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
-                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+// Lattice weights and the odd-part coefficients k = 3 w, as FP32 constants
+// chosen so that the moment identities of the collision hold exactly for the
+// stored values: w_0 + 6 w_1 + 12 w_2 = 1 (mass) and 2 (k_1 + 4 k_2) = 1
+// (momentum).  Rounding 1/3, 1/18, 1/36 and 3 w one by one leaves both sums
+// off by ~1e-8, and the same constants repeat that error at every node and
+// step: a flow's momentum then grows or decays by that fraction per step, a
+// drift that dominated the FP32 error of long runs (about 6x the rest after
+// 2000 steps of a wall-driven flow).  Each value is within 2 ulp of the exact
+// weight: w_2 = fl(1/36) - 1 ulp, w_1 = 2 w_2, w_0 = 1 - 24 w_2 (exact),
+// k_2 = fl(1/12), k_1 = 1/2 - 4 k_2 (exact).  The values are HC_W0..HC_K2
+// (common.h; the host's moving-wall coefficients use them too).
+__device__ constexpr float wq[kQ] = {HC_W0, HC_W1, HC_W1, HC_W1, HC_W1, HC_W1, HC_W1,
+                                     HC_W2, HC_W2, HC_W2, HC_W2, HC_W2, HC_W2,
+                                     HC_W2, HC_W2, HC_W2, HC_W2, HC_W2, HC_W2};
+__device__ constexpr float kq[kQ] = {0.f,   HC_K1, HC_K1, HC_K1, HC_K1, HC_K1, HC_K1,
+                                     HC_K2, HC_K2, HC_K2, HC_K2, HC_K2, HC_K2,
+                                     HC_K2, HC_K2, HC_K2, HC_K2, HC_K2, HC_K2};
 __device__ constexpr int opp[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 // g: shifted populations in, post-collision shifted populations out.
@@ -49,14 +62,16 @@ __device__ inline void collide(float (&g)[kQ], float fx, float fy, float fz, flo
   const float uu = ux * ux + uy * uy + uz * uz;
   const float uF = ux * fx + uy * fy + uz * fz;
   const float c0 = drho - 1.5f * rho * uu;   // f_eq / w at e = 0
-  g[0] = keep * g[0] + wq[0] * (omega * c0 - 3.f * src * uF);
+  const float omr = omega * rho;
+  // each constant multiplies last, so no product of two constants (a rounded
+  // coefficient shared by every node) enters the moments
+  g[0] = keep * g[0] + wq[0] * (omega * c0 - 3.f * (src * uF));
 #pragma unroll
   for (int a = 1; a < kQ; a += 2) {
-    const float w = wq[a];
     const float eu = cx[a] * ux + cy[a] * uy + cz[a] * uz;
     const float eF = cx[a] * fx + cy[a] * fy + cz[a] * fz;
-    const float even = omega * w * (c0 + 4.5f * rho * eu * eu) + src * w * (9.f * eu * eF - 3.f * uF);
-    const float odd = 3.f * w * (omega * rho * eu + src * eF);
+    const float even = wq[a] * (omega * (c0 + 4.5f * rho * eu * eu) + src * (9.f * eu * eF - 3.f * uF));
+    const float odd = kq[a] * (omr * eu + src * eF);
     g[a] = keep * g[a] + (even + odd);
     g[a + 1] = keep * g[a + 1] + (even - odd);
   }
@@ -83,7 +98,7 @@ __device__ inline int stream_target(int i, int x, int y, int z, int nx, int ny, 
   if (crossed) {
     const float uw = crossed == 1 ? cx[i] * W.lo[0] + cy[i] * W.lo[1] + cz[i] * W.lo[2]
                                   : cx[i] * W.hi[0] + cy[i] * W.hi[1] + cz[i] * W.hi[2];
-    *dw = -6.f * wq[i] * rho * uw;
+    *dw = -2.f * kq[i] * rho * uw;
     *dst = ((int64_t)z * ny + y) * nx + x;
     return opp[i];
   }
@@ -139,7 +154,7 @@ __device__ inline float wall_coeff(const Lattice& L, int q, int x, int y, int z)
   const int side = wall_crossed(L, q, x, y, z);
   if (side == 0) return 0.f;
   const float* uw = side == 1 ? L.ulo : L.uhi;
-  return -6.f * wq[q] * (cx[q] * uw[0] + cy[q] * uw[1] + cz[q] * uw[2]);
+  return -2.f * kq[q] * (cx[q] * uw[0] + cy[q] * uw[1] + cz[q] * uw[2]);
 }
 
 // Population q arriving at boundary node (x, y, z) across the z boundary of

@@ -54,4 +54,18 @@ __device__ inline float stencil_w(float f, int k) {
   return k == 0 ? 1.f - f : f;
 }
 
+// A vertex coordinate held as the unevaluated sum hi + lo of two floats, moved
+// by d.  hi + a is formed with its exact rounding error (Knuth's TwoSum), which
+// becomes the new lo: a float position alone drops up to half an ulp per move,
+// and when a vertex creeps at nearly constant speed the same rounding repeats
+// every step, a drift that grows linearly with the step count.  Readers of the
+// position use hi (within half an ulp of hi + lo).
+__device__ __forceinline__ void move_compensated(float& hi, float& lo, float d) {
+  const float a = d + lo;
+  const float s = hi + a;
+  const float bp = s - hi;
+  lo = (hi - (s - bp)) + (a - bp);
+  hi = s;
+}
+
 }  // namespace hc
