@@ -15,27 +15,9 @@ from gpu_common import relerr
 
 pytestmark = pytest.mark.gpu
 
-SIDES = [(24, 24, 24), (17, 20, 19), (26, 18, 22), (20, 20, 20), (25, 23, 17)]
-
-
 def _boxes(seed=0, walls_box=2, kernel=4):
-    rng = np.random.default_rng(seed)
-    rest64, tri = rbc_mesh()
-    lats, cells = [], []
-    for b, (nx, ny, nz) in enumerate(SIDES):
-        tau = float(rng.uniform(0.8, 1.2))
-        if b == walls_box:
-            lat = Lattice(nx, ny, nz, bc=(0, 0, 1), tau=tau, wall_u_lo=(-0.01, 0, 0),
-                          wall_u_hi=(0.01, 0, 0), ibm_kernel=kernel)
-        else:
-            lat = Lattice(nx, ny, nz, tau=tau, body_force=(1e-5 * (b % 2), 0.0, 0.0), ibm_kernel=kernel)
-        lats.append(lat)
-        centre = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2]) + rng.uniform(-0.5, 0.5, 3)
-        R = small_rotation(rng, 8.0)
-        c = place_cells(rest64, centre[None], R[None], log_uniform_k(rng, 1),
-                        traction=[[rng.uniform(0, PN200_LU), 0.0, 0.0]])
-        cells.append(jitter_cells(rng, c, 0.04))
-    return lats, rest64.astype(np.float32), tri, cells
+    from workloads.configs import small_batch_boxes
+    return small_batch_boxes(seed, walls_box, kernel)
 
 
 def _make(lats, rest, tri, cells, tiling=None):

@@ -108,3 +108,17 @@ def test_complex_step_matches_fd():
     # loss of about 10 changes by only ~1e-9 for the small components, so
     # rounding of the loss limits them to a few 1e-6
     assert np.all(np.abs(p * (g_cs - g_fd)) <= 1e-5 * np.abs(p * g_fd))
+
+
+def test_stored_full_box_gradients_agree():
+    """The stored full-size gradients (48^3, 2000 steps) by the oracle's two
+    independent methods: central differences and the complex step."""
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    fd = np.load(os.path.join(here, "adjoint_full_boxes_fd.npz"))
+    cs = np.load(os.path.join(here, "adjoint_full_boxes_cs.npz"))
+    assert (fd["boxes"] == cs["boxes"]).all() and fd["steps"] == cs["steps"] == 2000
+    for b in range(len(fd["boxes"])):
+        p = fd["params"][b]
+        pf, pc = p * fd["fd_grad"][b], p * cs["cs_grad"][b]
+        assert np.linalg.norm(pf - pc) <= 1e-6 * np.linalg.norm(pc)

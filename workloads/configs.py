@@ -346,6 +346,31 @@ def tiny_periodic(seed: int = 5, n=(24, 20, 16), n_cells: int = 1, walls: int = 
     return Workload("tiny", lat, rest64.astype(np.float32), tri, cells, 10)
 
 
+def small_batch_boxes(seed: int = 0, walls_box: int = 2, kernel: int = 4):
+    """Five small boxes of uneven sides for the batched-form parity tests:
+    one with z walls moving +-0.01, the others periodic (every other one with
+    a body force); one jittered cell per box with log-uniform stiffness and a
+    pole traction.  Returns (lattices, rest_pos float32, tri, cells)."""
+    sides = [(24, 24, 24), (17, 20, 19), (26, 18, 22), (20, 20, 20), (25, 23, 17)]
+    rng = np.random.default_rng(seed)
+    rest64, tri = _mesh()
+    lats, cells = [], []
+    for b, (nx, ny, nz) in enumerate(sides):
+        tau = float(rng.uniform(0.8, 1.2))
+        if b == walls_box:
+            lat = Lattice(nx, ny, nz, bc=(PERIODIC, PERIODIC, WALL), tau=tau, wall_u_lo=(-0.01, 0, 0),
+                          wall_u_hi=(0.01, 0, 0), ibm_kernel=kernel)
+        else:
+            lat = Lattice(nx, ny, nz, tau=tau, body_force=(1e-5 * (b % 2), 0.0, 0.0), ibm_kernel=kernel)
+        lats.append(lat)
+        centre = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2]) + rng.uniform(-0.5, 0.5, 3)
+        R = small_rotation(rng, 8.0)
+        c = place_cells(rest64, centre[None], R[None], log_uniform_k(rng, 1),
+                        traction=[[rng.uniform(0, PN200_LU), 0.0, 0.0]])
+        cells.append(jitter_cells(rng, c, 0.04))
+    return lats, rest64.astype(np.float32), tri, cells
+
+
 # --------------------------------------------------------------------------- random states
 def random_shifted_populations(rng, lat: Lattice, scale: float = 1e-3) -> np.ndarray:
     """Random shifted populations g_i = f_i - w_i, float32 [19, nz, ny, nx]."""
