@@ -65,6 +65,9 @@ struct hc_ctx {
   int force_every = 1;
   int scheme = HC_EULER;
   bool have_prev = false;
+  // offsets re-centred after moves; off while the adjoint records a forward
+  // run (its segment replay keeps one origin per cell)
+  bool recentre = true;
   // interior viscosity (Sec. 1, Sec. 3.4): sites inside the cells relax with
   // ratio times the plasma viscosity.  One ratio for every cell
   // (uniform_ratio; 1 switches the marking off) or one per cell, as up to
@@ -269,7 +272,7 @@ hc_status one_step(hc_ctx* c) {
   const bool refresh = c->step % c->force_every == 0;
   HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
     return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, refresh, ab2,
-                            c->stream);
+                            c->recentre, c->stream);
   }));
   if (adv) c->have_prev = true;
   unsigned char* mask = nullptr;
@@ -358,7 +361,7 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   float4* Mi = c->sg_macro + i * N;
   const float* prev = i > 0 ? c->sg_off + (i - 1) * X : nullptr;
   HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev, true,
-                                   false, c->stream),
+                                   false, false, c->stream),
                "cell step"));
   unsigned char* mask = nullptr;
   if (interior_on(c)) {   // the forward step's marks, from slot i's positions
@@ -1078,6 +1081,11 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int64_t P = 19 * c->L.np, X = (int64_t)c->C.n * c->hm.nv * 3;
   HC_TRY(copy_h2d(c, c->targets, targets, (size_t)c->C.n * 16));
+  c->recentre = false;
+  struct Restore {
+    hc_ctx* c;
+    ~Restore() { c->recentre = true; }
+  } restore{c};
   for (int s = 0; s < c->adj_n; ++s) {
     if (s % c->adj_ck == 0) {
       const int k = s / c->adj_ck;

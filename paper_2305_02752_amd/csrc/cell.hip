@@ -5,6 +5,12 @@
 //     sum) when they are due (refresh); between refreshes the forces of
 //     the last one are held (Sec. 2.6 time-scale separation);
 // (3) bins the cell's vertices to the tiles their IBM stencils reach.
+// After a move, a cell whose bounding-box centre lies more than kRecentre
+// lattice units from its integer origin along an axis is re-centred: the
+// origin takes the nearest integer of that centre and every offset gives it
+// up (TwoSum into the low part, so origin + offset + low part is unchanged).
+// Offsets then stay within the cell's own size however far it travels, and
+// keep the resolution a float has there.
 // All three read the same 642 positions, so the cell is loaded once and its
 // latency-bound steps overlap across the resident work-groups.
 #include <algorithm>
@@ -16,6 +22,64 @@
 namespace hc {
 namespace {
 
+constexpr float kRecentre = 8.f;
+
+template <int kThreads>
+__device__ void recentre_cell(const Cells& C, const Mesh& M, int c, float* sp, float (*ext)[kThreads / kWave],
+                              int tid) {
+  float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int v = tid; v < M.nv; v += kThreads) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fminf(mn[d], sp[3 * v + d]);
+      mx[d] = fmaxf(mx[d], sp[3 * v + d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+      mn[d] = fminf(mn[d], __shfl_xor(mn[d], m));
+      mx[d] = fmaxf(mx[d], __shfl_xor(mx[d], m));
+    }
+  }
+  if ((tid & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ext[d][tid / kWave] = mn[d];
+      ext[3 + d][tid / kWave] = mx[d];
+    }
+  }
+  __syncthreads();
+  int sh[3];
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float a = ext[d][0], b = ext[3 + d][0];
+    for (int w = 1; w < kThreads / kWave; ++w) {
+      a = fminf(a, ext[d][w]);
+      b = fmaxf(b, ext[3 + d][w]);
+    }
+    const float mid = 0.5f * (a + b);
+    sh[d] = fabsf(mid) > kRecentre ? (int)floorf(mid + 0.5f) : 0;
+    any = any || sh[d] != 0;
+  }
+  if (!any) return;   // the same decision in every thread
+  const int64_t b3 = (int64_t)c * M.nv * 3;
+  for (int v = tid; v < M.nv; v += kThreads) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (sh[d] == 0) continue;
+      float hi = sp[3 * v + d], lo = C.lo[b3 + 3 * v + d];
+      move_compensated(hi, lo, (float)-sh[d]);
+      sp[3 * v + d] = hi;
+      C.off[b3 + 3 * v + d] = hi;
+      C.lo[b3 + 3 * v + d] = lo;
+    }
+  }
+  if (tid < 3) C.origin[3 * c + tid] += sh[tid];
+  __syncthreads();
+}
+
 // Work-group size: 256 threads when the cells fill the chip; with fewer
 // cells than a few per CU each cell's work-group is widened so that its
 // latency-bound loops take fewer rounds.
@@ -24,9 +88,10 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
                                                            const float4* __restrict__ partial,
                                                            int* __restrict__ flags, int advect,
                                                            const float* __restrict__ src,
-                                                           int refresh, int ab2) {
+                                                           int refresh, int ab2, int recentre) {
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
+  __shared__ float ext[6][kCellThreads / kWave];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
   // LDS: [membrane accumulator, later the binning's slot records][offsets]
   const int region = max(24, bin::slot_lds_per_vertex(L.max_touch)) * M.nv;   // bytes
@@ -43,6 +108,10 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
       sp[3 * vl] = nx[0];
       sp[3 * vl + 1] = nx[1];
       sp[3 * vl + 2] = nx[2];
+    }
+    if (recentre) {
+      __syncthreads();   // every moved offset in sp
+      recentre_cell<kCellThreads>(C, M, c, sp, ext, tid);
     }
   } else {
     for (int i = tid; i < 3 * M.nv; i += kCellThreads) sp[i] = C.off[b3 + i];
@@ -63,13 +132,14 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
 // Tile-list counts must be zero on entry (see launch_bin_vertices).
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, const float* src,
-                            bool refresh, bool ab2, hipStream_t s) {
+                            bool refresh, bool ab2, bool recentre, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const int region = std::max(24, bin::slot_lds_per_vertex(L.max_touch)) * m.nv;
   const size_t lds = (size_t)((region + 7) & ~7) + (size_t)m.nv * 3 * sizeof(float);
-  const int adv = advect ? 1 : 0, ref = refresh ? 1 : 0, a2 = ab2 ? 1 : 0;
+  const int adv = advect ? 1 : 0, ref = refresh ? 1 : 0, a2 = ab2 ? 1 : 0, rc = recentre ? 1 : 0;
   auto go = [&](auto kern, int threads) {
-    hipLaunchKernelGGL(kern, dim3(c.n), dim3(threads), lds, s, c, m, L, b, partial, flags, adv, src, ref, a2);
+    hipLaunchKernelGGL(kern, dim3(c.n), dim3(threads), lds, s, c, m, L, b, partial, flags, adv, src, ref, a2,
+                       rc);
   };
   // sheared images: one 256-thread form
   if (L.le) {

@@ -292,3 +292,50 @@ def test_multistep_1000_tiny():
     e_x = relerr(o[:, None, :] + off.astype(np.float64) - X0, X - X0)
     print("1000 steps: pops", e_g, "displacement", e_x, flush=True)
     assert e_g <= TOL_LONG and e_x <= TOL_LONG
+
+
+def test_cell_carried_past_recentring():
+    """A cell carried ~20 lu by a uniform stream (0.1 lu/step, 200 steps) in a
+    periodic 40 x 24 x 24 box, with a pole traction deforming it: its origin
+    is re-centred on the way (the bounding-box centre may not stray more than
+    8 lu from the integer origin), origin + offsets stay within 1e-3 of the
+    oracle's positions (relative to the largest displacement), and the
+    binning of the re-centred (origin, offsets) is bit-exact."""
+    from types import SimpleNamespace
+
+    from workloads import rbc_mesh
+    from workloads.configs import small_rotation
+    rng = np.random.default_rng(17)
+    rest64, tri = rbc_mesh()
+    lat = Lattice(40, 24, 24, tau=1.0)
+    cells = place_cells(rest64, np.array([[10.3, 11.7, 12.2]]), small_rotation(rng, 10.0)[None], K_REF[None],
+                        traction=[[2e-3, 0.0, 0.0]])
+    cells = jitter_cells(rng, cells, 0.05)
+    w = SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri, cells=cells)
+    sim = make_sim(w, cells)
+    u0 = (0.1, 0.0, 0.0)
+    sim.init_equilibrium(u0=u0)
+    n = 200
+    sim.step(n)
+    sim.sync()
+    o, off, _ = sim.read_vertices()
+    owner, tptr, touch, cptr, clist = sim.read_bins()
+    sim.close()
+    m = oracle_model(w, cells)
+    X0 = cells.positions64()
+    _, X = step.run(m, lattice.init_equilibrium(lat.shape, u0=u0), X0, n)
+    Xg = o[:, None, :].astype(np.float64) + off.astype(np.float64)
+    e_x = relerr(Xg - X0, X - X0)
+    mid = 0.5 * (off.min(axis=1) + off.max(axis=1))
+    print(f"origin {cells.origin[0]} -> {o[0]}, box centre offset {mid[0]}, displacement max "
+          f"{np.abs(X - X0).max():.2f} lu, error {e_x:.2e}", flush=True)
+    assert o[0, 0] - cells.origin[0, 0] >= 8          # re-centred at least once along x
+    assert np.abs(mid).max() <= 8.0 + 0.1 * 1.5      # at most one move past the threshold
+    assert np.abs(X - X0).max() > 16.0
+    assert e_x <= TOL_LONG
+    dims, bc = (lat.nx, lat.ny, lat.nz), lat.bc
+    ow, _, _, cptr_r, clist_r = binning.bins(o, off, dims, bc)
+    tptr_r, touch_r = binning.touch_lists(o, off, dims, bc, lat.ibm_kernel)
+    assert np.array_equal(owner, ow)
+    assert np.array_equal(cptr, cptr_r) and np.array_equal(clist, clist_r)
+    assert np.array_equal(tptr, tptr_r) and np.array_equal(touch, touch_r)
