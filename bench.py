@@ -95,23 +95,29 @@ def cpu_baseline(w, steps: int = 3, side: int = 64):
     }
 
 
-def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
-    """GB/s of the library's streaming copy kernel (read + write bytes)."""
+def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5):
+    """GB/s (read + write bytes) of the library's streaming copy kernel and,
+    beside it, of torch's device-to-device copy (a hipMemcpyAsync)."""
     from paper_2305_02752_amd.hemo import device_copy
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     s = torch.cuda.current_stream().cuda_stream
-    device_copy(b.data_ptr(), a.data_ptr(), nbytes, s)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        device_copy(b.data_ptr(), a.data_ptr(), nbytes, s)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    lib = timed(lambda: device_copy(b.data_ptr(), a.data_ptr(), nbytes, s))
+    memcpy = timed(lambda: b.copy_(a))
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return lib, memcpy
 
 
 def bench_separated(sim, n_sites: int, warmup: int, steps: int, force_every: int = 10):
@@ -442,8 +448,8 @@ def main():
     log(f"workload {w.name}: {n_sites} sites, {w.cells.n} cells, {n_vert} vertices, "
         f"packing residual {w.extra['pack_residual']:.2f} lu, built in {time.time() - t:.1f}s")
 
-    copy_gbps = copy_bandwidth(torch)
-    log(f"library copy kernel: {copy_gbps:.0f} GB/s")
+    copy_gbps, memcpy_gbps = copy_bandwidth(torch)
+    log(f"library copy kernel: {copy_gbps:.0f} GB/s; hipMemcpyAsync device to device: {memcpy_gbps:.0f} GB/s")
 
     sim = Simulation(lat, w.rest_pos, w.tri, max_cells=w.cells.n)
     sim.set_cells(w.cells.origin, w.cells.offsets, w.cells.k, None)
@@ -559,6 +565,7 @@ def main():
         "step_hbm_frac": step_frac,
         "step_algorithmic_bytes": b_step,
         "copy_kernel_GBps": copy_gbps,
+        "memcpy_GBps": memcpy_gbps,
         "kernel_ms": {k: ms / max(n, 1) for k, (ms, n) in prof.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -259,7 +259,8 @@ hc_status hc_profile(hc_ctx* ctx, int32_t enable);
 hc_status hc_profile_read(hc_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Device-to-device copy of `bytes` with the library's own streaming copy
- * kernel (16-byte vector loads and stores), enqueued on hip_stream.  Used as
+ * kernel (16-byte nontemporal vector loads and stores, four in flight per
+ * thread, one pass), enqueued on hip_stream.  Used as
  * the measured bandwidth reference beside the roofline.  dst and src must
  * not overlap and must be 16-byte aligned. */
 hc_status hc_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
