@@ -338,61 +338,57 @@ def bench_batched(torch, seed: int = 3, steps: int = 2000, warmup: int = 20):
 def bench_adjoint(torch, boxes: int = 64, seed: int = 4):
     """Adjoint workload (48^3 sheared boxes with pole traction, 2000 steps,
     checkpoint every 100): gradients of the cell-shape loss with respect to
-    (k_link, k_bend, k_area, k_volume, tau) for `boxes` of the 64 boxes (all
-    of them by default), each box on its own stream and host thread.  Reports gradient evaluations per
-    second and the cost of a gradient relative to a plain forward run."""
-    from concurrent.futures import ThreadPoolExecutor
+    (k_link, k_bend, k_area, k_volume, tau) of `boxes` of the 64 boxes (all
+    of them by default), timed through the torch form itself:
+    CoupledStepFn.apply(params, runner) and .backward(), whose runner drives
+    the batched reverse-mode calls (one launch per kernel over all boxes).
+    The cost of a gradient is reported against the batched persistent form
+    advancing the same boxes by the same number of steps."""
+    import tempfile
 
-    from paper_2305_02752_amd import Simulation
+    from paper_2305_02752_amd import Batch
+    from paper_2305_02752_amd.autograd import AdjointBoxes, CoupledStepFn
     from workloads import adjoint_boxes
 
     w = adjoint_boxes(seed=seed)
     n, ck = w.steps, w.extra["ckpt_every"]
-    sims, streams, starts = [], [], []
-    for b in range(boxes):
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            sim = Simulation(w.lattice[b], w.rest_pos, w.tri, max_cells=1)
-            c = w.cells[b]
-            sim.set_cells(c.origin, c.offsets, c.k, c.traction)
-            sim.init_equilibrium()
-            sim.adj_bind(n, ck)
-            starts.append(sim.checkpoint_save())
-        sims.append(sim)
-        streams.append(s)
-
-    def each(fn):
-        with ThreadPoolExecutor(max_workers=boxes) as ex:
-            return list(ex.map(fn, range(boxes)))
-
-    def fwd_plain(b):
-        with torch.cuda.stream(streams[b]):
-            sims[b].checkpoint_restore(starts[b])
-            sims[b].step(n)
-            sims[b].sync()
-
-    def fwd_adj(b):
-        with torch.cuda.stream(streams[b]):
-            sims[b].checkpoint_restore(starts[b])
-            return sims[b].adj_forward(w.extra["targets"][b])[0]
-
-    def bwd(b):
-        with torch.cuda.stream(streams[b]):
-            return sims[b].adj_backward()[0]
-
-    each(fwd_plain)                      # warm-up
+    lats, cells = w.lattice[:boxes], w.cells[:boxes]
+    # the forward it is measured against: the batched persistent form
+    bt = Batch(lats, w.rest_pos, w.tri)
+    bt.set_cells(np.concatenate([c.origin for c in cells]), np.concatenate([c.offsets for c in cells]),
+                 np.concatenate([c.k for c in cells]), np.concatenate([c.traction for c in cells]))
+    with tempfile.TemporaryDirectory() as d:
+        bt.autotune(os.path.join(d, "tiling.txt"), trial_steps=10)
+    bt.run(20)
+    bt.sync()
     torch.cuda.synchronize()
-    t0 = time.perf_counter(); each(fwd_plain); torch.cuda.synchronize(); t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter(); loss = each(fwd_adj); torch.cuda.synchronize(); t_af = time.perf_counter() - t0
-    t0 = time.perf_counter(); grads = each(bwd); torch.cuda.synchronize(); t_bw = time.perf_counter() - t0
-    g = np.array(grads)
-    for sim in sims:
+    t0 = time.perf_counter()
+    bt.run(n)
+    bt.sync()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    bt.close()
+
+    runner = AdjointBoxes(lats, w.rest_pos, w.tri, cells, w.extra["targets"][:boxes], n, ck)
+    p0 = np.array([np.concatenate([c.k[0], [lat.tau]]) for c, lat in zip(cells, lats)])
+    params = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = CoupledStepFn.apply(params, runner)
+    torch.cuda.synchronize()
+    t_af = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss.sum().backward()
+    torch.cuda.synchronize()
+    t_bw = time.perf_counter() - t0
+    g = params.grad.numpy()
+    for sim in runner.sims:
         sim.close()
     return {"workload": w.name, "boxes_timed": boxes, "boxes_in_workload": len(w.cells), "steps": n,
-            "ckpt_every": ck, "grads_per_s": boxes / (t_af + t_bw),
-            "t_forward_s": t_fwd, "t_adjoint_forward_s": t_af, "t_backward_s": t_bw,
+            "ckpt_every": ck, "batched_calls": bool(runner.batched), "grads_per_s": boxes / (t_af + t_bw),
+            "t_forward_batched_form_s": t_fwd, "t_adjoint_forward_s": t_af, "t_backward_s": t_bw,
             "t_grad_over_t_forward": (t_af + t_bw) / t_fwd,
-            "finite": bool(np.all(np.isfinite(g)) and np.all(np.isfinite(loss)))}
+            "finite": bool(np.all(np.isfinite(g)) and np.all(np.isfinite(loss.detach().numpy())))}
 
 
 def main():

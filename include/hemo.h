@@ -372,6 +372,21 @@ hc_status hc_adj_bind_workspace(hc_ctx* ctx, void* dev_ptr, size_t bytes, int32_
 hc_status hc_adj_forward(hc_ctx* ctx, const double* targets, double* loss);
 hc_status hc_adj_backward(hc_ctx* ctx, double* grad);
 
+/* The same reverse-mode pair over n boxes at once (Sec. 2.3: fitting the
+ * stiffness constants and relaxation time to many single-cell experiments):
+ * ctxs[n] are contexts of one lattice shape and boundary kind, the same
+ * mesh and cell count, each with its own adjoint workspace bound for the
+ * same n_steps and ckpt_every; Euler moves with forces every step, the
+ * 4-point kernel, no sheared images and no interior viscosity.  Every
+ * per-step kernel runs as one launch over all boxes, on ctxs[0]'s stream
+ * (the other streams are synchronised first); each box's loss and gradient
+ * are those hc_adj_forward / hc_adj_backward give it alone, up to a few FP32
+ * roundings (the same arithmetic in kernels compiled a second time).
+ * targets [n][C][2], loss [n][C], grad [n][C][5] (host, row-major).  The
+ * call returns after its work is done; errors are reported on ctxs[0]. */
+hc_status hc_adj_multi_forward(hc_ctx* const* ctxs, int32_t n, const double* targets, double* loss);
+hc_status hc_adj_multi_backward(hc_ctx* const* ctxs, int32_t n, double* grad);
+
 /* ---------------------------------------------------------------------------
  * Batched form: n_boxes independent boxes, one cell each, advanced together
  * by ONE persistent kernel launch per hc_batch_run (replayed from a captured

@@ -15,8 +15,10 @@ from .hemo import Simulation
 
 
 class AdjointBoxes:
-    """One Simulation per box, each on its own stream, with a fixed initial
-    state that every forward evaluation restarts from."""
+    """One Simulation per box with a fixed initial state that every forward
+    evaluation restarts from.  Boxes of one shape run through the batched
+    reverse-mode calls (every per-step kernel one launch over all boxes);
+    otherwise each box runs on its own stream in turn."""
 
     def __init__(self, lattices, rest_pos, tri, cells, targets, n_steps, ckpt_every, device="cuda:0"):
         self.n_steps, self.ckpt_every = int(n_steps), int(ckpt_every)
@@ -34,18 +36,26 @@ class AdjointBoxes:
                 self.start.append(sim.checkpoint_save())
             self.sims.append(sim)
             self.streams.append(s)
+        shape = {(lat.nx, lat.ny, lat.nz, tuple(lat.bc)) for lat in lattices}
+        self.batched = len(shape) == 1
 
     def forward(self, params: np.ndarray) -> np.ndarray:
         self.generation += 1
-        loss = np.empty(len(self.sims))
         for b, sim in enumerate(self.sims):
             with torch.cuda.stream(self.streams[b]):
                 sim.checkpoint_restore(self.start[b])
                 sim.set_params(k=params[b, :4], tau=params[b, 4])
+        if self.batched:
+            return Simulation.adj_multi_forward(self.sims, self.targets)[:, 0]
+        loss = np.empty(len(self.sims))
+        for b, sim in enumerate(self.sims):
+            with torch.cuda.stream(self.streams[b]):
                 loss[b] = sim.adj_forward(self.targets[b])[0]
         return loss
 
     def backward(self) -> np.ndarray:
+        if self.batched:
+            return Simulation.adj_multi_backward(self.sims)[:, 0, :]
         g = np.empty((len(self.sims), 5))
         for b, sim in enumerate(self.sims):
             with torch.cuda.stream(self.streams[b]):

@@ -49,15 +49,15 @@ __device__ __forceinline__ double wq64(int j) { return j == 0 ? 1.0 / 3 : (j < 7
 // stores those projections to 7 digits and loses most of the differences in
 // smooth regions, and an FP32 f_eq repeats the same rounding across a smooth
 // flow, so both would bias the sum over every site and step.
-__global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ lam1,
-                                                     double* __restrict__ lam0,
-                                                     const float* __restrict__ h0,
-                                                     const float* __restrict__ F,
-                                                     const float* __restrict__ lamu,
-                                                     float* __restrict__ lamF,
-                                                     double* __restrict__ domega_part,
-                                                     unsigned char* __restrict__ mask,
-                                                     double* __restrict__ domega_in_part, Lattice L) {
+// LT: the lattice record by value (single-box kernel) or by reference to
+// global memory (batched kernel), so that neither puts it in scratch.
+template <class LT>
+__device__ __forceinline__ void adj_collide_body(const double* __restrict__ lam1, double* __restrict__ lam0,
+                                                 const float* __restrict__ h0, const float* __restrict__ F,
+                                                 const float* __restrict__ lamu, float* __restrict__ lamF,
+                                                 double* __restrict__ domega_part,
+                                                 unsigned char* __restrict__ mask,
+                                                 double* __restrict__ domega_in_part, LT L) {
   __shared__ double red[1 + kVisClasses][4];
   const int64_t N = L.np;   // slots of every (tile-major) lattice field
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,59 +78,96 @@ __global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ 
         mask[s] = 0;
       }
     }
-    // cotangent of the post-collision values stored at this node; a value
-    // stored for a bounce-back carries the wall term c rho
-    double ls[kQ];
-    double lrho = 0.0;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      ls[i] = lam1[i * N + s];
-      lrho += (double)lbm::wall_coeff(L, i, x, y, z) * ls[i];
-    }
-    // pre-collision populations, pulled as in the forward step
-    float g[kQ];
-    int64_t from[kQ];
-    int qs[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      from[i] = lbm::pull_source(L, i, x, y, z, &qs[i]);
-      g[i] = h0[qs[i] * N + from[i]];
-    }
+    // pre-collision populations, pulled as in the forward step.  The
+    // tile-major site index is separable (site = Sx(x) + Sy(y) + Sz(z)), so
+    // the pull source x - e_q of each direction is a sum of one part per
+    // axis; a source past a wall is the opposite population at the node.
+    const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+    const unsigned py = (unsigned)L.tx << 9, pz = py * (unsigned)L.ty;
+    const unsigned SX[3] = {(unsigned)(((xp >> 3) << 9) | (xp & 7)), (unsigned)(((x >> 3) << 9) | (x & 7)),
+                            (unsigned)(((xm >> 3) << 9) | (xm & 7))};
+    const unsigned SY[3] = {(unsigned)(yp >> 3) * py + (unsigned)((yp & 7) << 3),
+                            (unsigned)(y >> 3) * py + (unsigned)((y & 7) << 3),
+                            (unsigned)(ym >> 3) * py + (unsigned)((ym & 7) << 3)};
+    const unsigned SZ[3] = {(unsigned)(zp >> 3) * pz + (unsigned)((zp & 7) << 6),
+                            (unsigned)(z >> 3) * pz + (unsigned)((z & 7) << 6),
+                            (unsigned)(zm >> 3) * pz + (unsigned)((zm & 7) << 6)};
+    const unsigned hl = SX[1] + SY[1] + SZ[1];   // this node (== s)
+    const int wa = L.wall_axis;
+    const int wc = wa == 0 ? x : (wa == 1 ? y : z), wn = wa == 0 ? L.nx : (wa == 1 ? L.ny : L.nz);
+    const bool wlo = wa >= 0 && wc == 0, whi = wa >= 0 && wc == wn - 1;
+    // element offset of the value pulled into direction q
+    auto source = [&](int q) -> int64_t {
+      const int ex = cx[q], ey = cy[q], ez = cz[q];
+      const int ew = wa == 0 ? ex : (wa == 1 ? ey : ez);
+      if ((ew == 1 && wlo) || (ew == -1 && whi)) return (int64_t)opp[q] * N + hl;
+      const unsigned sx = ex > 0 ? SX[2] : (ex < 0 ? SX[0] : SX[1]);
+      const unsigned sy = ey > 0 ? SY[2] : (ey < 0 ? SY[0] : SY[1]);
+      const unsigned sz = ez > 0 ? SZ[2] : (ez < 0 ? SZ[0] : SZ[1]);
+      return (int64_t)q * N + (sx + sy + sz);
+    };
+    // Every sum over the directions of the VJP is a contraction of the
+    // cotangents l_j with 1, e_j or e_j e_j (weighted by w_j), or with the
+    // pulled populations g_j, so one pass over the directions accumulates
+    // the moments of g (drho, j), the moments M0 = sum w l, M1 = sum w l e,
+    // M2 = sum w l e e, and sum l g; no direction's values are kept.  A value
+    // stored for a bounce-back carries the wall term c rho.
     const double fx = F[s], fy = F[N + s], fz = F[2 * N + s];
     double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    double M0 = 0.0, M1x = 0.0, M1y = 0.0, M1z = 0.0, Pg = 0.0, lrho = 0.0;
+    double Mxx = 0.0, Myy = 0.0, Mzz = 0.0, Mxy = 0.0, Mxz = 0.0, Myz = 0.0;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      drho += g[i];
-      jx += cx[i] * (double)g[i];
-      jy += cy[i] * (double)g[i];
-      jz += cz[i] * (double)g[i];
+    for (int j = 0; j < kQ; ++j) {
+      const double gj = h0[source(j)];
+      const double l = lam1[j * N + s];
+      // (terms of zero directions are left out, not added as zeros)
+      drho += gj;
+      if (cx[j] != 0) jx += cx[j] * gj;
+      if (cy[j] != 0) jy += cy[j] * gj;
+      if (cz[j] != 0) jz += cz[j] * gj;
+      lrho += (double)lbm::wall_coeff(L, j, x, y, z) * l;
+      Pg += l * gj;
+      const double wl = wq64(j) * l;
+      M0 += wl;
+      if (cx[j] != 0) M1x += cx[j] * wl;
+      if (cy[j] != 0) M1y += cy[j] * wl;
+      if (cz[j] != 0) M1z += cz[j] * wl;
+      if (cx[j] != 0) Mxx += wl;
+      if (cy[j] != 0) Myy += wl;
+      if (cz[j] != 0) Mzz += wl;
+      if (cx[j] * cy[j] != 0) Mxy += (cx[j] * cy[j]) * wl;
+      if (cx[j] * cz[j] != 0) Mxz += (cx[j] * cz[j]) * wl;
+      if (cy[j] * cz[j] != 0) Myz += (cy[j] * cz[j]) * wl;
     }
     const double rho = 1.0 + drho, inv = 1.0 / rho;
     const double ux = (jx + 0.5 * fx) * inv, uy = (jy + 0.5 * fy) * inv, uz = (jz + 0.5 * fz) * inv;
     const double src = 1.0 - 0.5 * om;
     const double uu = ux * ux + uy * uy + uz * uz, uF = ux * fx + uy * fy + uz * fz;
-    double A = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0, t = 0.0;
-#pragma unroll
-    for (int j = 0; j < kQ; ++j) {
-      const double w = wq64(j);
-      const double eu = cx[j] * ux + cy[j] * uy + cz[j] * uz;
-      const double eF = cx[j] * fx + cy[j] * fy + cz[j] * fz;
-      const double phi = 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
-      A += ls[j] * w * phi;                            // d f_eq / d rho at fixed u
-      const double cu = om * w * rho, cs = src * w;
-      // omega d f_eq/du + (1 - omega/2) dS/du
-      Bx += ls[j] * (cu * (3.0 * cx[j] + 9.0 * eu * cx[j] - 3.0 * ux) + cs * (-3.0 * fx + 9.0 * eF * cx[j]));
-      By += ls[j] * (cu * (3.0 * cy[j] + 9.0 * eu * cy[j] - 3.0 * uy) + cs * (-3.0 * fy + 9.0 * eF * cy[j]));
-      Bz += ls[j] * (cu * (3.0 * cz[j] + 9.0 * eu * cz[j] - 3.0 * uz) + cs * (-3.0 * fz + 9.0 * eF * cz[j]));
-      // (1 - omega/2) dS/dF at fixed u
-      Gx += ls[j] * cs * (3.0 * (cx[j] - ux) + 9.0 * eu * cx[j]);
-      Gy += ls[j] * cs * (3.0 * (cy[j] - uy) + 9.0 * eu * cy[j]);
-      Gz += ls[j] * cs * (3.0 * (cz[j] - uz) + 9.0 * eu * cz[j]);
-      // d h / d omega = -(f - f_eq) - S / 2
-      const double geq = w * (drho + rho * (phi - 1.0));
-      const double S = w * (3.0 * (eF - uF) + 9.0 * eu * eF);
-      t += ls[j] * (-((double)g[j] - geq) - 0.5 * S);
-    }
+    const double M2ux = Mxx * ux + Mxy * uy + Mxz * uz, M2uy = Mxy * ux + Myy * uy + Myz * uz,
+                 M2uz = Mxz * ux + Myz * uy + Mzz * uz;
+    const double M2Fx = Mxx * fx + Mxy * fy + Mxz * fz, M2Fy = Mxy * fx + Myy * fy + Myz * fz,
+                 M2Fz = Mxz * fx + Myz * fy + Mzz * fz;
+    const double M1u = M1x * ux + M1y * uy + M1z * uz, M1F = M1x * fx + M1y * fy + M1z * fz;
+    const double uMu = ux * M2ux + uy * M2uy + uz * M2uz, uMF = ux * M2Fx + uy * M2Fy + uz * M2Fz;
+    const double orho = om * rho;
+    // d f_eq / d rho at fixed u: sum w l phi, phi = 1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u
+    double A = M0 * (1.0 - 1.5 * uu) + 3.0 * M1u + 4.5 * uMu;
+    // omega d f_eq/du + (1 - omega/2) dS/du
+    double Bx = orho * (3.0 * M1x + 9.0 * M2ux - 3.0 * ux * M0) + src * (9.0 * M2Fx - 3.0 * fx * M0);
+    double By = orho * (3.0 * M1y + 9.0 * M2uy - 3.0 * uy * M0) + src * (9.0 * M2Fy - 3.0 * fy * M0);
+    double Bz = orho * (3.0 * M1z + 9.0 * M2uz - 3.0 * uz * M0) + src * (9.0 * M2Fz - 3.0 * fz * M0);
+    // (1 - omega/2) dS/dF at fixed u
+    const double Gx = src * (3.0 * M1x - 3.0 * ux * M0 + 9.0 * M2ux);
+    const double Gy = src * (3.0 * M1y - 3.0 * uy * M0 + 9.0 * M2uy);
+    const double Gz = src * (3.0 * M1z - 3.0 * uz * M0 + 9.0 * M2uz);
+    // d h / d omega = -(f - f_eq) - S / 2, summed against l:
+    // sum l f_eq = drho M0 + rho (3 M1.u + 9/2 u.M2.u - 3/2 u.u M0),
+    // sum l S = 3 M1.F - 3 u.F M0 + 9 u.M2.F
+    const double lfeq = drho * M0 + rho * (3.0 * M1u + 4.5 * uMu - 1.5 * uu * M0);
+    const double lS = 3.0 * M1F - 3.0 * uF * M0 + 9.0 * uMF;
+    const double t = -(Pg - lfeq) - 0.5 * lS;
     if (inside) dom_in = t;
     else dom = t;
     A = om * A + lrho;
@@ -139,8 +176,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ 
     Bz += lamu[2 * N + s];
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      lam0[qs[i] * N + from[i]] = (1.0 - om) * ls[i] + A +
-                                 (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
+      lam0[source(i)] = (1.0 - om) * lam1[i * N + s] + A +
+                        (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
     lamF[s] = (float)(Gx + 0.5 * Bx * inv);
     lamF[N + s] = (float)(Gy + 0.5 * By * inv);
     lamF[2 * N + s] = (float)(Gz + 0.5 * Bz * inv);
@@ -163,12 +200,30 @@ __global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
-                                                    const float* __restrict__ lamX1,
-                                                    const float4* __restrict__ macro,
-                                                    const float* __restrict__ lamF,
-                                                    float* __restrict__ lamFv,
-                                                    float* __restrict__ lamX0) {
+__global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ lam1,
+                                                     double* __restrict__ lam0,
+                                                     const float* __restrict__ h0,
+                                                     const float* __restrict__ F,
+                                                     const float* __restrict__ lamu,
+                                                     float* __restrict__ lamF,
+                                                     double* __restrict__ domega_part,
+                                                     unsigned char* __restrict__ mask,
+                                                     double* __restrict__ domega_in_part, Lattice L) {
+  adj_collide_body<Lattice>(lam1, lam0, h0, F, lamu, lamF, domega_part, mask, domega_in_part, L);
+}
+
+// Batched form: box blockIdx.y (the grid's x extent is every box's own).
+__global__ __launch_bounds__(256) void k_adj_collide_multi(const AdjCollideArgs* __restrict__ many) {
+  const AdjCollideArgs& a = many[blockIdx.y];
+  adj_collide_body<const Lattice&>(a.lam1, a.lam0, a.h0, a.F, a.lamu, a.lamF, a.domega_part, a.mask,
+                                   a.domega_in_part, a.L);
+}
+
+__device__ __forceinline__ void adj_vertex_body(Cells C, Mesh M, Lattice L,
+                                                const float* __restrict__ lamX1,
+                                                const float4* __restrict__ macro,
+                                                const float* __restrict__ lamF, float* __restrict__ lamFv,
+                                                float* __restrict__ lamX0) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= (int64_t)C.n * M.nv) return;
   const int c = (int)(v / M.nv);
@@ -230,6 +285,20 @@ __global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
   lamX0[3 * v + 2] = luz + gz;
 }
 
+__global__ __launch_bounds__(256) void k_adj_vertex(Cells C, Mesh M, Lattice L,
+                                                    const float* __restrict__ lamX1,
+                                                    const float4* __restrict__ macro,
+                                                    const float* __restrict__ lamF,
+                                                    float* __restrict__ lamFv,
+                                                    float* __restrict__ lamX0) {
+  adj_vertex_body(C, M, L, lamX1, macro, lamF, lamFv, lamX0);
+}
+
+__global__ __launch_bounds__(256) void k_adj_vertex_multi(const AdjVertexArgs* __restrict__ many) {
+  const AdjVertexArgs& a = many[blockIdx.y];
+  adj_vertex_body(a.C, a.M, a.L, a.lamX1, a.macro, a.lamF, a.lamFv, a.lamX0);
+}
+
 __device__ inline V3<Dual> ldd(const float* p, const float* t, int i) {
   return {{p[3 * i], t[3 * i]}, {p[3 * i + 1], t[3 * i + 1]}, {p[3 * i + 2], t[3 * i + 2]}};
 }
@@ -268,10 +337,8 @@ __device__ inline void block_sum4(double (&v)[4], double* red) {
 // for the forward per-cell kernel).  LDS: positions, tangents
 // (= lam_{F_v}), int64 accumulator of the Jacobian-vector product.
 template <int kAdjThreads>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
-                                                              const float* __restrict__ lamFv,
-                                                              float* __restrict__ lamX,
-                                                              double* __restrict__ dk) {
+__device__ __forceinline__ void adj_membrane_body(Cells C, Mesh M, const float* __restrict__ lamFv,
+                                                  float* __restrict__ lamX, double* __restrict__ dk) {
   extern __shared__ long long lds64[];
   __shared__ double red[4 * kAdjThreads / kWave];
   long long* acc = lds64;
@@ -376,6 +443,20 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
   for (int i = tid; i < 3 * M.nv; i += kAdjThreads) lamX[b3 + i] += (float)((double)acc[i] * kFixInv);
 }
 
+template <int kAdjThreads>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_membrane(Cells C, Mesh M,
+                                                              const float* __restrict__ lamFv,
+                                                              float* __restrict__ lamX,
+                                                              double* __restrict__ dk) {
+  adj_membrane_body<kAdjThreads>(C, M, lamFv, lamX, dk);
+}
+
+template <int kAdjThreads>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_membrane_multi(const AdjMembraneArgs* __restrict__ many) {
+  const AdjMembraneArgs& a = many[blockIdx.y];
+  adj_membrane_body<kAdjThreads>(a.C, a.M, a.lamFv, a.lamX, a.dk);
+}
+
 // Loss (D_A - D_A*)^2 + (D_T - D_T*)^2 of every cell from its extents along
 // x and y, and the seed cotangent lam_X = dL/dX (extreme vertices only;
 // ties go to the lower vertex index).  One wave per cell.
@@ -455,6 +536,34 @@ hipError_t launch_adj_membrane(const Cells& c, const Mesh& m, const float* lamFv
     hipLaunchKernelGGL(k_adj_membrane<512>, dim3(c.n), dim3(512), lds, s, c, m, lamFv, lamX, dk);
   else
     hipLaunchKernelGGL(k_adj_membrane<256>, dim3(c.n), dim3(256), lds, s, c, m, lamFv, lamX, dk);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_collide_multi(const AdjCollideArgs& a0, const AdjCollideArgs* dev, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_collide_multi, dim3((unsigned)((a0.L.np + 255) / 256), (unsigned)n), dim3(256), 0, s,
+                     dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_vertex_multi(const AdjVertexArgs& a0, const AdjVertexArgs* dev, int n, hipStream_t s) {
+  const int64_t nv = (int64_t)a0.C.n * a0.M.nv;
+  if (n == 0 || nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_vertex_multi, dim3((unsigned)((nv + 255) / 256), (unsigned)n), dim3(256), 0, s, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_membrane_multi(const AdjMembraneArgs& a0, const AdjMembraneArgs* dev, int n,
+                                     hipStream_t s) {
+  if (n == 0 || a0.C.n == 0) return hipSuccess;
+  const size_t lds = (size_t)a0.M.nv * 3 * (8 + 4 + 4);
+  const dim3 grid((unsigned)a0.C.n, (unsigned)n);
+  if (a0.C.n <= 64)
+    hipLaunchKernelGGL(k_adj_membrane_multi<1024>, grid, dim3(1024), lds, s, dev);
+  else if (a0.C.n <= 1024)
+    hipLaunchKernelGGL(k_adj_membrane_multi<512>, grid, dim3(512), lds, s, dev);
+  else
+    hipLaunchKernelGGL(k_adj_membrane_multi<256>, grid, dim3(256), lds, s, dev);
   return hipGetLastError();
 }
 

@@ -1148,6 +1148,240 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   return HC_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The adjoint over several boxes of one shape: every per-step kernel runs as
+// one batched launch over all boxes (work-group (x, y) = work-group x of box
+// y), on the first context's stream, so the boxes share the chip instead of
+// taking turns.  The arithmetic per box is that of hc_adj_forward /
+// hc_adj_backward, so each box's loss and gradient equal its single-box ones.
+
+namespace {
+
+// Device copy of per-box argument records, laid out [record set][box].
+template <class T>
+struct DevTable {
+  T* dev = nullptr;
+  std::vector<T> host;
+  int n = 0;   // boxes per record set
+  ~DevTable() {
+    if (dev) (void)hipFree(dev);
+  }
+  T& at(int set, int box) { return host[(size_t)set * n + box]; }
+  const T* set(int k) const { return dev + (size_t)k * n; }
+  const T& first(int k) const { return host[(size_t)k * n]; }
+  hipError_t upload(hipStream_t s) {
+    hipError_t e = hipMalloc(&dev, host.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);   // the host records may go once the copy is done
+  }
+};
+
+hc_status multi_check(hc_ctx* const* cs, int n, bool need_ready) {
+  if (!cs || n < 1) return HC_ERR_ARG;
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    if (!c || !c->ws) return fail(cs[0], HC_ERR_STATE, "batched adjoint: a box has no workspace bound");
+    if (!c->adj_ws) return fail(cs[0], HC_ERR_STATE, "no adjoint workspace bound");
+    if (!c->have_cells) return fail(cs[0], HC_ERR_STATE, "adjoint: no cells");
+    if (c->force_every != 1 || c->scheme != HC_EULER || c->L.le || interior_on(c) || c->L.kernel != HC_PHI4)
+      return fail(cs[0], HC_ERR_UNSUPPORTED,
+                  "batched adjoint: Euler steps with forces every step, 4-point kernel, no sheared images, "
+                  "no interior viscosity");
+    if (need_ready && !c->adj_ready) return fail(cs[0], HC_ERR_STATE, "hc_adj_multi_forward must run first");
+    if (!need_ready && c->advect_pending) return fail(cs[0], HC_ERR_STATE, "a vertex move is pending");
+    const hc_ctx* a = cs[0];
+    if (c->L.nx != a->L.nx || c->L.ny != a->L.ny || c->L.nz != a->L.nz || c->L.wall_axis != a->L.wall_axis ||
+        c->L.bc[0] != a->L.bc[0] || c->L.bc[1] != a->L.bc[1] || c->L.bc[2] != a->L.bc[2] ||
+        c->hm.nv != a->hm.nv || c->C.n != a->C.n || c->adj_n != a->adj_n || c->adj_ck != a->adj_ck ||
+        c->L.max_touch != a->L.max_touch || c->B.cap != a->B.cap)
+      return fail(cs[0], HC_ERR_ARG, "batched adjoint: boxes differ in shape, boundaries, cells or run length");
+  }
+  for (int b = 0; b < n; ++b)
+    for (int e = b + 1; e < n; ++e)
+      if (cs[b] == cs[e]) return fail(cs[0], HC_ERR_ARG, "batched adjoint: a context appears twice");
+  for (int b = 0; b < n; ++b) HC_TRY(sync(cs[b], "batched adjoint"));   // earlier work on every stream
+  return HC_OK;
+}
+
+hc_status mcheck(hc_ctx* c, hipError_t e, const char* what) { return check(c, e, what); }
+
+hc_status mcopy(hc_ctx* c, void* dst, const void* src, size_t bytes, hipMemcpyKind k, hipStream_t s) {
+  if (!bytes) return HC_OK;
+  return check(c, hipMemcpyAsync(dst, src, bytes, k, s), "batched adjoint copy");
+}
+
+}  // namespace
+
+extern "C" {
+
+hc_status hc_adj_multi_forward(hc_ctx* const* cs, int32_t n, const double* targets, double* loss) {
+  HC_TRY(multi_check(cs, n, false));
+  if (!targets || !loss) return fail(cs[0], HC_ERR_ARG, "null targets or loss");
+  hc_ctx* c0 = cs[0];
+  hipStream_t s = c0->stream;
+  const int C = c0->C.n, ns = c0->adj_n, ck = c0->adj_ck;
+  const int64_t P = 19 * c0->L.np, X = (int64_t)C * c0->hm.nv * 3;
+  // record sets: [parity q][advect] for the per-cell kernel, [parity q] for the lattice pass
+  DevTable<CellStepArgs> cell;
+  DevTable<TileStepArgs> tile;
+  cell.n = tile.n = n;
+  cell.host.resize((size_t)4 * n);
+  tile.host.resize((size_t)2 * n);
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    for (int q = 0; q < 2; ++q) {
+      const int in = c->cur ^ q;
+      for (int adv = 0; adv < 2; ++adv)
+        cell.at(2 * q + adv, b) = CellStepArgs{c->C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, 1, 0, 0};
+      tile.at(q, b) = TileStepArgs{c->C, c->M, c->L, c->B, c->pops[in], c->pops[in ^ 1], c->F, c->macro,
+                                   c->partial, c->fields ? 1 : 0, nullptr};
+    }
+    HC_TRY(mcopy(c0, c->targets, targets + (size_t)b * C * 2, (size_t)C * 16, hipMemcpyHostToDevice, s));
+  }
+  HC_TRY(mcheck(c0, cell.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, tile.upload(s), "batched adjoint tables"));
+  for (int st = 0; st < ns; ++st) {
+    const int q = st & 1;
+    if (st % ck == 0) {
+      const int k = st / ck;
+      for (int b = 0; b < n; ++b) {
+        hc_ctx* c = cs[b];
+        HC_TRY(mcopy(c0, c->ck_pops + k * P, c->pops[c->cur ^ q], (size_t)P * 4, hipMemcpyDeviceToDevice, s));
+        HC_TRY(mcopy(c0, c->ck_off + k * X, c->C.off, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
+        HC_TRY(mcopy(c0, c->ck_lo + k * X, c->C.lo, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
+      }
+    }
+    const int adv = st % ck != 0 ? 1 : 0;   // each segment ends with its move applied
+    HC_TRY(mcheck(c0, launch_cell_step_multi(cell.first(2 * q + adv), cell.set(2 * q + adv), n, s), "cell step"));
+    HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(q), tile.set(q), n, s), "lattice pass"));
+    if ((st + 1) % ck == 0 || st + 1 == ns)
+      for (int b = 0; b < n; ++b) {
+        hc_ctx* c = cs[b];
+        HC_TRY(mcheck(c0, launch_advect(c->C, c->M, c->L, c->B, c->partial, c->B.flags, false, s), "advect"));
+      }
+  }
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    HC_TRY(mcheck(c0, launch_loss_seed(c->C, c->M, c->targets, c->loss, c->lam_X[0], s), "loss"));
+    HC_TRY(mcopy(c0, loss + (size_t)b * C, c->loss, (size_t)C * 8, hipMemcpyDeviceToHost, s));
+  }
+  HC_TRY(mcheck(c0, hipStreamSynchronize(s), "batched adjoint forward"));
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    c->cur ^= ns & 1;
+    c->step += ns;
+    c->advect_pending = false;
+    c->have_prev = true;
+    c->L.le_raw = 0;
+    c->adj_ready = true;
+  }
+  return HC_OK;
+}
+
+hc_status hc_adj_multi_backward(hc_ctx* const* cs, int32_t n, double* grad) {
+  HC_TRY(multi_check(cs, n, true));
+  if (!grad) return fail(cs[0], HC_ERR_ARG, "null gradient");
+  hc_ctx* c0 = cs[0];
+  hipStream_t s = c0->stream;
+  const int C = c0->C.n, ck = c0->adj_ck;
+  const int64_t N = c0->L.np, P = 19 * N, X = (int64_t)C * c0->hm.nv * 3;
+  const int nblk = (int)((N + 255) / 256);
+  DevTable<CellStepArgs> cell;
+  DevTable<TileStepArgs> tile;
+  DevTable<BinArgs> bins;
+  DevTable<SpreadArgs> spread;
+  DevTable<AdjCollideArgs> coll;
+  DevTable<AdjVertexArgs> vert;
+  DevTable<AdjMembraneArgs> memb;
+  cell.n = tile.n = bins.n = spread.n = coll.n = vert.n = memb.n = n;
+  cell.host.resize((size_t)ck * n);
+  tile.host.resize((size_t)ck * n);
+  bins.host.resize((size_t)ck * n);
+  spread.host.resize((size_t)2 * ck * n);
+  coll.host.resize((size_t)2 * ck * n);
+  vert.host.resize((size_t)2 * ck * n);
+  memb.host.resize((size_t)2 * ck * n);
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    for (int i = 0; i < ck; ++i) {
+      Cells Ci = c->C;
+      Ci.off = c->sg_off + i * X;
+      Ci.lo = c->sg_lo;
+      Ci.force = c->sg_Fv + i * X;
+      Ci.vel = c->vel_scratch;
+      const float* prev = i > 0 ? c->sg_off + (i - 1) * X : nullptr;
+      cell.at(i, b) = CellStepArgs{Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0 ? 1 : 0, prev, 1, 0, 0};
+      tile.at(i, b) = TileStepArgs{Ci, c->M, c->L, c->B, c->sg_pops + i * P, c->sg_pops + (i + 1) * P,
+                                   c->sg_F + i * 3 * N, c->sg_macro + i * N, c->partial, 1, nullptr};
+      bins.at(i, b) = BinArgs{Ci, c->M, c->L, c->B};
+      for (int a = 0; a < 2; ++a) {
+        const int k = 2 * i + a;
+        spread.at(k, b) = SpreadArgs{Ci, c->M, c->L, c->B, c->lam_X[a], 0.f, c->lam_u};
+        coll.at(k, b) = AdjCollideArgs{c->lam_f[a], c->lam_f[a ^ 1], c->sg_pops + i * P, c->sg_F + i * 3 * N,
+                                       c->lam_u, c->lam_F, c->dom_part, nullptr, c->dom_in_part, c->L};
+        vert.at(k, b) = AdjVertexArgs{Ci, c->M, c->L, c->lam_X[a], c->sg_macro + i * N, c->lam_F, c->lam_Fv,
+                                      c->lam_X[a ^ 1]};
+        memb.at(k, b) = AdjMembraneArgs{Ci, c->M, c->lam_Fv, c->lam_X[a ^ 1], c->dk};
+      }
+    }
+    HC_TRY(mcheck(c0, launch_zero_f64(c->lam_f[0], P, s), "zero"));
+    HC_TRY(mcheck(c0, launch_zero_f64(c->dk, (int64_t)C * 4, s), "zero"));
+    HC_TRY(mcheck(c0, launch_zero_f64(c->dom_part, nblk, s), "zero"));
+    HC_TRY(mcheck(c0, launch_zero_f64(c->dom_in_part, (int64_t)kVisClasses * nblk, s), "zero"));
+  }
+  HC_TRY(mcheck(c0, cell.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, tile.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, bins.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, spread.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, coll.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, vert.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, memb.upload(s), "batched adjoint tables"));
+  int a = 0;   // lam_f[a], lam_X[a] hold the cotangents of the later state
+  for (int seg = c0->adj_nseg - 1; seg >= 0; --seg) {
+    const int len = std::min(ck, c0->adj_n - seg * ck);
+    for (int b = 0; b < n; ++b) {
+      hc_ctx* c = cs[b];
+      HC_TRY(mcopy(c0, c->sg_pops, c->ck_pops + seg * P, (size_t)P * 4, hipMemcpyDeviceToDevice, s));
+      HC_TRY(mcopy(c0, c->sg_off, c->ck_off + seg * X, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
+      HC_TRY(mcopy(c0, c->sg_lo, c->ck_lo + seg * X, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
+    }
+    for (int i = 0; i < len; ++i) {
+      HC_TRY(mcheck(c0, launch_cell_step_multi(cell.first(i), cell.set(i), n, s), "cell step"));
+      HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(i), tile.set(i), n, s), "lattice pass"));
+    }
+    for (int i = len - 1; i >= 0; --i) {
+      const int k = 2 * i + a;
+      HC_TRY(mcheck(c0, launch_bin_vertices_multi(bins.first(i), bins.set(i), n, s), "binning"));
+      HC_TRY(mcheck(c0, launch_spread_vec_multi(spread.first(k), spread.set(k), n, s), "spread"));
+      HC_TRY(mcheck(c0, launch_adj_collide_multi(coll.first(k), coll.set(k), n, s), "adjoint collide"));
+      HC_TRY(mcheck(c0, launch_adj_vertex_multi(vert.first(k), vert.set(k), n, s), "adjoint ibm"));
+      HC_TRY(mcheck(c0, launch_adj_membrane_multi(memb.first(k), memb.set(k), n, s), "adjoint membrane"));
+      a ^= 1;
+    }
+  }
+  std::vector<double> dk((size_t)n * C * 4), dom((size_t)n * (1 + kVisClasses));
+  for (int b = 0; b < n; ++b) {
+    hc_ctx* c = cs[b];
+    HC_TRY(mcheck(c0, launch_sum_parts(c->dom_part, nblk, c->scal, s), "sum"));
+    HC_TRY(mcopy(c0, dk.data() + (size_t)b * C * 4, c->dk, (size_t)C * 32, hipMemcpyDeviceToHost, s));
+    HC_TRY(mcopy(c0, dom.data() + (size_t)b * (1 + kVisClasses), c->scal, 8, hipMemcpyDeviceToHost, s));
+  }
+  HC_TRY(mcheck(c0, hipStreamSynchronize(s), "batched adjoint backward"));
+  for (int b = 0; b < n; ++b) {
+    const double om = cs[b]->L.omega;
+    const double dtau = -om * om * dom[(size_t)b * (1 + kVisClasses)];
+    for (int i = 0; i < C; ++i) {
+      for (int j = 0; j < 4; ++j) grad[((size_t)b * C + i) * 5 + j] = dk[((size_t)b * C + i) * 4 + j];
+      grad[((size_t)b * C + i) * 5 + 4] = dtau;
+    }
+  }
+  return HC_OK;
+}
+
 hc_status hc_get_step(const hc_ctx* c, int64_t* step) {
   if (!c || !step) return HC_ERR_ARG;
   *step = c->step;

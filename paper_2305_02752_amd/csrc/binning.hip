@@ -15,8 +15,8 @@
 namespace hc {
 namespace {
 
-template <bool LE, int kThreads>
-__global__ __launch_bounds__(kThreads) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
+template <bool LE>
+__device__ __forceinline__ void bin_vertices_body(Cells C, Mesh M, Lattice L, Bins B) {
   extern __shared__ unsigned short slots[];
   __shared__ int keys[bin::kHash], count[bin::kHash], base[bin::kHash];
   const int c = blockIdx.x;
@@ -24,6 +24,18 @@ __global__ __launch_bounds__(kThreads) void k_bin_vertices(Cells C, Mesh M, Latt
   unsigned char* shash = reinterpret_cast<unsigned char*>(slots + (size_t)M.nv * L.max_touch);
   bin::bin_cell<LE>(C, M, L, B, c, C.off + (int64_t)c * M.nv * 3, keys, count, base, srank, shash,
                     threadIdx.x, blockDim.x);
+}
+
+template <bool LE, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_bin_vertices(Cells C, Mesh M, Lattice L, Bins B) {
+  bin_vertices_body<LE>(C, M, L, B);
+}
+
+// Batched form: box blockIdx.y.
+template <int kThreads>
+__global__ __launch_bounds__(kThreads) void k_bin_vertices_multi(const BinArgs* __restrict__ many) {
+  const BinArgs& a = many[blockIdx.y];
+  bin_vertices_body<false>(a.C, a.M, a.L, a.B);
 }
 
 // Copy the fixed-capacity tile lists into CSR form (read-out path).
@@ -221,6 +233,18 @@ hipError_t launch_bin_vertices(const Cells& c, const Mesh& m, const Lattice& L, 
     hipLaunchKernelGGL((k_bin_vertices<false, 1024>), dim3(c.n), dim3(1024), lds, s, c, m, L, b);
   else
     hipLaunchKernelGGL((k_bin_vertices<false, 256>), dim3(c.n), dim3(256), lds, s, c, m, L, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_vertices_multi(const BinArgs& a0, const BinArgs* dev, int n, hipStream_t s) {
+  if (n == 0 || a0.C.n == 0) return hipSuccess;
+  if (a0.L.le) return hipErrorInvalidValue;
+  const size_t lds = (size_t)a0.M.nv * bin::slot_lds_per_vertex(a0.L.max_touch);
+  const dim3 grid((unsigned)a0.C.n, (unsigned)n);
+  if (a0.C.n <= 64)
+    hipLaunchKernelGGL((k_bin_vertices_multi<1024>), grid, dim3(1024), lds, s, dev);
+  else
+    hipLaunchKernelGGL((k_bin_vertices_multi<256>), grid, dim3(256), lds, s, dev);
   return hipGetLastError();
 }
 

@@ -84,11 +84,10 @@ __device__ void recentre_cell(const Cells& C, const Mesh& M, int c, float* sp, f
 // cells than a few per CU each cell's work-group is widened so that its
 // latency-bound loops take fewer rounds.
 template <int K, int kCellThreads, bool LE>
-__global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
-                                                           const float4* __restrict__ partial,
-                                                           int* __restrict__ flags, int advect,
-                                                           const float* __restrict__ src,
-                                                           int refresh, int ab2, int recentre) {
+__device__ __forceinline__ void cell_step_body(Cells C, Mesh M, Lattice L, Bins B,
+                                               const float4* __restrict__ partial, int* __restrict__ flags,
+                                               int advect, const float* __restrict__ src, int refresh, int ab2,
+                                               int recentre) {
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
   __shared__ float ext[6][kCellThreads / kWave];
@@ -127,6 +126,23 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
   bin::bin_cell<LE>(C, M, L, B, c, sp, keys, count, base, srank, shash, tid, kCellThreads);
 }
 
+template <int K, int kCellThreads, bool LE>
+__global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lattice L, Bins B,
+                                                           const float4* __restrict__ partial,
+                                                           int* __restrict__ flags, int advect,
+                                                           const float* __restrict__ src,
+                                                           int refresh, int ab2, int recentre) {
+  cell_step_body<K, kCellThreads, LE>(C, M, L, B, partial, flags, advect, src, refresh, ab2, recentre);
+}
+
+// Batched form: box blockIdx.y.
+template <int K, int kCellThreads>
+__global__ __launch_bounds__(kCellThreads) void k_cell_step_multi(const CellStepArgs* __restrict__ many) {
+  const CellStepArgs& a = many[blockIdx.y];
+  cell_step_body<K, kCellThreads, false>(a.C, a.M, a.L, a.B, a.partial, a.flags, a.advect, a.src, a.refresh,
+                                         a.ab2, a.recentre);
+}
+
 }  // namespace
 
 // Tile-list counts must be zero on entry (see launch_bin_vertices).
@@ -154,6 +170,28 @@ hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, con
   } else {
     if (L.kernel == 4) go(k_cell_step<4, 256, false>, 256);
     else go(k_cell_step<2, 256, false>, 256);
+  }
+  return hipGetLastError();
+}
+
+// Boxes of one shape without sheared images; every box holds the same number
+// of cells.
+hipError_t launch_cell_step_multi(const CellStepArgs& a0, const CellStepArgs* dev, int n, hipStream_t s) {
+  if (n == 0 || a0.C.n == 0) return hipSuccess;
+  if (a0.L.le) return hipErrorInvalidValue;
+  const int region = std::max(24, bin::slot_lds_per_vertex(a0.L.max_touch)) * a0.M.nv;
+  const size_t lds = (size_t)((region + 7) & ~7) + (size_t)a0.M.nv * 3 * sizeof(float);
+  const dim3 grid((unsigned)a0.C.n, (unsigned)n);
+  auto go = [&](auto kern, int threads) { hipLaunchKernelGGL(kern, grid, dim3(threads), lds, s, dev); };
+  if (a0.C.n <= 64) {
+    if (a0.L.kernel == 4) go(k_cell_step_multi<4, 1024>, 1024);
+    else go(k_cell_step_multi<2, 1024>, 1024);
+  } else if (a0.C.n <= 1024) {
+    if (a0.L.kernel == 4) go(k_cell_step_multi<4, 512>, 512);
+    else go(k_cell_step_multi<2, 512>, 512);
+  } else {
+    if (a0.L.kernel == 4) go(k_cell_step_multi<4, 256>, 256);
+    else go(k_cell_step_multi<2, 256>, 256);
   }
   return hipGetLastError();
 }

@@ -194,6 +194,39 @@ hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             const float4* partial, int* flags, bool advect, const float* src,
                             bool refresh, bool ab2, bool recentre, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Batched forms of the per-step kernels for several boxes of one shape (one
+// launch covers every box: work-group (x, y) does work-group x of box y with
+// box y's arguments, read from the device array `dev` of n records; `a0` is
+// box 0's record on the host, which fixes the grid and the kernel variant).
+struct CellStepArgs {
+  Cells C; Mesh M; Lattice L; Bins B;
+  const float4* partial; int* flags; int advect; const float* src; int refresh; int ab2; int recentre;
+};
+struct TileStepArgs {
+  Cells C; Mesh M; Lattice L; Bins B;
+  const float* gin; float* gout; float* F; float4* macro; float4* partial; int fields; unsigned char* mask;
+};
+struct BinArgs { Cells C; Mesh M; Lattice L; Bins B; };
+struct SpreadArgs { Cells C; Mesh M; Lattice L; Bins B; const float* vec; float body; float* F; };
+struct AdjCollideArgs {
+  const double* lam1; double* lam0; const float* h0; const float* F; const float* lamu; float* lamF;
+  double* domega_part; unsigned char* mask; double* domega_in_part; Lattice L;
+};
+struct AdjVertexArgs {
+  Cells C; Mesh M; Lattice L;
+  const float* lamX1; const float4* macro; const float* lamF; float* lamFv; float* lamX0;
+};
+struct AdjMembraneArgs { Cells C; Mesh M; const float* lamFv; float* lamX; double* dk; };
+hipError_t launch_cell_step_multi(const CellStepArgs& a0, const CellStepArgs* dev, int n, hipStream_t s);
+hipError_t launch_tile_step_multi(const TileStepArgs& a0, const TileStepArgs* dev, int n, hipStream_t s);
+hipError_t launch_bin_vertices_multi(const BinArgs& a0, const BinArgs* dev, int n, hipStream_t s);
+hipError_t launch_spread_vec_multi(const SpreadArgs& a0, const SpreadArgs* dev, int n, hipStream_t s);
+hipError_t launch_adj_collide_multi(const AdjCollideArgs& a0, const AdjCollideArgs* dev, int n, hipStream_t s);
+hipError_t launch_adj_vertex_multi(const AdjVertexArgs& a0, const AdjVertexArgs* dev, int n, hipStream_t s);
+hipError_t launch_adj_membrane_multi(const AdjMembraneArgs& a0, const AdjMembraneArgs* dev, int n,
+                                     hipStream_t s);
+
 // stored (pull-form) state of a uniform equilibrium on the tile-major lattice
 hipError_t launch_init_equilibrium(float* g, float rho0, float ux, float uy, float uz,
                                    const Lattice& L, hipStream_t s);

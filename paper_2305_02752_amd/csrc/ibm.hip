@@ -265,9 +265,8 @@ __device__ inline void interp_tile(const Cells& C, const Mesh& M, const Lattice&
 // with it): writes body * g + the spread field, tile-major (padding slots
 // receive body * g).
 template <int K>
-__global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
-                                                const float* __restrict__ vec, float body,
-                                                float* __restrict__ F) {
+__device__ __forceinline__ void spread_body(Cells C, Mesh M, Lattice L, Bins B,
+                                            const float* __restrict__ vec, float body, float* __restrict__ F) {
   __shared__ long long acc[3][kTile * kTile * kTile];
   const int t = blockIdx.x;
   int x0, y0, z0;
@@ -288,6 +287,19 @@ __global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins
     F[NP + h0 + i] = body * L.g[1] + (float)((double)acc[1][i] * kFixInv);
     F[2 * NP + h0 + i] = body * L.g[2] + (float)((double)acc[2][i] * kFixInv);
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_spread(Cells C, Mesh M, Lattice L, Bins B,
+                                                const float* __restrict__ vec, float body,
+                                                float* __restrict__ F) {
+  spread_body<K>(C, M, L, B, vec, body, F);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_spread_multi(const SpreadArgs* __restrict__ many) {
+  const SpreadArgs& a = many[blockIdx.y];
+  spread_body<K>(a.C, a.M, a.L, a.B, a.vec, a.body, a.F);
 }
 
 // Which tile block b works on.  Work-groups go to the 8 XCDs round-robin by
@@ -676,14 +688,17 @@ __device__ __forceinline__ void interp(int m, const Smem& S, int64_t stride, flo
 // Tiles with more entries than the LDS stages at once take them in chunks
 // (the scale then comes from a first pass over all their forces, and the
 // interpolation stages the chunks again).
-template <int K, bool W>
-__global__ __launch_bounds__(256) void k_tile_step_sorted(Cells C, Mesh M, Lattice L, Bins B,
-                                                          const float* __restrict__ gin,
-                                                          float* __restrict__ gout,
-                                                          float* __restrict__ F,
-                                                          float4* __restrict__ macro,
-                                                          float4* __restrict__ partial, int fields,
-                                                          unsigned char* __restrict__ mask) {
+// The struct arguments come by value from the single-box kernel (its own
+// parameters) and by reference to global memory from the batched one: a
+// reference to a kernel's by-value parameter, or a by-value copy of a record
+// in global memory, would put the lattice record in scratch.
+template <int K, bool W, class CT, class MT, class LT, class BT>
+__device__ __forceinline__ void tile_step_sorted_body(CT C, MT M, LT L, BT B,
+                                                      const float* __restrict__ gin,
+                                                      float* __restrict__ gout, float* __restrict__ F,
+                                                      float4* __restrict__ macro,
+                                                      float4* __restrict__ partial, int fields,
+                                                      unsigned char* __restrict__ mask) {
   __shared__ srt::Smem S;
   const int t = tile_of_block(L, blockIdx.x);
   if (t < 0) return;
@@ -815,6 +830,25 @@ __global__ __launch_bounds__(256) void k_tile_step_sorted(Cells C, Mesh M, Latti
   if (threadIdx.x == 0) B.touch_cnt[t] = 0;
 }
 
+template <int K, bool W>
+__global__ __launch_bounds__(256) void k_tile_step_sorted(Cells C, Mesh M, Lattice L, Bins B,
+                                                          const float* __restrict__ gin,
+                                                          float* __restrict__ gout,
+                                                          float* __restrict__ F,
+                                                          float4* __restrict__ macro,
+                                                          float4* __restrict__ partial, int fields,
+                                                          unsigned char* __restrict__ mask) {
+  tile_step_sorted_body<K, W, Cells, Mesh, Lattice, Bins>(C, M, L, B, gin, gout, F, macro, partial, fields, mask);
+}
+
+// Batched form: box blockIdx.y.
+template <int K, bool W>
+__global__ __launch_bounds__(256) void k_tile_step_sorted_multi(const TileStepArgs* __restrict__ many) {
+  const TileStepArgs& a = many[blockIdx.y];
+  tile_step_sorted_body<K, W, const Cells&, const Mesh&, const Lattice&, const Bins&>(
+      a.C, a.M, a.L, a.B, a.gin, a.gout, a.F, a.macro, a.partial, a.fields, a.mask);
+}
+
 // The fused lattice pass of one step, one work-group per tile:
 //  1. spread the vertex forces of every entry reaching the tile into LDS;
 //  2. pull-stream + collide the tile's nodes (force = body force + spread
@@ -916,6 +950,33 @@ hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, co
     hipLaunchKernelGGL(k_spread<4>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
   else
     hipLaunchKernelGGL(k_spread<2>, dim3(L.ntiles), dim3(256), 0, s, c, m, L, b, vec, body, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread_vec_multi(const SpreadArgs& a0, const SpreadArgs* dev, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)a0.L.ntiles, (unsigned)n);
+  if (a0.L.kernel == 4)
+    hipLaunchKernelGGL(k_spread_multi<4>, grid, dim3(256), 0, s, dev);
+  else
+    hipLaunchKernelGGL(k_spread_multi<2>, grid, dim3(256), 0, s, dev);
+  return hipGetLastError();
+}
+
+// Boxes of one shape and one kind of boundary (walled or not), without
+// sheared images.
+hipError_t launch_tile_step_multi(const TileStepArgs& a0, const TileStepArgs* dev, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (a0.L.le) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tile_grid(a0.L), (unsigned)n);
+  const bool w = a0.L.wall_axis >= 0;
+  if (a0.L.kernel == 4) {
+    if (w) hipLaunchKernelGGL((k_tile_step_sorted_multi<4, true>), grid, dim3(256), 0, s, dev);
+    else hipLaunchKernelGGL((k_tile_step_sorted_multi<4, false>), grid, dim3(256), 0, s, dev);
+  } else {
+    if (w) hipLaunchKernelGGL((k_tile_step_sorted_multi<2, true>), grid, dim3(256), 0, s, dev);
+    else hipLaunchKernelGGL((k_tile_step_sorted_multi<2, false>), grid, dim3(256), 0, s, dev);
+  }
   return hipGetLastError();
 }
 

@@ -81,6 +81,8 @@ def _declare(lib):
         "hc_adj_bind_workspace": [_P, _P, sz, i32, i32],
         "hc_adj_forward": [_P, _P, _P],
         "hc_adj_backward": [_P, _P],
+        "hc_adj_multi_forward": [_P, i32, _P, _P],
+        "hc_adj_multi_backward": [_P, i32, _P],
         "hc_pack_query_workspace": [_P, i32, _P],
         "hc_pack_run": [_P, _P, _P, _P, i32, i32, _P, sz, _P, _P],
         "hc_pack_run_static": [_P, _P, _P, _P, i32, i32, _P, _P],
@@ -347,6 +349,33 @@ class Simulation:
     def adj_backward(self) -> np.ndarray:
         g = np.empty((self.n_cells, 5), dtype=np.float64)
         self._check(self.lib.hc_adj_backward(self.ctx, _ptr(g)))
+        return g
+
+    @staticmethod
+    def _ctx_array(sims):
+        arr = (C.c_void_p * len(sims))(*[s.ctx for s in sims])
+        return arr
+
+    @staticmethod
+    def adj_multi_forward(sims, targets) -> np.ndarray:
+        """hc_adj_multi_forward over boxes of one shape: every per-step kernel
+        is one launch over all boxes (on the first box's stream).  targets
+        [B][cells][2]; returns the losses [B][cells]."""
+        n, nc = len(sims), sims[0].n_cells
+        t = np.ascontiguousarray(targets, dtype=np.float64).reshape(n, nc, 2)
+        loss = np.empty((n, nc), dtype=np.float64)
+        arr = Simulation._ctx_array(sims)
+        sims[0]._check(sims[0].lib.hc_adj_multi_forward(C.cast(arr, C.c_void_p), n, _ptr(t), _ptr(loss)))
+        return loss
+
+    @staticmethod
+    def adj_multi_backward(sims) -> np.ndarray:
+        """hc_adj_multi_backward: gradients [B][cells][5] of the last
+        hc_adj_multi_forward."""
+        n, nc = len(sims), sims[0].n_cells
+        g = np.empty((n, nc, 5), dtype=np.float64)
+        arr = Simulation._ctx_array(sims)
+        sims[0]._check(sims[0].lib.hc_adj_multi_backward(C.cast(arr, C.c_void_p), n, _ptr(g)))
         return g
 
     def checkpoint_save(self) -> bytes:
