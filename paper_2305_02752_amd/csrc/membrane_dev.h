@@ -102,11 +102,15 @@ __device__ inline void add_force(long long* acc, int v, f3 f) {
 
 // Cell area and volume (float64 sums over triangles, fixed-order reduction
 // over the nthr cooperating threads; red holds 2 * nthr / 64 doubles).
-__device__ inline void area_volume(const Mesh& M, const float* sp, double* red, int tid, int nthr,
-                                   double& A, double& V) {
+// Area and volume of the cell in FP64, by the 64 lanes of one wave: lane i
+// sums triangles i, i + 64, ... in order and the 64 partial sums are
+// combined by a fixed butterfly, so the result does not depend on how many
+// threads share the cell (the per-cell kernel widens its work-group when
+// the cells are few).  Every lane ends with the totals.
+__device__ inline void area_volume_wave(const Mesh& M, const float* sp, int lane, double& A, double& V) {
   A = 0.0;
   V = 0.0;
-  for (int t = tid; t < M.nt; t += nthr) {
+  for (int t = lane; t < M.nt; t += kWave) {
     const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
     const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
     const double cx = xc.x, cy = xc.y, cz = xc.z;
@@ -118,19 +122,6 @@ __device__ inline void area_volume(const Mesh& M, const float* sp, double* red, 
   for (int m = kWave / 2; m > 0; m >>= 1) {
     A += __shfl_xor(A, m);
     V += __shfl_xor(V, m);
-  }
-  const int nw = nthr / kWave;
-  __syncthreads();
-  if ((tid & (kWave - 1)) == 0) {
-    red[tid / kWave] = A;
-    red[nw + tid / kWave] = V;
-  }
-  __syncthreads();
-  A = 0.0;
-  V = 0.0;
-  for (int w = 0; w < nw; ++w) {   // fixed order: reproducible sums
-    A += red[w];
-    V += red[nw + w];
   }
 }
 
@@ -147,31 +138,28 @@ __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ of
     acc[i] = 0;
   }
   __syncthreads();
-  double A, V;
-  area_volume(M, sp, red, tid, nthr, A, V);
-  if (tid == 0) {
-    *area = A;
-    *volume = V;
-  }
+  // wave 0: area and volume; meanwhile the other waves take the links and
+  // hinges, which do not need them (fixed-point sums: any order).  A single
+  // wave does both in turn.
   const float kl = k4[0], kb = k4[1], ka = k4[2], kv = k4[3];
-  const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
-  const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
-
-  for (int t = tid; t < M.nt; t += nthr) {
-    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-    f3 fa, fb, fc;
-    tri_forces<float>(ld3(sp, ia), ld3(sp, ib), ld3(sp, ic), ca, cv, fa, fb, fc);
-    add_force(acc, ia, fa);
-    add_force(acc, ib, fb);
-    add_force(acc, ic, fc);
+  if (tid < kWave) {
+    double A, V;
+    area_volume_wave(M, sp, tid, A, V);
+    if (tid == 0) {
+      red[0] = A;
+      red[1] = V;
+      *area = A;
+      *volume = V;
+    }
   }
-  for (int e = tid; e < M.ne; e += nthr) {
+  const int e0 = nthr > kWave ? tid - kWave : tid, es = nthr > kWave ? nthr - kWave : nthr;
+  for (int e = e0; e >= 0 && e < M.ne; e += es) {
     const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
     const f3 f = link_force<float>(ld3(sp, i), ld3(sp, j), M.L0[e], kl);
     add_force(acc, i, f);
     add_force(acc, j, -1.f * f);
   }
-  for (int h = tid; h < M.nh; h += nthr) {
+  for (int h = e0; h >= 0 && h < M.nh; h += es) {
     const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
     const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
     f3 fi, fj, fk, fl;
@@ -181,6 +169,18 @@ __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ of
     add_force(acc, l, fl);
     add_force(acc, i, fi);
     add_force(acc, j, fj);
+  }
+  __syncthreads();   // area and volume in red
+  const double A = red[0], V = red[1];
+  const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
+  const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
+  for (int t = tid; t < M.nt; t += nthr) {
+    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
+    f3 fa, fb, fc;
+    tri_forces<float>(ld3(sp, ia), ld3(sp, ib), ld3(sp, ic), ca, cv, fa, fb, fc);
+    add_force(acc, ia, fa);
+    add_force(acc, ib, fb);
+    add_force(acc, ic, fc);
   }
   __syncthreads();
 

@@ -339,3 +339,37 @@ def test_cell_carried_past_recentring():
     assert np.array_equal(owner, ow)
     assert np.array_equal(cptr, cptr_r) and np.array_equal(clist, clist_r)
     assert np.array_equal(tptr, tptr_r) and np.array_equal(touch, touch_r)
+
+
+def test_membrane_forces_independent_of_workgroup_size():
+    """One jittered cell's membrane forces and FP64 area/volume are bit for
+    bit the same whether the per-cell kernel runs it with 1024 threads (1
+    cell), 512 (65 cells) or 256 (1025 cells), and as hc_compute_forces
+    (256 threads): the area/volume sums do not depend on the work-group."""
+    from types import SimpleNamespace
+
+    from workloads import rbc_mesh
+    from workloads.configs import random_rotation
+    rng = np.random.default_rng(23)
+    rest64, tri = rbc_mesh()
+    lat = Lattice(128, 128, 128)
+    n_max = 1025
+    cen = rng.uniform(8, 120, (n_max, 3))
+    rots = np.stack([random_rotation(rng) for _ in range(n_max)])
+    k = K_REF[None] * 10.0 ** rng.uniform(-0.5, 0.5, (n_max, 4))
+    cells = jitter_cells(rng, place_cells(rest64, cen, rots, k, traction=rng.uniform(-1e-3, 1e-3, (n_max, 3))), 0.05)
+    out = []
+    for n in (1, 65, 1025):
+        sub = SimpleNamespace(origin=cells.origin[:n], offsets=cells.offsets[:n], k=cells.k[:n],
+                              traction=cells.traction[:n], n=n)
+        sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest64.astype(np.float32), tri=tri, cells=sub), sub)
+        fv2, area, volume = sim.compute_forces()   # 256 threads, initial positions
+        fv2 = fv2[0].copy()
+        sim.step(1)                                # the first step's forces, same positions
+        sim.sync()
+        _, _, fv = sim.read_vertices()
+        out.append((fv[0].copy(), fv2, area[0], volume[0]))
+        sim.close()
+    for fv, fv2, a, v in out:
+        assert np.array_equal(fv, out[0][0]) and np.array_equal(fv2, out[0][0])
+        assert a == out[0][2] and v == out[0][3]
