@@ -114,6 +114,20 @@ const char* hc_last_error(const hc_ctx* ctx);
 /* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
 hc_status hc_set_stream(hc_ctx* ctx, void* hip_stream);
 
+/* Entries per tile list (Sec. 2.6 domain bookkeeping: which tile holds
+ * which vertex stencils).  Each 8^3 tile keeps one list of the (vertex,
+ * tile) pairs that reach it, of fixed capacity: 2048 by default (4 per
+ * node, about 4x the mean of a 44% haematocrit suspension).  entries in
+ * [64, 16384]; only before hc_bind_workspace (HC_ERR_STATE after), since
+ * the lists live in the workspace.  hc_set_cells refuses cells whose
+ * fullest list would exceed the capacity (HC_ERR_UNSUPPORTED, with the
+ * capacity needed); a list that overflows later, as cells crowd, loses
+ * entries of that step and is reported by hc_sync. */
+hc_status hc_set_list_capacity(hc_ctx* ctx, int32_t entries);
+/* Entries the fullest tile list holds for the current positions (after
+ * applying a pending move), and the capacity (may be NULL). */
+hc_status hc_densest_tile(hc_ctx* ctx, int32_t* entries, int32_t* capacity);
+
 /* Device bytes the context needs (populations x2, fields, cells, bins). */
 hc_status hc_query_workspace(const hc_ctx* ctx, size_t* bytes);
 /* dev_ptr: device buffer of >= the queried bytes, 256-byte aligned, owned by

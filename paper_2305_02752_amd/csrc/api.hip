@@ -558,6 +558,25 @@ hc_status hc_set_stream(hc_ctx* c, void* s) {
   return HC_OK;
 }
 
+static hc_status densest_tile(hc_ctx* c, int32_t* out);
+
+hc_status hc_set_list_capacity(hc_ctx* c, int32_t entries) {
+  if (!c) return HC_ERR_ARG;
+  if (c->ws) return fail(c, HC_ERR_STATE, "set the list capacity before binding the workspace");
+  if (entries < 64 || entries > (1 << 14)) return fail(c, HC_ERR_ARG, "list capacity outside [64, 16384]");
+  c->list_cap = entries;
+  return HC_OK;
+}
+
+hc_status hc_densest_tile(hc_ctx* c, int32_t* entries, int32_t* capacity) {
+  HC_TRY(need_ws(c));
+  if (!entries) return fail(c, HC_ERR_ARG, "null pointer");
+  HC_TRY(flush(c));
+  HC_TRY(densest_tile(c, entries));
+  if (capacity) *capacity = c->list_cap;
+  return HC_OK;
+}
+
 hc_status hc_query_workspace(const hc_ctx* c, size_t* bytes) {
   if (!c || !bytes) return HC_ERR_ARG;
   Layout lay;
@@ -614,6 +633,8 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   B.touch_cnt = at<int>(c, c->o_tcnt);
   B.touch = at<int>(c, c->o_touch);
   B.cap = c->list_cap;
+  B.bexp = 30;
+  while ((int64_t)B.cap << B.bexp > ((int64_t)1 << 30)) --B.bexp;   // cap 2^bexp <= 2^30
   c->touch_ptr = at<int>(c, c->o_tptr);
   c->touch_csr = at<int>(c, c->o_csr);
   B.flags = at<int>(c, c->o_flags);
@@ -640,6 +661,24 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   return sync(c, "bind");
 }
 
+// Entries of the fullest tile list for the current positions (a binning
+// pass counts every (vertex, tile) pair, also past the capacity); leaves the
+// lists and the overflow flag clear.
+static hc_status densest_tile(hc_ctx* c, int32_t* out) {
+  *out = 0;
+  if (!c->have_cells) return HC_OK;
+  const int NT = c->L.ntiles;
+  HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, NT, c->stream), "clear tile lists"));
+  HC_TRY(check(c, launch_bin_vertices(c->C, c->M, c->L, c->B, c->stream), "binning"));
+  std::vector<int> cnt(NT);
+  HC_TRY(copy_d2h(c, cnt.data(), c->B.touch_cnt, (size_t)NT * 4));
+  HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, NT, c->stream), "clear tile lists"));
+  HC_TRY(check(c, launch_fill_i32(c->B.flags, 0, 4, c->stream), "clear flags"));
+  HC_TRY(sync(c, "densest tile"));
+  for (int t = 0; t < NT; ++t) *out = std::max(*out, cnt[t]);
+  return HC_OK;
+}
+
 // Shared by the two ways of setting cells: stiffnesses, traction and the
 // reset of everything that belonged to the previous cells.
 static hc_status cells_changed(hc_ctx* c, int32_t n, const float* k, const float* traction) {
@@ -660,7 +699,21 @@ static hc_status cells_changed(hc_ctx* c, int32_t n, const float* k, const float
   if (c->per_cell_ratio) interior_uniform(c);   // per-cell ratios belong to the old cells
   HC_TRY(check(c, launch_fill_i32(c->B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));
   c->step = 0;
-  return sync(c, "set_cells");
+  HC_TRY(sync(c, "set_cells"));
+  // a tile list that would overflow at the first step is refused here, with
+  // the capacity it needs (lists only fill past their capacity when cells
+  // crowd; later overflows are reported by hc_sync)
+  int32_t dense = 0;
+  HC_TRY(densest_tile(c, &dense));
+  if (dense > c->list_cap) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "the fullest tile list needs %d entries, capacity %d: create the context with "
+                  "hc_set_list_capacity >= %d before binding its workspace",
+                  dense, c->list_cap, dense);
+    return fail(c, HC_ERR_UNSUPPORTED, msg);
+  }
+  return HC_OK;
 }
 
 hc_status hc_set_cells(hc_ctx* c, int32_t n, const int32_t* origin, const float* offsets,

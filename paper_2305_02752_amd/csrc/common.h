@@ -138,6 +138,7 @@ struct Bins {
   int* touch_cnt;           // [ntiles] entries in each tile list
   int* touch;               // [ntiles][cap] vertex * 32 + j (its j-th reached tile)
   int cap;                  // fixed capacity of one tile list
+  int bexp;                 // force-bound grid 2^-bexp of the tile's largest component (cap * 2^bexp <= 2^30)
   int* flags;               // [4]: 0 non-finite, 1 list overflow
   int* scan_tmp;            // block sums of the tile scan
 };

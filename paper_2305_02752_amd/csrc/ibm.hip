@@ -333,7 +333,7 @@ __host__ __device__ inline int tile_grid(const Lattice& L) { return ((L.ntiles +
 // truncated) at a power-of-two scale chosen per tile from a bound
 // on every node sum: the sum over the tile's entries of their largest force
 // component times the largest weight one entry puts on one node.  The bound
-// is summed in integers (each term rounded up on a 2^-19 grid of the tile's
+// is summed in integers (each term rounded up on a 2^-bexp grid of the tile's
 // largest component), so it does not depend on the order of the entries;
 // integer node sums do not either, so the result is bitwise reproducible
 // although the order of the records is not.
@@ -349,7 +349,7 @@ struct Smem {
   float2 fyz[kStage];       // force y, z
   int cnt[kKeys];           // records per box shape, then the first record of each shape
   unsigned fmax;            // largest force component magnitude (float bits)
-  int fsum;                 // sum of the entries' largest components, in units of fmax 2^-19
+  int fsum;                 // sum of the entries' largest components, in units of fmax 2^-bexp
 };
 
 // In-tile stencil list along one axis: of the K positions base + k (wrapped
@@ -428,20 +428,21 @@ __device__ __forceinline__ void decode(unsigned word, float f, Axis& A) {
 // distinct nodes).
 __device__ __forceinline__ float max_node_weight(const Lattice& L) { return L.kernel == 4 ? 0.125f : 1.f; }
 
-// Units of fmax 2^-19 that bound an entry's largest force component fm
+// Units of fmax 2^-bexp that bound an entry's largest force component fm
 // from above (fm <= fmax, rfmax a reciprocal of fmax within a few ulp: the
 // product is within 0.2 units, so truncating and adding one unit bounds it);
-// a tile list's 2048 entries sum to below 2^31.
-__device__ __forceinline__ int bound_units(float fm, float fmax, float rfmax) {
-  return fmax > 0.f ? (int)(fm * rfmax * 524288.f) + 1 : 1;
+// the grid is set by the list capacity (cap 2^bexp <= 2^30), so a full
+// tile list's units sum to below 2^31.
+__device__ __forceinline__ int bound_units(float fm, float fmax, float rfmax, int bexp) {
+  return fmax > 0.f ? (int)(fm * rfmax * ldexpf(1.f, bexp)) + 1 : 1;
 }
 
 // Exponent k of the fixed-point scale 2^k: with the entries' largest force
-// components summing to at most fsum units of fmax 2^-19, every node sum
+// components summing to at most fsum units of fmax 2^-bexp, every node sum
 // stays below 2^30 (half the int32 range, which also covers the rounding of
 // the weights and of the contributions).
-__device__ __forceinline__ int fix_exponent(int fsum, float fmax, float wmax) {
-  const float x = (float)fsum * ldexpf(fmax, -19) * wmax;
+__device__ __forceinline__ int fix_exponent(int fsum, float fmax, float wmax, int bexp) {
+  const float x = (float)fsum * ldexpf(fmax, -bexp) * wmax;
   if (!(x > 0.f)) return 30;     // no force (or NaN): any scale
   if (!(x < 3.0e38f)) return 0;  // infinite force: the move's non-finite check reports it
   int e;
@@ -494,7 +495,7 @@ __device__ __forceinline__ void force_bound(const Cells& C, const Bins& B, int t
   __syncthreads();
   const float fmx = __uint_as_float(S.fmax), rf = __builtin_amdgcn_rcpf(fmx);
   int u = 0;
-  for (int i = threadIdx.x; i < ne; i += blockDim.x) u += bound_units(entry_fmax(C, B, t, i), fmx, rf);
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) u += bound_units(entry_fmax(C, B, t, i), fmx, rf, B.bexp);
   u = wave_sum(u);
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&S.fsum, u);
   __syncthreads();
@@ -557,7 +558,7 @@ __device__ __forceinline__ void stage(const Cells& C, const Mesh& M, const Latti
     int u = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
-      if (key[h] >= 0) u += bound_units(fm[h], fmx, rf);
+      if (key[h] >= 0) u += bound_units(fm[h], fmx, rf, B.bexp);
     u = wave_sum(u);
     if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&S.fsum, u);
   }
@@ -583,8 +584,14 @@ __device__ __forceinline__ void stage(const Cells& C, const Mesh& M, const Latti
   __syncthreads();
 }
 
-// Spread the m staged records into S.acc at the scale 2^kexp.
-template <int K>
+// Spread the m staged records into S.acc at the scale 2^kexp.  Node
+// contributions are truncated (RN false) or rounded to nearest (RN true).
+// A node sum's error is then at most one unit per contribution, or about
+// the square root of the contributions times half a unit; the unit grows
+// with the tile's force bound, i.e. with its entries, so crowded tiles
+// (more than kRoundAbove entries) round.
+constexpr int kRoundAbove = 1024;
+template <int K, bool RN>
 __device__ __forceinline__ void spread(int m, float scale, Smem& S) {
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const int4 g = S.geo[i];
@@ -614,9 +621,15 @@ __device__ __forceinline__ void spread(int m, float scale, Smem& S) {
         for (int ix = 0; ix < K; ++ix) {
           if (ix >= X.n) continue;
           const int li = row + X.l[ix];
-          atomicAdd(&S.acc[0][li], (int)(wzy * gx[ix]));
-          atomicAdd(&S.acc[1][li], (int)(wzy * gy[ix]));
-          atomicAdd(&S.acc[2][li], (int)(wzy * gz[ix]));
+          if (RN) {
+            atomicAdd(&S.acc[0][li], __float2int_rn(wzy * gx[ix]));
+            atomicAdd(&S.acc[1][li], __float2int_rn(wzy * gy[ix]));
+            atomicAdd(&S.acc[2][li], __float2int_rn(wzy * gz[ix]));
+          } else {
+            atomicAdd(&S.acc[0][li], (int)(wzy * gx[ix]));
+            atomicAdd(&S.acc[1][li], (int)(wzy * gy[ix]));
+            atomicAdd(&S.acc[2][li], (int)(wzy * gz[ix]));
+          }
         }
       }
     }
@@ -722,8 +735,9 @@ __device__ __forceinline__ void tile_step_sorted_body(CT C, MT M, LT L, BT B,
     for (int e0 = 0; e0 < ne; e0 += srt::kStage) {
       const int m = min(srt::kStage, ne - e0);
       srt::stage<K>(C, M, L, B, t, x0, y0, z0, e0, m, true, one, S);
-      if (e0 == 0) kexp = srt::fix_exponent(S.fsum, __uint_as_float(S.fmax), srt::max_node_weight(L));
-      srt::spread<K>(m, ldexpf(1.f, kexp), S);
+      if (e0 == 0) kexp = srt::fix_exponent(S.fsum, __uint_as_float(S.fmax), srt::max_node_weight(L), B.bexp);
+      if (ne > srt::kRoundAbove) srt::spread<K, true>(m, ldexpf(1.f, kexp), S);
+      else srt::spread<K, false>(m, ldexpf(1.f, kexp), S);
       __syncthreads();
     }
   }
@@ -833,7 +847,8 @@ __device__ __forceinline__ void tile_step_sorted_body(CT C, MT M, LT L, BT B,
 }
 
 template <int K, bool W>
-__global__ __launch_bounds__(256) void k_tile_step_sorted(Cells C, Mesh M, Lattice L, Bins B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_tile_step_sorted(
+    Cells C, Mesh M, Lattice L, Bins B,
                                                           const float* __restrict__ gin,
                                                           float* __restrict__ gout,
                                                           float* __restrict__ F,

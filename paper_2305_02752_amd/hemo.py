@@ -87,6 +87,8 @@ def _declare(lib):
         "hc_pack_run": [_P, _P, _P, _P, i32, i32, _P, sz, _P, _P],
         "hc_pack_run_static": [_P, _P, _P, _P, i32, i32, _P, _P],
         "hc_place_cells": [_P, i32, _P, _P, _P, _P],
+        "hc_set_list_capacity": [_P, i32],
+        "hc_densest_tile": [_P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -136,7 +138,10 @@ class Simulation:
     wall_u_hi, ibm_kernel.  rest_pos float32 [V,3], tri int32 [T,3].
     """
 
-    def __init__(self, lattice, rest_pos, tri, max_cells: int, device: str = "cuda:0"):
+    def __init__(self, lattice, rest_pos, tri, max_cells: int, device: str = "cuda:0",
+                 list_capacity: int | None = None):
+        """list_capacity: entries per tile list (hc_set_list_capacity), None
+        for the library's default."""
         import torch
 
         self.lib = load_library()
@@ -156,6 +161,8 @@ class Simulation:
             raise HemoError(rc, self.lib.hc_last_error(None).decode())
         self.ctx = ctx
         self.n_cells = 0
+        if list_capacity is not None:
+            self._check(self.lib.hc_set_list_capacity(self.ctx, int(list_capacity)))
         nbytes = C.c_size_t()
         self._check(self.lib.hc_query_workspace(self.ctx, C.byref(nbytes)))
         self.workspace_bytes = nbytes.value
@@ -292,6 +299,12 @@ class Simulation:
         origin = np.ascontiguousarray(origin, dtype=np.int32)
         offsets = np.ascontiguousarray(offsets, dtype=np.float32)
         self._check(self.lib.hc_write_vertices(self.ctx, _ptr(origin), _ptr(offsets), self.n_cells))
+
+    def densest_tile(self):
+        """(entries of the fullest tile list for the current positions, capacity)."""
+        e, cap = C.c_int32(), C.c_int32()
+        self._check(self.lib.hc_densest_tile(self.ctx, C.byref(e), C.byref(cap)))
+        return e.value, cap.value
 
     def compute_forces(self):
         a = np.empty(self.n_cells, dtype=np.float64)

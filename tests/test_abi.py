@@ -154,3 +154,28 @@ def test_batch_settings_need_a_workspace(lib, rbc):
     n = C.c_size_t()
     assert lib.hc_batch_query_workspace(b, C.byref(n)) == OK and n.value > 19 * (16 ** 3 + 20 * 16 * 12) * 12
     lib.hc_batch_destroy(b)
+
+
+def test_list_capacity_sets_the_workspace(lib):
+    """hc_set_list_capacity before binding grows the workspace by the tile
+    lists (4 bytes per entry per tile) and refuses values out of range."""
+    from paper_2305_02752_amd import hemo
+    from workloads import rbc_mesh
+    from workloads.configs import Lattice
+    rest, tri = rbc_mesh()
+    rest = np.ascontiguousarray(rest, dtype=np.float32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    desc = hemo.lattice_desc(Lattice(32, 24, 16))
+    mesh = hemo.MeshDesc(rest.shape[0], tri.shape[0], tri.ctypes.data_as(C.POINTER(C.c_int32)),
+                         rest.ctypes.data_as(C.POINTER(C.c_float)))
+    ctx = C.c_void_p()
+    assert lib.hc_create(C.byref(desc), C.byref(mesh), 64, C.byref(ctx)) == OK
+    n0, n1 = C.c_size_t(), C.c_size_t()
+    assert lib.hc_query_workspace(ctx, C.byref(n0)) == OK
+    assert lib.hc_set_list_capacity(ctx, 4096) == OK
+    assert lib.hc_query_workspace(ctx, C.byref(n1)) == OK
+    ntiles = 4 * 3 * 2
+    assert n1.value - n0.value >= (4096 - 2048) * 4 * ntiles
+    assert lib.hc_set_list_capacity(ctx, 32) == ARG
+    assert lib.hc_set_list_capacity(ctx, 1 << 15) == ARG
+    lib.hc_destroy(ctx)

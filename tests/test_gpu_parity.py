@@ -373,3 +373,55 @@ def test_membrane_forces_independent_of_workgroup_size():
     for fv, fv2, a, v in out:
         assert np.array_equal(fv, out[0][0]) and np.array_equal(fv2, out[0][0])
         assert a == out[0][2] and v == out[0][3]
+
+
+def test_crowded_tiles_need_a_larger_list_capacity():
+    """30 overlapping cells in a 24^3 box: the fullest tile list exceeds the
+    default capacity, so hc_set_cells refuses them and names the capacity it
+    needs; with that capacity (lists past 512 entries, staged in chunks, and
+    the force bound on the capacity's coarser grid) one step matches the
+    oracle field by field."""
+    from types import SimpleNamespace
+
+    from paper_2305_02752_amd import Simulation
+    from paper_2305_02752_amd.hemo import HemoError
+    from workloads import rbc_mesh
+    from workloads.configs import random_rotation
+    rng = np.random.default_rng(29)
+    rest64, tri = rbc_mesh()
+    lat = Lattice(24, 24, 24, bc=(0, 0, 1), tau=0.9, wall_u_lo=(-0.01, 0, 0), wall_u_hi=(0.01, 0, 0))
+    n = 30
+    cen = 11.5 + rng.uniform(-2.5, 2.5, (n, 3))
+    rots = np.stack([random_rotation(rng) for _ in range(n)])
+    k = K_REF[None] * 10.0 ** rng.uniform(-0.5, 0.5, (n, 4))
+    cells = jitter_cells(rng, place_cells(rest64, cen, rots, k, traction=rng.uniform(-2e-3, 2e-3, (n, 3))), 0.05)
+    rest = rest64.astype(np.float32)
+    sim = Simulation(lat, rest, tri, max_cells=n)
+    with pytest.raises(HemoError) as err:
+        sim.set_cells(cells.origin, cells.offsets, cells.k, cells.traction)
+    need = int(str(err.value).split("needs ")[1].split(" ")[0])
+    print("fullest list", need, flush=True)
+    assert need > 2048
+    sim.close()
+    cap = 1 << int(np.ceil(np.log2(need)))
+    sim = Simulation(lat, rest, tri, max_cells=n, list_capacity=cap)
+    sim.set_cells(cells.origin, cells.offsets, cells.k, cells.traction)
+    assert sim.densest_tile() == (need, cap)
+    rng2 = np.random.default_rng(3)
+    g0 = random_shifted_populations(rng2, lat, 1e-3)
+    sim.write_populations(g0)
+    sim.step(1)
+    sim.sync()
+    rho, u = sim.read_macro()
+    _, _, fv = sim.read_vertices()
+    w = SimpleNamespace(lattice=lat, rest_pos=rest, tri=tri)
+    m = oracle_model(w, cells)
+    f0, X0 = oracle_state(g0, cells)
+    f1, X1, info = step.step(m, f0, X0)
+    errs = {"g": relerr(sim.read_populations(), lattice.shifted(f1)), "u": relerr(u, info["u"]),
+            "F": relerr(sim.read_force_field(), info["F"]), "Fv": relerr(fv, info["Fv"]),
+            "U": relerr(sim.read_vertex_velocity(), info["U"])}
+    print({kk: f"{v:.2e}" for kk, v in errs.items()}, flush=True)
+    sim.close()
+    for kk, e in errs.items():
+        assert e <= TOL_STEP, (kk, e)
