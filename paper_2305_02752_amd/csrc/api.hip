@@ -98,7 +98,7 @@ struct hc_ctx {
   double* dom_in_part = nullptr;   // d/d omega_in partial sums (sites inside cells)
   // workspace offsets
   size_t o_pops[2], o_F, o_macro, o_partial, o_origin, o_off, o_lo, o_force, o_vel, o_k, o_trac, o_area, o_vol;
-  size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole;
+  size_t o_tri, o_edge, o_L0, o_hv, o_th0, o_pole, o_own;
   size_t o_owner, o_ntouch, o_scan, o_slot, o_tcnt, o_tptr, o_touch, o_csr, o_flags;
   size_t o_ccnt, o_cptr, o_ctiles, o_crank, o_clist, o_mask, o_cclass, o_rest;
   std::vector<float> rest;   // the rest mesh [nv][3], copied at create
@@ -151,6 +151,7 @@ void plan(hc_ctx* c, Layout& lay) {
   c->o_hv = lay.add(m.hinge_v.size() * 4);
   c->o_th0 = lay.add(m.theta0.size() * 4);
   c->o_pole = lay.add(m.pole.size() * 4);
+  c->o_own = lay.add(m.hinge_own.size() * 4);
   c->o_owner = lay.add(C * nv * 4);
   c->o_ntouch = lay.add(C * nv * 4);
   c->o_scan = lay.add(((NT + 4095) / 4096 + 1) * 4);
@@ -611,6 +612,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   M.hinge_v = at<int>(c, c->o_hv);
   M.theta0 = at<float>(c, c->o_th0);
   M.pole = at<float>(c, c->o_pole);
+  M.hinge_own = at<int>(c, c->o_own);
   M.inv_npole = 1.0f / kNPole;
   M.A0 = m.A0;
   M.V0 = m.V0;
@@ -652,6 +654,7 @@ hc_status hc_bind_workspace(hc_ctx* c, void* dev, size_t bytes) {
   HC_TRY(copy_h2d(c, (void*)M.hinge_v, m.hinge_v.data(), m.hinge_v.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.theta0, m.theta0.data(), m.theta0.size() * 4));
   HC_TRY(copy_h2d(c, (void*)M.pole, m.pole.data(), m.pole.size() * 4));
+  HC_TRY(copy_h2d(c, (void*)M.hinge_own, m.hinge_own.data(), m.hinge_own.size() * 4));
   HC_TRY(copy_h2d(c, at<float>(c, c->o_rest), c->rest.data(), c->rest.size() * 4));
   HC_TRY(check(c, launch_fill_i32(B.flags, 0, 4, c->stream), "clear flags"));
   HC_TRY(check(c, launch_fill_i32(B.touch_cnt, 0, c->L.ntiles, c->stream), "clear tile lists"));

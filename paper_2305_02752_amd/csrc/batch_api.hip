@@ -52,7 +52,7 @@ struct hc_batch {
   char* ws = nullptr;
   bool have_cells = false;
   std::string err;
-  size_t o_pop0, o_pop1, o_snap_pop, o_box, o_tri, o_edge, o_L0, o_hv, o_th0, o_pole, o_origin,
+  size_t o_pop0, o_pop1, o_snap_pop, o_box, o_tri, o_edge, o_L0, o_hv, o_th0, o_pole, o_own, o_origin,
       o_off, o_lo, o_force, o_vel, o_snap_off, o_snap_lo, o_k, o_trac, o_area, o_vol, o_uacc, o_bbox, o_wg, o_bar,
       o_step, o_snap_step, o_flags, o_mask;
 };
@@ -92,6 +92,7 @@ void plan(hc_batch* b, Lay& L) {
   b->o_hv = L.add(m.hinge_v.size() * 4);
   b->o_th0 = L.add(m.theta0.size() * 4);
   b->o_pole = L.add(m.pole.size() * 4);
+  b->o_own = L.add(m.hinge_own.size() * 4);
   b->o_origin = L.add(B * 12);
   b->o_off = L.add(B * nv * 12);
   b->o_lo = L.add(B * nv * 12);
@@ -364,6 +365,7 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   V.M.hinge_v = bat<int>(b, b->o_hv);
   V.M.theta0 = bat<float>(b, b->o_th0);
   V.M.pole = bat<float>(b, b->o_pole);
+  V.M.hinge_own = bat<int>(b, b->o_own);
   V.M.inv_npole = 1.0f / kNPole;
   V.M.A0 = m.A0;
   V.M.V0 = m.V0;
@@ -392,6 +394,7 @@ hc_status hc_batch_bind_workspace(hc_batch* b, void* dev, size_t bytes) {
   HB_TRY(h2d(b, (void*)V.M.hinge_v, m.hinge_v.data(), m.hinge_v.size() * 4));
   HB_TRY(h2d(b, (void*)V.M.theta0, m.theta0.data(), m.theta0.size() * 4));
   HB_TRY(h2d(b, (void*)V.M.pole, m.pole.data(), m.pole.size() * 4));
+  HB_TRY(h2d(b, (void*)V.M.hinge_own, m.hinge_own.data(), m.hinge_own.size() * 4));
   HB_TRY(bcheck(b, launch_fill_i32(V.box_step, 0, b->nbox, b->stream), "clear"));
   HB_TRY(bcheck(b, launch_fill_i32(V.flags, 0, 4, b->stream), "clear"));
   HB_TRY(bcheck(b, launch_fill_i32(reinterpret_cast<int*>(V.mask), 0, (b->sites + 3) / 4, b->stream),

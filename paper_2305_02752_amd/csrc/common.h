@@ -113,6 +113,7 @@ struct Mesh {
   const float* L0;          // [ne] rest length
   const int* hinge_v;       // [nh][4] (i, j, k, l): i->j in (i, j, k), j->i in (j, i, l)
   const float* theta0;      // [nh]
+  const int* hinge_own;     // [nh] bit 0: evaluates triangle (i, j, k), bit 1: (j, i, l)
   const float* pole;        // [nv] +1 / -1 / 0: pole traction sign
   float inv_npole;          // 1 / |P+|
   double A0, V0;

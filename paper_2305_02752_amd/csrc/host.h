@@ -13,7 +13,7 @@ constexpr int kNPole = 32;   // vertices per traction pole
 
 struct HostMesh {
   int nv = 0, nt = 0, ne = 0, nh = 0;
-  std::vector<int> tri, edge, hinge_v;
+  std::vector<int> tri, edge, hinge_v, hinge_own;
   std::vector<float> L0, theta0, pole;
   double A0 = 0, V0 = 0;
 };

@@ -100,87 +100,100 @@ __device__ inline void add_force(long long* acc, int v, f3 f) {
            f.z * kFixScaleF);
 }
 
-// Cell area and volume (float64 sums over triangles, fixed-order reduction
-// over the nthr cooperating threads; red holds 2 * nthr / 64 doubles).
-// Area and volume of the cell in FP64, by the 64 lanes of one wave: lane i
-// sums triangles i, i + 64, ... in order and the 64 partial sums are
-// combined by a fixed butterfly, so the result does not depend on how many
-// threads share the cell (the per-cell kernel widens its work-group when
-// the cells are few).  Every lane ends with the totals.
-__device__ inline void area_volume_wave(const Mesh& M, const float* sp, int lane, double& A, double& V) {
-  A = 0.0;
-  V = 0.0;
-  for (int t = lane; t < M.nt; t += kWave) {
-    const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
-    const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
-    const double cx = xc.x, cy = xc.y, cz = xc.z;
-    const double ux = bx - ax, uy = by - ay, uz = bz - az, vx = cx - ax, vy = cy - ay, vz = cz - az;
-    const double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
-    A += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
-    V += (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx)) / 6.0;
-  }
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    A += __shfl_xor(A, m);
-    V += __shfl_xor(V, m);
-  }
+// Area and volume terms of triangle t (FP64): the triangle's area and its
+// signed volume with the origin.
+__device__ inline void tri_area_volume(const Mesh& M, const float* sp, int t, double& a, double& v) {
+  const f3 xa = ld3(sp, M.tri[3 * t]), xb = ld3(sp, M.tri[3 * t + 1]), xc = ld3(sp, M.tri[3 * t + 2]);
+  const double ax = xa.x, ay = xa.y, az = xa.z, bx = xb.x, by = xb.y, bz = xb.z;
+  const double cx = xc.x, cy = xc.y, cz = xc.z;
+  const double ux = bx - ax, uy = by - ay, uz = bz - az, vx = cx - ax, vy = cy - ay, vz = cz - az;
+  const double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+  a = 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+  v = (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx)) / 6.0;
 }
 
 // Forces on one cell with `nthr` cooperating threads (thread `tid`).
-// acc: LDS [nv][3] int64, sp: LDS [nv][3] float, red: LDS [2 * nthr / 64]
-// double.  Writes area/volume (float64) and the per-vertex forces.  With
-// off == nullptr the caller has already staged the offsets in sp.
+// acc: LDS [nv][3] int64, sp: LDS [nv][3] float (red: unused).  Writes
+// area/volume (float64) and the per-vertex forces.  With off == nullptr the
+// caller has already staged the offsets in sp.
 __device__ inline void membrane_cell(const Mesh& M, const float* __restrict__ off,
                                      const float* __restrict__ k4, const float* trac,
                                      float* __restrict__ out, double* area, double* volume,
                                      long long* acc, float* sp, double* red, int tid, int nthr) {
-  for (int i = tid; i < 3 * M.nv; i += nthr) {
-    if (off) sp[i] = off[i];
-    acc[i] = 0;
-  }
+  (void)red;
+  if (off)
+    for (int i = tid; i < 3 * M.nv; i += nthr) sp[i] = off[i];
   __syncthreads();
-  // wave 0: area and volume; meanwhile the other waves take the links and
-  // hinges, which do not need them (fixed-point sums: any order).  A single
-  // wave does both in turn.
-  const float kl = k4[0], kb = k4[1], ka = k4[2], kv = k4[3];
-  if (tid < kWave) {
-    double A, V;
-    area_volume_wave(M, sp, tid, A, V);
-    if (tid == 0) {
-      red[0] = A;
-      red[1] = V;
-      *area = A;
-      *volume = V;
+  // 1. Area and volume (FP64) over chunks of 64 triangles: lane i of a wave
+  //    takes triangle 64 c + i of chunk c, the chunk is reduced by a fixed
+  //    butterfly, and the chunk sums are added in chunk order, so the result
+  //    does not depend on how many threads share the cell (the per-cell
+  //    kernel widens its work-group when the cells are few).  The chunk sums
+  //    are parked in the accumulator, free until the forces accumulate.
+  double* cs = reinterpret_cast<double*>(acc);
+  const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr > kWave ? nthr / kWave : 1;
+  const int nchunk = (M.nt + kWave - 1) / kWave;
+  for (int ch = wv; ch < nchunk; ch += nw) {
+    double a = 0.0, v = 0.0;
+    if (ch * kWave + lane < M.nt) tri_area_volume(M, sp, ch * kWave + lane, a, v);
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+      a += __shfl_xor(a, m);
+      v += __shfl_xor(v, m);
+    }
+    if (lane == 0) {
+      cs[2 * ch] = a;
+      cs[2 * ch + 1] = v;
     }
   }
-  const int e0 = nthr > kWave ? tid - kWave : tid, es = nthr > kWave ? nthr - kWave : nthr;
-  for (int e = e0; e >= 0 && e < M.ne; e += es) {
-    const int i = M.edge[2 * e], j = M.edge[2 * e + 1];
-    const f3 f = link_force<float>(ld3(sp, i), ld3(sp, j), M.L0[e], kl);
-    add_force(acc, i, f);
-    add_force(acc, j, -1.f * f);
+  __syncthreads();
+  double A = 0.0, V = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    A += cs[2 * ch];
+    V += cs[2 * ch + 1];
   }
-  for (int h = e0; h >= 0 && h < M.nh; h += es) {
-    const int i = M.hinge_v[4 * h], j = M.hinge_v[4 * h + 1];
-    const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
-    f3 fi, fj, fk, fl;
-    hinge_forces<float>(ld3(sp, i), ld3(sp, j), ld3(sp, k), ld3(sp, l), M.theta0[h], kb, fi, fj, fk,
-                        fl);
-    add_force(acc, k, fk);
-    add_force(acc, l, fl);
-    add_force(acc, i, fi);
-    add_force(acc, j, fj);
+  if (tid == 0) {
+    *area = A;
+    *volume = V;
   }
-  __syncthreads();   // area and volume in red
-  const double A = red[0], V = red[1];
+  __syncthreads();   // every thread has read the chunk sums
+  for (int i = tid; i < 3 * M.nv; i += nthr) acc[i] = 0;
+  __syncthreads();
+  const float kl = k4[0], kb = k4[1], ka = k4[2], kv = k4[3];
   const float ca = -ka * (float)((A - M.A0) / M.A0);        // F_area = ca * dA/dx
   const float cv = -kv * (float)((V - M.V0) / M.V0) / 6.f;  // F_vol  = cv * 6 dV/dx
-  for (int t = tid; t < M.nt; t += nthr) {
-    const int ia = M.tri[3 * t], ib = M.tri[3 * t + 1], ic = M.tri[3 * t + 2];
-    f3 fa, fb, fc;
-    tri_forces<float>(ld3(sp, ia), ld3(sp, ib), ld3(sp, ic), ca, cv, fa, fb, fc);
-    add_force(acc, ia, fa);
-    add_force(acc, ib, fb);
-    add_force(acc, ic, fc);
+  // 2. One pass over the hinges (one per edge, same index): the edge's link
+  //    force, the bending forces of its two triangles, and the area/volume
+  //    forces of the triangle(s) it evaluates (each triangle with exactly
+  //    one hinge); the four vertices' sums go to the fixed-point
+  //    accumulator once each.
+  for (int h = tid; h < M.nh; h += nthr) {
+    const int p = M.hinge_v[4 * h], q = M.hinge_v[4 * h + 1];
+    const int k = M.hinge_v[4 * h + 2], l = M.hinge_v[4 * h + 3];
+    const f3 xp = ld3(sp, p), xq = ld3(sp, q), xk = ld3(sp, k), xl = ld3(sp, l);
+    const f3 fe = link_force<float>(xp, xq, M.L0[h], kl);
+    f3 Fp, Fq, Fk, Fl;
+    hinge_forces<float>(xp, xq, xk, xl, M.theta0[h], kb, Fp, Fq, Fk, Fl);
+    Fp = Fp + fe;
+    Fq = Fq + -1.f * fe;
+    const int own = M.hinge_own[h];
+    if (own & 1) {
+      f3 fa, fb, fc;
+      tri_forces<float>(xp, xq, xk, ca, cv, fa, fb, fc);
+      Fp = Fp + fa;
+      Fq = Fq + fb;
+      Fk = Fk + fc;
+    }
+    if (own & 2) {
+      f3 fa, fb, fc;
+      tri_forces<float>(xq, xp, xl, ca, cv, fa, fb, fc);
+      Fq = Fq + fa;
+      Fp = Fp + fb;
+      Fl = Fl + fc;
+    }
+    add_force(acc, k, Fk);
+    add_force(acc, l, Fl);
+    add_force(acc, p, Fp);
+    add_force(acc, q, Fq);
   }
   __syncthreads();
 

@@ -73,6 +73,18 @@ std::string build_mesh(const hc_mesh_desc* d, HostMesh& m) {
     if (degree[v] == 0) return "mesh: isolated vertex";
   m.ne = (int)m.L0.size();
   m.nh = m.ne;
+  // each triangle is evaluated with one hinge of its first stored edge (a, b):
+  // bit 0 when it is that hinge's (i, j, k) (a < b), bit 1 its (j, i, l)
+  {
+    std::map<std::pair<int, int>, int> hidx;
+    for (int h = 0; h < m.nh; ++h) hidx[std::make_pair(m.hinge_v[4 * h], m.hinge_v[4 * h + 1])] = h;
+    m.hinge_own.assign(m.nh, 0);
+    for (int t = 0; t < nt; ++t) {
+      const int a = m.tri[3 * t], b = m.tri[3 * t + 1];
+      const int h = hidx.at(std::make_pair(std::min(a, b), std::max(a, b)));
+      m.hinge_own[h] |= a < b ? 1 : 2;
+    }
+  }
   // rest area and volume (float64, divergence theorem)
   double A = 0, V = 0;
   for (int t = 0; t < nt; ++t) {
