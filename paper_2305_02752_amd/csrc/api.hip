@@ -273,7 +273,7 @@ hc_status one_step(hc_ctx* c) {
   const bool refresh = c->step % c->force_every == 0;
   HC_TRY(timed(c, HC_K_CELL, "cell step", [&] {
     return launch_cell_step(C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, refresh, ab2,
-                            c->recentre, c->stream);
+                            c->recentre, c->scheme == HC_AB2, c->stream);
   }));
   if (adv) c->have_prev = true;
   unsigned char* mask = nullptr;
@@ -362,7 +362,7 @@ hc_status adj_forward_into(hc_ctx* c, int i) {
   float4* Mi = c->sg_macro + i * N;
   const float* prev = i > 0 ? c->sg_off + (i - 1) * X : nullptr;
   HC_TRY(check(c, launch_cell_step(Ci, c->M, c->L, c->B, c->partial, c->B.flags, i > 0, prev, true,
-                                   false, false, c->stream),
+                                   false, false, false, c->stream),
                "cell step"));
   unsigned char* mask = nullptr;
   if (interior_on(c)) {   // the forward step's marks, from slot i's positions

@@ -87,7 +87,7 @@ template <int K, int kCellThreads, bool LE>
 __device__ __forceinline__ void cell_step_body(Cells C, Mesh M, Lattice L, Bins B,
                                                const float4* __restrict__ partial, int* __restrict__ flags,
                                                int advect, const float* __restrict__ src, int refresh, int ab2,
-                                               int recentre) {
+                                               int recentre, int keep_vel) {
   extern __shared__ long long lds64[];
   __shared__ double red[2 * kCellThreads / kWave];
   __shared__ float ext[6][kCellThreads / kWave];
@@ -103,7 +103,8 @@ __device__ __forceinline__ void cell_step_body(Cells C, Mesh M, Lattice L, Bins 
   if (advect) {
     for (int vl = tid; vl < M.nv; vl += kCellThreads) {
       float nx[3];
-      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src, ab2 != 0);
+      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src, ab2 != 0,
+                             keep_vel != 0);
       sp[3 * vl] = nx[0];
       sp[3 * vl + 1] = nx[1];
       sp[3 * vl + 2] = nx[2];
@@ -131,8 +132,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step(Cells C, Mesh M, Lat
                                                            const float4* __restrict__ partial,
                                                            int* __restrict__ flags, int advect,
                                                            const float* __restrict__ src,
-                                                           int refresh, int ab2, int recentre) {
-  cell_step_body<K, kCellThreads, LE>(C, M, L, B, partial, flags, advect, src, refresh, ab2, recentre);
+                                                           int refresh, int ab2, int recentre, int keep_vel) {
+  cell_step_body<K, kCellThreads, LE>(C, M, L, B, partial, flags, advect, src, refresh, ab2, recentre, keep_vel);
 }
 
 // Batched form: box blockIdx.y.
@@ -140,7 +141,7 @@ template <int K, int kCellThreads>
 __global__ __launch_bounds__(kCellThreads) void k_cell_step_multi(const CellStepArgs* __restrict__ many) {
   const CellStepArgs& a = many[blockIdx.y];
   cell_step_body<K, kCellThreads, false>(a.C, a.M, a.L, a.B, a.partial, a.flags, a.advect, a.src, a.refresh,
-                                         a.ab2, a.recentre);
+                                         a.ab2, a.recentre, 0);
 }
 
 }  // namespace
@@ -148,14 +149,15 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_step_multi(const CellStep
 // Tile-list counts must be zero on entry (see launch_bin_vertices).
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, const float* src,
-                            bool refresh, bool ab2, bool recentre, hipStream_t s) {
+                            bool refresh, bool ab2, bool recentre, bool keep_vel, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const int region = std::max(24, bin::slot_lds_per_vertex(L.max_touch)) * m.nv;
   const size_t lds = (size_t)((region + 7) & ~7) + (size_t)m.nv * 3 * sizeof(float);
   const int adv = advect ? 1 : 0, ref = refresh ? 1 : 0, a2 = ab2 ? 1 : 0, rc = recentre ? 1 : 0;
+  const int kv = keep_vel ? 1 : 0;
   auto go = [&](auto kern, int threads) {
     hipLaunchKernelGGL(kern, dim3(c.n), dim3(threads), lds, s, c, m, L, b, partial, flags, adv, src, ref, a2,
-                       rc);
+                       rc, kv);
   };
   // sheared images: one 256-thread form
   if (L.le) {

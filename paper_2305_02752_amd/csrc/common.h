@@ -194,7 +194,7 @@ hipError_t launch_mark_interior(const Cells& c, const Mesh& m, const Lattice& L,
 // the membrane forces, else hold the stored ones; ab2: Adams-Bashforth move)
 hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                             const float4* partial, int* flags, bool advect, const float* src,
-                            bool refresh, bool ab2, bool recentre, hipStream_t s);
+                            bool refresh, bool ab2, bool recentre, bool keep_vel, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Batched forms of the per-step kernels for several boxes of one shape (one

@@ -16,13 +16,15 @@ namespace ibmd {
 // U_prev = the velocity stored by the previous move), reading X from src
 // when given (else in place) and writing C.off; the low parts C.lo are
 // carried in place (move_compensated).  The new offset is also
-// returned in nxyz.  The other two axes' weights sum to one, so a node layer beyond
-// the wall contributes its axis weight times the wall velocity.
+// returned in nxyz, and U is stored in C.vel when keep_vel (for the next
+// Adams-Bashforth move, and for the read-out after the closing move).  The
+// other two axes' weights sum to one, so a node layer beyond the wall
+// contributes its axis weight times the wall velocity.
 template <int K>
 __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                      const float4* __restrict__ partial, int* __restrict__ flags,
                                      int64_t v, float (&nxyz)[3], const float* src = nullptr,
-                                     bool ab2 = false) {
+                                     bool ab2 = false, bool keep_vel = true) {
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
   const int nt = B.ntouch[v];
   for (int j = 0; j < nt; ++j) {
@@ -68,9 +70,11 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
   lo[0] = lx;
   lo[1] = ly;
   lo[2] = lz;
-  vo[0] = Ux;
-  vo[1] = Uy;
-  vo[2] = Uz;
+  if (keep_vel) {   // read by the next Adams-Bashforth move and by the read-out
+    vo[0] = Ux;
+    vo[1] = Uy;
+    vo[2] = Uz;
+  }
   o[0] = nx;
   o[1] = ny;
   o[2] = nz;
