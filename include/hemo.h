@@ -371,10 +371,10 @@ hc_status hc_set_params(hc_ctx* ctx, const float* k, float tau);
  * sites through tau_in = 1/2 + ratio (tau - 1/2)).  Needs the 4-point
  * kernel, Euler moves with forces every step and no Lees-Edwards images
  * (HC_ERR_UNSUPPORTED otherwise).  hc_adj_backward refers to the last
- * hc_adj_forward: hc_set_params, hc_set_cells, hc_place_cells and a change
- * of hc_set_integration in between discard it (HC_ERR_STATE until the next
- * hc_adj_forward), since its reverse sweep recomputes under the parameters
- * and cells it ran with.  The
+ * hc_adj_forward: hc_set_params, hc_set_cells, hc_place_cells,
+ * hc_checkpoint_restore and a change of hc_set_integration in between
+ * discard it (HC_ERR_STATE until the next hc_adj_forward), since its reverse
+ * sweep recomputes under the parameters and cells it ran with.  The
  * adjoint workspace is separate from the main one and sized by
  * hc_adj_query_workspace.
  * ------------------------------------------------------------------------- */

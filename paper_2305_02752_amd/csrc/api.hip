@@ -979,6 +979,7 @@ hc_status hc_checkpoint_restore(hc_ctx* c, const void* host, size_t bytes) {
   p += X;
   HC_TRY(copy_h2d(c, c->C.force, p, X));
   c->step = h64[0];
+  c->adj_ready = false;   // a reverse sweep belongs to the state its forward ran from
   c->have_prev = h32[0] != 0;
   c->force_every = h32[1];
   c->scheme = h32[2];
