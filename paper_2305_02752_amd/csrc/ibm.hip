@@ -486,20 +486,35 @@ __device__ __forceinline__ float entry_fmax(const Cells& C, const Bins& B, int t
 
 // Largest force component over entries [0, ne) of tile t into S.fmax, then
 // the bound sum into S.fsum (both zeroed and synchronised by the caller).
-// Ends synchronised.
+// Each entry's largest component is gathered once and kept in the record
+// space (free until the staging) when the list fits it, else gathered
+// again for the sum.  Ends synchronised.
+constexpr int kBoundKeep = (int)(sizeof(float4) * kStage / sizeof(float));
 __device__ __forceinline__ void force_bound(const Cells& C, const Bins& B, int t, int ne, Smem& S) {
+  float* kept = reinterpret_cast<float*>(S.fr);
+  const bool keep = ne <= kBoundKeep;
   float m = 0.f;
-  for (int i = threadIdx.x; i < ne; i += blockDim.x) m = fmaxf(m, entry_fmax(C, B, t, i));
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+    const float f = entry_fmax(C, B, t, i);
+    if (keep) kept[i] = f;
+    m = fmaxf(m, f);
+  }
   m = wave_max(m);
   if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&S.fmax, __float_as_uint(m));
   __syncthreads();
   const float fmx = __uint_as_float(S.fmax), rf = __builtin_amdgcn_rcpf(fmx);
   int u = 0;
-  for (int i = threadIdx.x; i < ne; i += blockDim.x) u += bound_units(entry_fmax(C, B, t, i), fmx, rf, B.bexp);
+  for (int i = threadIdx.x; i < ne; i += blockDim.x)
+    u += bound_units(keep ? kept[i] : entry_fmax(C, B, t, i), fmx, rf, B.bexp);
   u = wave_sum(u);
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&S.fsum, u);
   __syncthreads();
 }
+
+// Chunks of a list longer than kStage: a first one of 1..kStage entries,
+// then full ones, so that the last chunk staged for the spread is a full
+// one, and it is still staged when the interpolation starts.
+__device__ __forceinline__ int first_chunk(int ne) { return ne - (ne - 1) / kStage * kStage; }
 
 // Stage entries [e0, e0 + m) of tile t (m <= kStage, two per thread) as
 // records ordered by box shape; with_force also stages the forces, and with
@@ -700,7 +715,7 @@ __device__ __forceinline__ void interp(int m, const Smem& S, int64_t stride, flo
 //  3. interpolate u to the staged entries into their partial-sum slots.
 // Tiles with more entries than the LDS stages at once take them in chunks
 // (the scale then comes from a first pass over all their forces, and the
-// interpolation stages the chunks again).
+// interpolation stages again every chunk but the last).
 // The struct arguments come by value from the single-box kernel (its own
 // parameters) and by reference to global memory from the batched one: a
 // reference to a kernel's by-value parameter, or a by-value copy of a record
@@ -732,8 +747,7 @@ __device__ __forceinline__ void tile_step_sorted_body(CT C, MT M, LT L, BT B,
   if (ne > 0) {
     const bool one = ne <= srt::kStage;
     if (!one) srt::force_bound(C, B, t, ne, S);   // the scale must cover every chunk
-    for (int e0 = 0; e0 < ne; e0 += srt::kStage) {
-      const int m = min(srt::kStage, ne - e0);
+    for (int e0 = 0, m = srt::first_chunk(ne); e0 < ne; e0 += m, m = srt::kStage) {
       srt::stage<K>(C, M, L, B, t, x0, y0, z0, e0, m, true, one, S);
       if (e0 == 0) kexp = srt::fix_exponent(S.fsum, __uint_as_float(S.fmax), srt::max_node_weight(L), B.bexp);
       if (ne > srt::kRoundAbove) srt::spread<K, true>(m, ldexpf(1.f, kexp), S);
@@ -835,8 +849,10 @@ __device__ __forceinline__ void tile_step_sorted_body(CT C, MT M, LT L, BT B,
   if (ne <= srt::kStage) {
     srt::interp<K>(ne, S, stride, partial);
   } else {
-    for (int e0 = 0; e0 < ne; e0 += srt::kStage) {
-      const int m = min(srt::kStage, ne - e0);
+    // the last chunk of the spread is still staged; the others stage again
+    srt::interp<K>(srt::kStage, S, stride, partial);
+    __syncthreads();
+    for (int e0 = 0, m = srt::first_chunk(ne); e0 < ne - srt::kStage; e0 += m, m = srt::kStage) {
       srt::stage<K>(C, M, L, B, t, x0, y0, z0, e0, m, false, false, S);
       srt::interp<K>(m, S, stride, partial);
       __syncthreads();
