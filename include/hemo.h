@@ -122,7 +122,10 @@ hc_status hc_set_stream(hc_ctx* ctx, void* hip_stream);
  * the lists live in the workspace.  hc_set_cells refuses cells whose
  * fullest list would exceed the capacity (HC_ERR_UNSUPPORTED, with the
  * capacity needed); a list that overflows later, as cells crowd, loses
- * entries of that step and is reported by hc_sync. */
+ * entries of that step and is reported by hc_sync (HC_ERR_UNSUPPORTED).
+ * A checkpoint holds no list state, so such a run continues from its last
+ * checkpoint (hc_checkpoint_restore) in a context created with a larger
+ * capacity and the same cells (hc_set_cells). */
 hc_status hc_set_list_capacity(hc_ctx* ctx, int32_t entries);
 /* Entries the fullest tile list holds for the current positions (after
  * applying a pending move), and the capacity (may be NULL). */

@@ -425,3 +425,67 @@ def test_crowded_tiles_need_a_larger_list_capacity():
     sim.close()
     for kk, e in errs.items():
         assert e <= TOL_STEP, (kk, e)
+
+
+
+def test_list_overflow_recovers_from_a_checkpoint():
+    """A tile list that overflows during a run (the cells, set spread out in
+    a 48^3 box with the fullest list at 1,173 entries, are written into one
+    crowded spot whose fullest list holds 8,179) is reported by hc_sync;
+    the run then continues from its last checkpoint in a context with a
+    larger list capacity and stays within the one-step tolerance of a run
+    that had that capacity from the start (the capacity sets the force
+    bound's grid, so the two differ only in fixed-point rounding)."""
+    from paper_2305_02752_amd import Simulation
+    from paper_2305_02752_amd.hemo import HemoError
+    from workloads import rbc_mesh
+    from workloads.configs import random_rotation
+    rng = np.random.default_rng(31)
+    rest64, tri = rbc_mesh()
+    rest = rest64.astype(np.float32)
+    lat = Lattice(48, 48, 48, tau=0.9, body_force=(1e-5, 0.0, 0.0))
+    n = 30
+    rots = np.stack([random_rotation(rng) for _ in range(n)])
+    k = K_REF[None] * 10.0 ** rng.uniform(-0.5, 0.5, (n, 4))
+    spread = place_cells(rest64, rng.uniform(6, 42, (n, 3)), rots, k)
+    crowded = place_cells(rest64, 19.5 + rng.uniform(-2.5, 2.5, (n, 3)), rots, k)
+    g0 = random_shifted_populations(np.random.default_rng(5), lat, 1e-3)
+
+    def start(cap):
+        sim = Simulation(lat, rest, tri, max_cells=n, list_capacity=cap)
+        sim.set_cells(spread.origin, spread.offsets, spread.k, None)
+        return sim
+
+    sim = start(None)   # the default capacity, 2048
+    sim.write_populations(g0)
+    sim.step(2)
+    sim.sync()
+    ck = sim.checkpoint_save()
+    sim.write_vertices(crowded.origin, crowded.offsets)
+    sim.step(1)
+    with pytest.raises(HemoError, match="exceeded its capacity"):
+        sim.sync()
+    sim.close()
+    cap = 1 << 14
+    rec = start(cap)
+    rec.checkpoint_restore(ck)
+    ref = start(cap)
+    ref.write_populations(g0)
+    ref.step(2)
+    ref.sync()
+    for s_ in (rec, ref):
+        s_.write_vertices(crowded.origin, crowded.offsets)
+        s_.step(3)
+        s_.sync()
+    assert rec.densest_tile()[1] == cap
+    o1, x1, _ = rec.read_vertices()
+    o2, x2, _ = ref.read_vertices()
+    errs = {"g": relerr(rec.read_populations(), ref.read_populations()),
+            "X": relerr((o1[:, None, :] + x1.astype(np.float64)) - crowded.positions64(),
+                        (o2[:, None, :] + x2.astype(np.float64)) - crowded.positions64())}
+    print({kk: f"{v:.2e}" for kk, v in errs.items()}, flush=True)
+    rec.close()
+    ref.close()
+    assert np.array_equal(o1, o2)
+    for kk, e in errs.items():
+        assert e <= TOL_STEP, (kk, e)
