@@ -25,6 +25,8 @@
 //     dL/dk_j += sum_v lam_{F_v} . F_v^(j) / k_j per force term.
 // The IBM kernel must be the 4-point phi4 (C^1); the linear hat has no
 // derivative at the nodes.
+#include <algorithm>
+
 #include "common.h"
 #include "lbm_dev.h"
 #include "membrane_dev.h"
@@ -42,17 +44,17 @@ using lbm::wq;
 // Lattice weight of direction j, exact in FP64.
 __device__ __forceinline__ double wq64(int j) { return j == 0 ? 1.0 / 3 : (j < 7 ? 1.0 / 18 : 1.0 / 36); }
 
-// The collision VJP in FP64 from FP32 inputs (stored populations, force
-// density, lam_u), with FP64 population cotangents.  The part of lam_f that
-// d/d omega sees is its non-hydrodynamic (second-moment) part, which arises
-// from differences between neighbouring sites' projections; an FP32 lam_f
-// stores those projections to 7 digits and loses most of the differences in
-// smooth regions, and an FP32 f_eq repeats the same rounding across a smooth
-// flow, so both would bias the sum over every site and step.
+// The collision VJP in FP64 from FP32 inputs: the stored populations, force
+// density, lam_u and the population cotangents, which are stored in FP32.
+// Every contraction, f_eq and the d/d omega sum are formed in FP64 (an FP32
+// f_eq would repeat the same rounding across a smooth flow and bias the sum
+// over every site and step).  FP32 storage of the cotangents moves the
+// full-size gradient by about 1% of its difference from the oracle's and
+// takes the kernel from 416 to 264 bytes per site.
 // LT: the lattice record by value (single-box kernel) or by reference to
 // global memory (batched kernel), so that neither puts it in scratch.
 template <class LT>
-__device__ __forceinline__ void adj_collide_body(const double* __restrict__ lam1, double* __restrict__ lam0,
+__device__ __forceinline__ void adj_collide_body(const float* __restrict__ lam1, float* __restrict__ lam0,
                                                  const float* __restrict__ h0, const float* __restrict__ F,
                                                  const float* __restrict__ lamu, float* __restrict__ lamF,
                                                  double* __restrict__ domega_part,
@@ -176,8 +178,8 @@ __device__ __forceinline__ void adj_collide_body(const double* __restrict__ lam1
     Bz += lamu[2 * N + s];
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      lam0[source(i)] = (1.0 - om) * lam1[i * N + s] + A +
-                        (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv;
+      lam0[source(i)] = (float)((1.0 - om) * (double)lam1[i * N + s] + A +
+                                (Bx * (cx[i] - ux) + By * (cy[i] - uy) + Bz * (cz[i] - uz)) * inv);
     lamF[s] = (float)(Gx + 0.5 * Bx * inv);
     lamF[N + s] = (float)(Gy + 0.5 * By * inv);
     lamF[2 * N + s] = (float)(Gz + 0.5 * Bz * inv);
@@ -200,8 +202,8 @@ __device__ __forceinline__ void adj_collide_body(const double* __restrict__ lam1
   }
 }
 
-__global__ __launch_bounds__(256) void k_adj_collide(const double* __restrict__ lam1,
-                                                     double* __restrict__ lam0,
+__global__ __launch_bounds__(256) void k_adj_collide(const float* __restrict__ lam1,
+                                                     float* __restrict__ lam0,
                                                      const float* __restrict__ h0,
                                                      const float* __restrict__ F,
                                                      const float* __restrict__ lamu,
@@ -506,9 +508,26 @@ __global__ void k_fill_f64(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+// Record blockIdx.y of a batch of copies, strided over the x blocks.
+__global__ __launch_bounds__(256) void k_copy_many(const CopyRec* __restrict__ recs) {
+  const CopyRec r = recs[blockIdx.y];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  const bool wide = ((reinterpret_cast<uintptr_t>(r.dst) | reinterpret_cast<uintptr_t>(r.src) | r.bytes) & 15) == 0;
+  if (wide) {
+    using v4u = unsigned __attribute__((ext_vector_type(4)));
+    const v4u* src = static_cast<const v4u*>(r.src);
+    v4u* dst = static_cast<v4u*>(r.dst);
+    for (int64_t i = t0, n = r.bytes >> 4; i < n; i += step) dst[i] = src[i];
+  } else {
+    const unsigned* src = static_cast<const unsigned*>(r.src);
+    unsigned* dst = static_cast<unsigned*>(r.dst);
+    for (int64_t i = t0, n = r.bytes >> 2; i < n; i += step) dst[i] = src[i];
+  }
+}
+
 }  // namespace
 
-hipError_t launch_adj_collide(const double* lam1, double* lam0, const float* g0, const float* F,
+hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
                               const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
                               double* domega_in_part, const Lattice& L, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_collide, dim3((unsigned)((L.np + 255) / 256)), dim3(256), 0, s, lam1, lam0,
@@ -576,6 +595,14 @@ hipError_t launch_loss_seed(const Cells& c, const Mesh& m, const double* targets
 
 hipError_t launch_sum_parts(const double* parts, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, parts, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_many(const CopyRec* dev, int n, int64_t max_bytes, hipStream_t s) {
+  if (n <= 0 || max_bytes <= 0) return hipSuccess;
+  const int64_t per_block = 256 * 16 * 4;   // four 16-byte words per thread before the grid strides
+  const unsigned bx = (unsigned)std::min<int64_t>((max_bytes + per_block - 1) / per_block, 1024);
+  hipLaunchKernelGGL(k_copy_many, dim3(bx, (unsigned)n), dim3(256), 0, s, dev);
   return hipGetLastError();
 }
 

@@ -91,7 +91,7 @@ struct hc_ctx {
   float *ck_pops = nullptr, *ck_off = nullptr, *ck_lo = nullptr, *sg_lo = nullptr;
   float *sg_pops = nullptr, *sg_off = nullptr, *sg_F = nullptr, *sg_Fv = nullptr;
   float4* sg_macro = nullptr;
-  double* lam_f[2] = {nullptr, nullptr};   // population cotangents (FP64)
+  float* lam_f[2] = {nullptr, nullptr};   // population cotangents (FP32 storage, FP64 arithmetic)
   float* lam_X[2] = {nullptr, nullptr};
   float *lam_Fv = nullptr, *lam_u = nullptr, *lam_F = nullptr, *vel_scratch = nullptr;
   double *dom_part = nullptr, *dk = nullptr, *loss = nullptr, *targets = nullptr, *scal = nullptr;
@@ -328,8 +328,8 @@ AdjPlan adj_plan(const hc_ctx* c, int n, int ck) {
   p.sg_F = L.add(ck * 3 * N * 4);
   p.sg_macro = L.add(ck * N * 16);
   p.sg_Fv = L.add(ck * X * 4);
-  p.lf0 = L.add(P * 8);
-  p.lf1 = L.add(P * 8);
+  p.lf0 = L.add(P * 4);
+  p.lf1 = L.add(P * 4);
   p.lx0 = L.add(X * 4);
   p.lx1 = L.add(X * 4);
   p.lfv = L.add(X * 4);
@@ -383,8 +383,8 @@ hc_status adj_reverse_step(hc_ctx* c, int i, int a) {
   Ci.lo = c->sg_lo;   // carried in place through the segment, from its checkpoint
   Ci.force = c->sg_Fv + i * X;
   Ci.vel = c->vel_scratch;
-  double* lf1 = c->lam_f[a];
-  double* lf0 = c->lam_f[a ^ 1];
+  float* lf1 = c->lam_f[a];
+  float* lf0 = c->lam_f[a ^ 1];
   float* lx1 = c->lam_X[a];
   float* lx0 = c->lam_X[a ^ 1];
   HC_TRY(check(c, launch_bin_vertices(Ci, c->M, c->L, c->B, c->stream), "binning"));
@@ -1112,8 +1112,8 @@ hc_status hc_adj_bind_workspace(hc_ctx* c, void* dev, size_t bytes, int32_t n_st
   c->sg_F = reinterpret_cast<float*>(w + p.sg_F);
   c->sg_macro = reinterpret_cast<float4*>(w + p.sg_macro);
   c->sg_Fv = reinterpret_cast<float*>(w + p.sg_Fv);
-  c->lam_f[0] = reinterpret_cast<double*>(w + p.lf0);
-  c->lam_f[1] = reinterpret_cast<double*>(w + p.lf1);
+  c->lam_f[0] = reinterpret_cast<float*>(w + p.lf0);
+  c->lam_f[1] = reinterpret_cast<float*>(w + p.lf1);
   c->lam_X[0] = reinterpret_cast<float*>(w + p.lx0);
   c->lam_X[1] = reinterpret_cast<float*>(w + p.lx1);
   c->lam_Fv = reinterpret_cast<float*>(w + p.lfv);
@@ -1165,7 +1165,7 @@ hc_status hc_adj_backward(hc_ctx* c, double* grad) {
   if (!c->adj_ready || !grad) return fail(c, HC_ERR_STATE, "hc_adj_forward must run first");
   const int64_t N = c->L.np, P = 19 * N, X = (int64_t)c->C.n * c->hm.nv * 3;
   const int nblk = (int)((N + 255) / 256);
-  HC_TRY(check(c, launch_zero_f64(c->lam_f[0], P, c->stream), "zero"));
+  HC_TRY(check(c, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, c->stream), "zero"));   // +0.0f
   HC_TRY(check(c, launch_zero_f64(c->dk, (int64_t)c->C.n * 4, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_part, nblk, c->stream), "zero"));
   HC_TRY(check(c, launch_zero_f64(c->dom_in_part, (int64_t)kVisClasses * nblk, c->stream), "zero"));
@@ -1299,19 +1299,27 @@ hc_status hc_adj_multi_forward(hc_ctx* const* cs, int32_t n, const double* targe
     }
     HC_TRY(mcopy(c0, c->targets, targets + (size_t)b * C * 2, (size_t)C * 16, hipMemcpyHostToDevice, s));
   }
+  // checkpoint k (at step k ck): every box's populations, offsets and low
+  // parts, copied in one launch
+  DevTable<CopyRec> save;
+  const int nck = (ns + ck - 1) / ck;
+  save.n = 3 * n;
+  save.host.resize((size_t)nck * 3 * n);
+  for (int k = 0; k < nck; ++k)
+    for (int b = 0; b < n; ++b) {
+      hc_ctx* c = cs[b];
+      const int q = (k * ck) & 1;
+      save.at(k, 3 * b) = CopyRec{c->ck_pops + k * P, c->pops[c->cur ^ q], (int64_t)P * 4};
+      save.at(k, 3 * b + 1) = CopyRec{c->ck_off + k * X, c->C.off, (int64_t)X * 4};
+      save.at(k, 3 * b + 2) = CopyRec{c->ck_lo + k * X, c->C.lo, (int64_t)X * 4};
+    }
   HC_TRY(mcheck(c0, cell.upload(s), "batched adjoint tables"));
   HC_TRY(mcheck(c0, tile.upload(s), "batched adjoint tables"));
+  HC_TRY(mcheck(c0, save.upload(s), "batched adjoint tables"));
   for (int st = 0; st < ns; ++st) {
     const int q = st & 1;
-    if (st % ck == 0) {
-      const int k = st / ck;
-      for (int b = 0; b < n; ++b) {
-        hc_ctx* c = cs[b];
-        HC_TRY(mcopy(c0, c->ck_pops + k * P, c->pops[c->cur ^ q], (size_t)P * 4, hipMemcpyDeviceToDevice, s));
-        HC_TRY(mcopy(c0, c->ck_off + k * X, c->C.off, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
-        HC_TRY(mcopy(c0, c->ck_lo + k * X, c->C.lo, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
-      }
-    }
+    if (st % ck == 0)
+      HC_TRY(mcheck(c0, launch_copy_many(save.set(st / ck), 3 * n, (int64_t)P * 4, s), "checkpoint"));
     const int adv = st % ck != 0 ? 1 : 0;   // each segment ends with its move applied
     HC_TRY(mcheck(c0, launch_cell_step_multi(cell.first(2 * q + adv), cell.set(2 * q + adv), n, s), "cell step"));
     HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(q), tile.set(q), n, s), "lattice pass"));
@@ -1385,7 +1393,7 @@ hc_status hc_adj_multi_backward(hc_ctx* const* cs, int32_t n, double* grad) {
         memb.at(k, b) = AdjMembraneArgs{Ci, c->M, c->lam_Fv, c->lam_X[a ^ 1], c->dk};
       }
     }
-    HC_TRY(mcheck(c0, launch_zero_f64(c->lam_f[0], P, s), "zero"));
+    HC_TRY(mcheck(c0, launch_fill_i32(reinterpret_cast<int*>(c->lam_f[0]), 0, P, s), "zero"));   // +0.0f
     HC_TRY(mcheck(c0, launch_zero_f64(c->dk, (int64_t)C * 4, s), "zero"));
     HC_TRY(mcheck(c0, launch_zero_f64(c->dom_part, nblk, s), "zero"));
     HC_TRY(mcheck(c0, launch_zero_f64(c->dom_in_part, (int64_t)kVisClasses * nblk, s), "zero"));
@@ -1397,15 +1405,22 @@ hc_status hc_adj_multi_backward(hc_ctx* const* cs, int32_t n, double* grad) {
   HC_TRY(mcheck(c0, coll.upload(s), "batched adjoint tables"));
   HC_TRY(mcheck(c0, vert.upload(s), "batched adjoint tables"));
   HC_TRY(mcheck(c0, memb.upload(s), "batched adjoint tables"));
+  // segment seg starts from checkpoint seg: every box's copies in one launch
+  DevTable<CopyRec> restore;
+  restore.n = 3 * n;
+  restore.host.resize((size_t)c0->adj_nseg * 3 * n);
+  for (int seg = 0; seg < c0->adj_nseg; ++seg)
+    for (int b = 0; b < n; ++b) {
+      hc_ctx* c = cs[b];
+      restore.at(seg, 3 * b) = CopyRec{c->sg_pops, c->ck_pops + seg * P, (int64_t)P * 4};
+      restore.at(seg, 3 * b + 1) = CopyRec{c->sg_off, c->ck_off + seg * X, (int64_t)X * 4};
+      restore.at(seg, 3 * b + 2) = CopyRec{c->sg_lo, c->ck_lo + seg * X, (int64_t)X * 4};
+    }
+  HC_TRY(mcheck(c0, restore.upload(s), "batched adjoint tables"));
   int a = 0;   // lam_f[a], lam_X[a] hold the cotangents of the later state
   for (int seg = c0->adj_nseg - 1; seg >= 0; --seg) {
     const int len = std::min(ck, c0->adj_n - seg * ck);
-    for (int b = 0; b < n; ++b) {
-      hc_ctx* c = cs[b];
-      HC_TRY(mcopy(c0, c->sg_pops, c->ck_pops + seg * P, (size_t)P * 4, hipMemcpyDeviceToDevice, s));
-      HC_TRY(mcopy(c0, c->sg_off, c->ck_off + seg * X, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
-      HC_TRY(mcopy(c0, c->sg_lo, c->ck_lo + seg * X, (size_t)X * 4, hipMemcpyDeviceToDevice, s));
-    }
+    HC_TRY(mcheck(c0, launch_copy_many(restore.set(seg), 3 * n, (int64_t)P * 4, s), "checkpoint restore"));
     for (int i = 0; i < len; ++i) {
       HC_TRY(mcheck(c0, launch_cell_step_multi(cell.first(i), cell.set(i), n, s), "cell step"));
       HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(i), tile.set(i), n, s), "lattice pass"));

@@ -160,7 +160,7 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_spread_vec(const Cells& c, const Mesh& m, const Lattice& L, const Bins& b,
                              const float* vec, float body, float* F, hipStream_t s);
 // adjoint kernels
-hipError_t launch_adj_collide(const double* lam1, double* lam0, const float* g0, const float* F,
+hipError_t launch_adj_collide(const float* lam1, float* lam0, const float* g0, const float* F,
                               const float* lamu, float* lamF, double* domega_part, unsigned char* mask,
                               double* domega_in_part, const Lattice& L, hipStream_t s);
 hipError_t launch_adj_vertex(const Cells& c, const Mesh& m, const Lattice& L, const float* lamX1,
@@ -196,6 +196,15 @@ hipError_t launch_cell_step(const Cells& c, const Mesh& m, const Lattice& L, con
                             const float4* partial, int* flags, bool advect, const float* src,
                             bool refresh, bool ab2, bool recentre, bool keep_vel, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Device-to-device copies of n records in one launch (bytes a multiple of 4;
+// records with 16-byte aligned ends move in 16-byte words).  max_bytes: the
+// largest record, which sets the grid.
+struct CopyRec {
+  void* dst;
+  const void* src;
+  int64_t bytes;
+};
+hipError_t launch_copy_many(const CopyRec* dev, int n, int64_t max_bytes, hipStream_t s);
 
 // Batched forms of the per-step kernels for several boxes of one shape (one
 // launch covers every box: work-group (x, y) does work-group x of box y with
@@ -212,7 +221,7 @@ struct TileStepArgs {
 struct BinArgs { Cells C; Mesh M; Lattice L; Bins B; };
 struct SpreadArgs { Cells C; Mesh M; Lattice L; Bins B; const float* vec; float body; float* F; };
 struct AdjCollideArgs {
-  const double* lam1; double* lam0; const float* h0; const float* F; const float* lamu; float* lamF;
+  const float* lam1; float* lam0; const float* h0; const float* F; const float* lamu; float* lamF;
   double* domega_part; unsigned char* mask; double* domega_in_part; Lattice L;
 };
 struct AdjVertexArgs {
