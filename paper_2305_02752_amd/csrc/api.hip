@@ -1138,12 +1138,20 @@ hc_status hc_adj_forward(hc_ctx* c, const double* targets, double* loss) {
     return fail(c, HC_ERR_UNSUPPORTED, "adjoint differentiates the Euler step with forces every step");
   const int64_t P = 19 * c->L.np, X = (int64_t)c->C.n * c->hm.nv * 3;
   HC_TRY(copy_h2d(c, c->targets, targets, (size_t)c->C.n * 16));
+  // no re-centring while recording; the force and (u, rho) fields (when
+  // field output is on) only at the last step: the loss needs neither, and
+  // the reverse sweep's recomputation writes its own
   c->recentre = false;
   struct Restore {
     hc_ctx* c;
-    ~Restore() { c->recentre = true; }
-  } restore{c};
+    bool fields;
+    ~Restore() {
+      c->recentre = true;
+      c->fields = fields;
+    }
+  } restore{c, c->fields};
   for (int s = 0; s < c->adj_n; ++s) {
+    c->fields = restore.fields && s + 1 == c->adj_n;
     if (s % c->adj_ck == 0) {
       const int k = s / c->adj_ck;
       HC_TRY(copy_d2d(c, c->ck_pops + k * P, c->pops[c->cur], (size_t)P * 4));
@@ -1282,20 +1290,24 @@ hc_status hc_adj_multi_forward(hc_ctx* const* cs, int32_t n, const double* targe
   hipStream_t s = c0->stream;
   const int C = c0->C.n, ns = c0->adj_n, ck = c0->adj_ck;
   const int64_t P = 19 * c0->L.np, X = (int64_t)C * c0->hm.nv * 3;
-  // record sets: [parity q][advect] for the per-cell kernel, [parity q] for the lattice pass
+  // record sets: [parity q][advect] for the per-cell kernel; [fields][parity
+  // q] for the lattice pass, which writes the force and (u, rho) fields (when
+  // the context has field output on) at the last step only: the loss needs
+  // neither, and the reverse sweep's recomputation writes its own
   DevTable<CellStepArgs> cell;
   DevTable<TileStepArgs> tile;
   cell.n = tile.n = n;
   cell.host.resize((size_t)4 * n);
-  tile.host.resize((size_t)2 * n);
+  tile.host.resize((size_t)4 * n);
   for (int b = 0; b < n; ++b) {
     hc_ctx* c = cs[b];
     for (int q = 0; q < 2; ++q) {
       const int in = c->cur ^ q;
       for (int adv = 0; adv < 2; ++adv)
         cell.at(2 * q + adv, b) = CellStepArgs{c->C, c->M, c->L, c->B, c->partial, c->B.flags, adv, nullptr, 1, 0, 0};
-      tile.at(q, b) = TileStepArgs{c->C, c->M, c->L, c->B, c->pops[in], c->pops[in ^ 1], c->F, c->macro,
-                                   c->partial, c->fields ? 1 : 0, nullptr};
+      for (int fl = 0; fl < 2; ++fl)
+        tile.at(2 * fl + q, b) = TileStepArgs{c->C, c->M, c->L, c->B, c->pops[in], c->pops[in ^ 1], c->F, c->macro,
+                                              c->partial, fl && c->fields ? 1 : 0, nullptr};
     }
     HC_TRY(mcopy(c0, c->targets, targets + (size_t)b * C * 2, (size_t)C * 16, hipMemcpyHostToDevice, s));
   }
@@ -1322,7 +1334,8 @@ hc_status hc_adj_multi_forward(hc_ctx* const* cs, int32_t n, const double* targe
       HC_TRY(mcheck(c0, launch_copy_many(save.set(st / ck), 3 * n, (int64_t)P * 4, s), "checkpoint"));
     const int adv = st % ck != 0 ? 1 : 0;   // each segment ends with its move applied
     HC_TRY(mcheck(c0, launch_cell_step_multi(cell.first(2 * q + adv), cell.set(2 * q + adv), n, s), "cell step"));
-    HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(q), tile.set(q), n, s), "lattice pass"));
+    const int tset = (st + 1 == ns ? 2 : 0) + q;
+    HC_TRY(mcheck(c0, launch_tile_step_multi(tile.first(tset), tile.set(tset), n, s), "lattice pass"));
     if ((st + 1) % ck == 0 || st + 1 == ns)
       for (int b = 0; b < n; ++b) {
         hc_ctx* c = cs[b];

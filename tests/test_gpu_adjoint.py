@@ -235,6 +235,50 @@ def test_adjoint_full_size_properties():
     assert np.array_equal(g1, g2)
 
 
+def test_adjoint_forward_leaves_the_last_step_fields():
+    """The adjoint forward writes the force and (u, rho) fields at its last
+    step only; with field output on, reading them afterwards gives what a
+    plain run of the same steps gives: bit for bit from hc_adj_forward (the
+    same kernels), within a few FP32 roundings from the batched form."""
+    from types import SimpleNamespace
+
+    from paper_2305_02752_amd import Simulation
+    n = 40
+    boxes = [_box(seed=s_) for s_ in (3, 4)]
+
+    def make(b):
+        lat, rest, tri, cells, _ = b
+        sim = make_sim(SimpleNamespace(lattice=lat, rest_pos=rest, tri=tri, cells=cells), cells)
+        sim.init_equilibrium()
+        return sim
+
+    plain = []
+    for b in boxes:
+        sim = make(b)
+        sim.step(n)
+        sim.sync()
+        plain.append((sim.read_macro(), sim.read_force_field()))
+        sim.close()
+    sim = make(boxes[0])
+    sim.adj_bind(n, 15)
+    sim.adj_forward(boxes[0][4])
+    (rho, u), F = sim.read_macro(), sim.read_force_field()
+    sim.close()
+    assert np.array_equal(rho, plain[0][0][0]) and np.array_equal(u, plain[0][0][1])
+    assert np.array_equal(F, plain[0][1])
+    sims = [make(b) for b in boxes]
+    for s_ in sims:
+        s_.adj_bind(n, 15)
+    Simulation.adj_multi_forward(sims, np.stack([b[4] for b in boxes])[:, None, :])
+    for k, s_ in enumerate(sims):
+        (rho, u), F = s_.read_macro(), s_.read_force_field()
+        (rho0, u0), F0 = plain[k]
+        assert np.abs(rho - rho0).max() <= 1e-6 * np.abs(rho0).max()
+        assert np.abs(u - u0).max() <= 1e-6 * np.abs(u0).max()
+        assert np.abs(F - F0).max() <= 1e-6 * np.abs(F0).max()
+        s_.close()
+
+
 def test_multi_box_adjoint_equals_single_box():
     """hc_adj_multi_forward / _backward over three boxes of the adjoint
     workload's shape (48^3, sheared; 240 steps, checkpoint every 50, so the
