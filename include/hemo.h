@@ -366,7 +366,9 @@ hc_status hc_set_params(hc_ctx* ctx, const float* k, float tau);
  * D_A = max x - min x and D_T = max y - min y over its vertices.
  * hc_adj_forward runs n steps from the current state (checkpointing every
  * ckpt_every steps) and returns the loss; the context then holds the final
- * state, as after hc_step(n).  hc_adj_backward recomputes one segment at a
+ * state, as after hc_step(n) (with field output on, the force and (u, rho)
+ * fields of the last step: earlier steps do not write them).
+ * hc_adj_backward recomputes one segment at a
  * time from its checkpoint, keeping every state, and sweeps it backwards.
  * grad [C][5] = dL_c/d(k_link, k_bend, k_area, k_volume) of cell c, and in
  * column 4 dL/dtau, where L is the sum of all cells' losses (tau is shared
