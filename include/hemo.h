@@ -21,7 +21,10 @@
  *  - Device memory is owned by the caller: hc_query_workspace reports the
  *    bytes the context needs and hc_bind_workspace hands over one device
  *    buffer of at least that size (256-byte aligned).  The library never
- *    frees it and allocates no device memory of its own.
+ *    frees it and allocates no device memory of its own, except the
+ *    argument tables of hc_adj_multi_forward / hc_adj_multi_backward (one
+ *    record per box and step kind, tens of MB at most), which each call
+ *    allocates and frees before it returns.
  *  - Host read/write calls take caller-owned host arrays with an explicit
  *    element count; a mismatch returns HC_ERR_ARG.  They synchronise the
  *    stream before returning.
