@@ -43,7 +43,7 @@ __device__ inline f3 ld3(const float* p, int i) { return {p[3 * i], p[3 * i + 1]
 __device__ inline float nonlin(float s, float lim) {
   const float m = kClamp * lim;
   s = fminf(fmaxf(s, -m), m);
-  return s + s / (lim * lim - s * s);
+  return s + quot(s, lim * lim - s * s);
 }
 __device__ inline Dual nonlin(Dual s, float lim) {
   const float m = kClamp * lim;
@@ -56,7 +56,7 @@ template <class T>
 __device__ inline V3<T> link_force(V3<T> xi, V3<T> xj, float L0, float kl) {
   const V3<T> d = xj - xi;
   const T L = sqrt_(dot(d, d));
-  return (kl * nonlin((L - L0) / L0, kTauLink) / L) * d;
+  return quot(kl * nonlin(quot(L - L0, L0), kTauLink), L) * d;
 }
 
 // Area and volume forces on the three vertices of triangle (a, b, c):
@@ -86,9 +86,9 @@ __device__ inline void hinge_forces(V3<T> xi, V3<T> xj, V3<T> xk, V3<T> xl, floa
   const T theta = atan2_(dot(cross(r1 * n1, r2 * n2), re * e), r1 * r2 * dot(n1, n2));
   const T m = -kb * nonlin(theta - theta0, kTauBend);
   const T el = el2 * re;
-  const V3<T> gk = (-el / n1s) * n1;
-  const V3<T> gl = (-el / n2s) * n2;
-  const T ak = dot(xk - xi, e) / el2, al = dot(xl - xi, e) / el2;
+  const V3<T> gk = quot(-el, n1s) * n1;
+  const V3<T> gl = quot(-el, n2s) * n2;
+  const T ak = quot(dot(xk - xi, e), el2), al = quot(dot(xl - xi, e), el2);
   fk = m * gk;
   fl = m * gl;
   fi = m * ((ak - 1.f) * gk + (al - 1.f) * gl);
