@@ -103,7 +103,7 @@ __device__ __forceinline__ void cell_step_body(Cells C, Mesh M, Lattice L, Bins 
   if (advect) {
     for (int vl = tid; vl < M.nv; vl += kCellThreads) {
       float nx[3];
-      ibmd::advect_vertex<K>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src, ab2 != 0,
+      ibmd::advect_vertex<K, true>(C, M, L, B, partial, flags, (int64_t)c * M.nv + vl, nx, src, ab2 != 0,
                              keep_vel != 0);
       sp[3 * vl] = nx[0];
       sp[3 * vl + 1] = nx[1];

@@ -20,18 +20,43 @@ namespace ibmd {
 // Adams-Bashforth move, and for the read-out after the closing move).  The
 // other two axes' weights sum to one, so a node layer beyond the wall
 // contributes its axis weight times the wall velocity.
-template <int K>
+// PRE: the first kPre slots are requested together with the slot count (a
+// latency-bound caller: the per-cell kernel, a few vertices per thread);
+// otherwise slot by slot up to the count (the vertex-parallel move, bound by
+// bandwidth, which the unused slots would waste).
+template <int K, bool PRE = false>
 __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattice& L, const Bins& B,
                                      const float4* __restrict__ partial, int* __restrict__ flags,
                                      int64_t v, float (&nxyz)[3], const float* src = nullptr,
                                      bool ab2 = false, bool keep_vel = true) {
   float Ux = 0.f, Uy = 0.f, Uz = 0.f;
+  // With PRE the first kPre slots (every slot of a lattice without sheared
+  // images) are requested together with the slot count, in bounds whatever
+  // the count, so that the vertex waits for one memory round trip rather
+  // than one per slot; every slot is summed in slot order either way.
+  constexpr int kPre = 8;
+  const int64_t stride = (int64_t)C.n * M.nv;
+  const int npre = PRE ? min(kPre, L.max_touch) : 0;
+  float3 q[kPre];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j)
+    if (j < npre) {
+      const float4 p = partial[j * stride + v];
+      q[j] = make_float3(p.x, p.y, p.z);
+    }
   const int nt = B.ntouch[v];
-  for (int j = 0; j < nt; ++j) {
-    const float4 q = partial[(int64_t)j * C.n * M.nv + v];
-    Ux += q.x;
-    Uy += q.y;
-    Uz += q.z;
+#pragma unroll
+  for (int j = 0; j < kPre; ++j)
+    if (j < nt && j < npre) {
+      Ux += q[j].x;
+      Uy += q[j].y;
+      Uz += q[j].z;
+    }
+  for (int j = npre; j < nt; ++j) {
+    const float4 p = partial[j * stride + v];
+    Ux += p.x;
+    Uy += p.y;
+    Uz += p.z;
   }
   float* o = C.off + v * 3;
   const float* oi = (src ? src : C.off) + v * 3;
