@@ -38,12 +38,13 @@ __device__ inline void advect_vertex(const Cells& C, const Mesh& M, const Lattic
   const int64_t stride = (int64_t)C.n * M.nv;
   const int npre = PRE ? min(kPre, L.max_touch) : 0;
   float3 q[kPre];
+  if (PRE) {
 #pragma unroll
-  for (int j = 0; j < kPre; ++j)
-    if (j < npre) {
-      const float4 p = partial[j * stride + v];
+    for (int j = 0; j < kPre; ++j) {   // slot min(j, npre - 1): every read in bounds, none behind a branch
+      const float4 p = partial[min(j, npre - 1) * stride + v];
       q[j] = make_float3(p.x, p.y, p.z);
     }
+  }
   const int nt = B.ntouch[v];
 #pragma unroll
   for (int j = 0; j < kPre; ++j)
