@@ -508,7 +508,9 @@ __global__ void k_fill_f64(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// Record blockIdx.y of a batch of copies, strided over the x blocks.
+// Record blockIdx.y of a batch of copies, strided over the x blocks: in
+// 16-byte words when both addresses and the size are multiples of 16, else
+// in 4-byte words.
 __global__ __launch_bounds__(256) void k_copy_many(const CopyRec* __restrict__ recs) {
   const CopyRec r = recs[blockIdx.y];
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
